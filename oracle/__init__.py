@@ -1,0 +1,225 @@
+"""CPU oracle for the GrowLocal-scheduled sparse lower-triangular solve.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+CPU-baseline leg of ``bench.py``; never by the product package.  It shares no
+code with the HIP library.  The arithmetic lives in ``oracle.c`` (plain C,
+compiled with ``-ffp-contract=off`` so every binary64 operation is rounded on
+its own); this module only marshals numpy arrays.
+
+Each function cites the passage of the paper (arxiv 2503.05408) it follows:
+
+* :func:`solve`      -- forward substitution, Eq. (2.1).
+* :func:`levels`     -- wavefronts; average wavefront size = floor(n / #levels)
+  (Sec. 6.2; the appendix tables round down).
+* :func:`validate`   -- Definition 2.1.
+* :func:`growlocal`  -- Algorithm 3.1 (Sec. 3, Eq. (3.1); acceptance factor
+  0.97 from the proof of Theorem 3.1 in Appendix B).
+* :func:`reorder`    -- Sec. 5.
+* :func:`bsp_solve`  -- the schedule executed superstep by superstep with
+  strict visibility (Sec. 2.3).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+# paper parameters of GrowLocal: L = 500 (Sec. 3, footnote), alpha starts at 20
+# and grows by 1.5 (Sec. 3), acceptance factor 0.97 (Appendix B)
+PAPER_L = 500.0
+PAPER_ALPHA0 = 20.0
+PAPER_GROWTH = 1.5
+PAPER_THETA = 0.97
+
+VALID = 0
+INVALID_RANGE = 1
+INVALID_ORDER = 2
+INVALID_CROSS = 3
+INVALID_EMPTY = 4
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           _SRC, "-o", _LIB + ".tmp", "-lm"]
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB)
+            P = ctypes.c_void_p
+            i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+            lib.oracle_check_csr.argtypes = [i64, P, P, P]
+            lib.oracle_solve.argtypes = [i64, P, P, P, P, P]
+            lib.oracle_levels.argtypes = [i64, P, P, P]
+            lib.oracle_levels.restype = i64
+            lib.oracle_validate.argtypes = [i64, P, P, i32, P, P, i32]
+            lib.oracle_growlocal.argtypes = [i64, P, P, i32, dbl, dbl, dbl, dbl, P, P, P,
+                                             i64, P, P, P, P, P]
+            lib.oracle_reorder.argtypes = [i64, P, P, P, P, P, P, P, P, P]
+            lib.oracle_bsp_solve.argtypes = [i64, P, P, P, P, P, P, P, P]
+            _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr(m):
+    rp = np.ascontiguousarray(m.row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(m.col, dtype=np.int32)
+    v = np.ascontiguousarray(m.val, dtype=np.float64)
+    return rp, c, v
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def check_csr(m) -> int:
+    rp, c, v = _csr(m)
+    return _load().oracle_check_csr(m.n, _p(rp), _p(c), _p(v))
+
+
+def solve(m, b) -> np.ndarray:
+    """Serial forward substitution, Eq. (2.1): running subtraction in stored
+    column order, then one division by the diagonal."""
+    rp, c, v = _csr(m)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.empty(m.n, dtype=np.float64)
+    rc = _load().oracle_solve(m.n, _p(rp), _p(c), _p(v), _p(b), _p(x))
+    if rc:
+        raise OracleError(f"oracle_solve: {rc}")
+    return x
+
+
+def levels(m):
+    """(level per row, number of wavefronts); sources have level 1."""
+    rp, c, _ = _csr(m)
+    lv = np.empty(m.n, dtype=np.int32)
+    nl = _load().oracle_levels(m.n, _p(rp), _p(c), _p(lv))
+    if nl < 0:
+        raise OracleError(f"oracle_levels: {nl}")
+    return lv, int(nl)
+
+
+def avg_wavefront(m) -> int:
+    _, nl = levels(m)
+    return m.n // nl if nl else 0
+
+
+def validate(m, k, pi, sigma, S=None) -> int:
+    rp, c, _ = _csr(m)
+    pi = np.ascontiguousarray(pi, dtype=np.int32)
+    sigma = np.ascontiguousarray(sigma, dtype=np.int32)
+    if S is None:
+        S = int(sigma.max()) + 1 if m.n else 0
+    return _load().oracle_validate(m.n, _p(rp), _p(c), int(k), _p(pi), _p(sigma), int(S))
+
+
+def growlocal(m, k, L=PAPER_L, alpha0=PAPER_ALPHA0, growth=PAPER_GROWTH, theta=PAPER_THETA,
+              trace: int = 0):
+    """GrowLocal (Algorithm 3.1).  Returns (pi, sigma, S) and, when ``trace`` > 0,
+    also a list of (superstep, alpha, beta, worthy) for the first ``trace``
+    iterations."""
+    rp, c, _ = _csr(m)
+    pi = np.empty(m.n, dtype=np.int32)
+    sigma = np.empty(m.n, dtype=np.int32)
+    S = ctypes.c_int32(0)
+    nt = ctypes.c_int64(0)
+    if trace:
+        ts = np.zeros(trace, np.int32)
+        ta = np.zeros(trace, np.float64)
+        tb = np.zeros(trace, np.float64)
+        tw = np.zeros(trace, np.int8)
+    else:
+        ts = ta = tb = tw = None
+    rc = _load().oracle_growlocal(m.n, _p(rp), _p(c), int(k), float(L), float(alpha0), float(growth),
+                                  float(theta), _p(pi), _p(sigma), ctypes.byref(S), int(trace),
+                                  _p(ts), _p(ta), _p(tb), _p(tw), ctypes.byref(nt))
+    if rc:
+        raise OracleError(f"oracle_growlocal: {rc}")
+    if trace:
+        cnt = min(trace, nt.value)
+        tr = [(int(ts[i]), float(ta[i]), float(tb[i]), bool(tw[i])) for i in range(cnt)]
+        return pi, sigma, S.value, tr
+    return pi, sigma, S.value
+
+
+def wavefront_schedule(m):
+    """The level-set schedule: superstep = level - 1, core = rank of the row
+    inside its level (one row per core)."""
+    lv, nl = levels(m)
+    sigma = (lv - 1).astype(np.int32)
+    order = np.argsort(sigma, kind="stable")           # by level, then ID
+    start = np.zeros(nl + 1, dtype=np.int64)
+    np.cumsum(np.bincount(sigma, minlength=nl), out=start[1:])
+    pi = np.empty(m.n, dtype=np.int32)
+    pi[order] = (np.arange(m.n) - start[sigma[order]]).astype(np.int32)
+    return pi, sigma, nl
+
+
+def reorder(m, pi, sigma):
+    """Sec. 5: returns (perm, permuted CSR as (row_ptr, col, val)); row t of the
+    permuted matrix is row perm[t] of A with columns renamed through the
+    inverse permutation and the stored entry order kept."""
+    rp, c, v = _csr(m)
+    pi = np.ascontiguousarray(pi, dtype=np.int32)
+    sigma = np.ascontiguousarray(sigma, dtype=np.int32)
+    perm = np.empty(m.n, dtype=np.int32)
+    rp2 = np.empty(m.n + 1, dtype=np.int64)
+    c2 = np.empty(m.nnz, dtype=np.int32)
+    v2 = np.empty(m.nnz, dtype=np.float64)
+    rc = _load().oracle_reorder(m.n, _p(rp), _p(c), _p(v), _p(pi), _p(sigma), _p(perm),
+                                _p(rp2), _p(c2), _p(v2))
+    if rc:
+        raise OracleError(f"oracle_reorder: {rc}")
+    return perm, (rp2, c2, v2)
+
+
+def bsp_solve(m, b, pi, sigma):
+    """Executes the schedule with strict visibility.  Returns x, or raises with
+    the first row that read a value it could not yet see."""
+    rp, c, v = _csr(m)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    pi = np.ascontiguousarray(pi, dtype=np.int32)
+    sigma = np.ascontiguousarray(sigma, dtype=np.int32)
+    x = np.empty(m.n, dtype=np.float64)
+    bad = ctypes.c_int64(-1)
+    rc = _load().oracle_bsp_solve(m.n, _p(rp), _p(c), _p(v), _p(b), _p(pi), _p(sigma), _p(x),
+                                  ctypes.byref(bad))
+    if rc:
+        raise OracleError(f"oracle_bsp_solve: {rc} at row {bad.value}")
+    return x
+
+
+def same_bits(a, b) -> bool:
+    """Comparison rule for binary64 results: bitwise equality (sign of zero
+    included); two NaNs count as equal whatever their payload or sign."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    if a.shape != b.shape:
+        return False
+    na, nb = np.isnan(a), np.isnan(b)
+    if not np.array_equal(na, nb):
+        return False
+    ia, ib = a.view(np.uint64), b.view(np.uint64)
+    return bool(np.array_equal(ia[~na], ib[~nb]))
