@@ -1,0 +1,176 @@
+/*
+ * gltrsv -- GrowLocal-scheduled sparse lower-triangular solve on AMD MI355X
+ * (gfx950).  C ABI of the shared library libgltrsv.so.
+ *
+ * The library solves A x = b for a sparse, non-singular, lower-triangular A by
+ * forward substitution (Eq. (2.1) of Boehnlein, Papp, Steiner, Matzoros and
+ * Yzelman, "Efficient parallel scheduling for sparse triangular solvers",
+ * arxiv 2503.05408), executed on the GPU under a bulk-synchronous schedule
+ * (Definition 2.1) built by the GrowLocal scheduler (Algorithm 3.1) and laid
+ * out in the schedule's order (Sec. 5).
+ *
+ * Conventions shared by every call:
+ *  - Return value: 0 (GLTRSV_OK) on success, a negative GLTRSV_E* code on
+ *    failure.  Nothing is thrown across the ABI.  gltrsv_last_error() returns
+ *    a text for the last failure of the calling thread.
+ *  - Matrices are CSR with int64 row pointers, int32 column indices and
+ *    binary64 values, in host memory owned by the caller; the library copies
+ *    what it needs.  Within each row the off-diagonal columns ascend strictly
+ *    and the diagonal is the last stored entry; it must be non-zero (the
+ *    matrix is non-singular, Sec. 2.2).  Every stored entry is an edge of the
+ *    DAG (Sec. 2.2), explicit zeros included.
+ *  - Vectors passed to solve calls are device pointers (hipMalloc'd or torch
+ *    CUDA tensors), caller-owned, n binary64 values in the original row
+ *    numbering.
+ *  - Streams are hipStream_t values passed as void* (NULL = default stream).
+ *    Solve calls are asynchronous with respect to the host.
+ *  - Results: every x_i is computed as acc <- b_i; acc <- acc - (A_ij * x_j)
+ *    for the stored off-diagonals of row i in stored order, each operation
+ *    rounded on its own (no fused multiply-add), then x_i <- acc / A_ii with
+ *    one correctly rounded division.  The result is therefore bit-identical
+ *    for every schedule, every core count, batched or not.
+ */
+#ifndef GLTRSV_H
+#define GLTRSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define GLTRSV_OK          0
+#define GLTRSV_EINVAL     -1   /* null pointer, negative size, bad option    */
+#define GLTRSV_ENOTLOWER  -2   /* an entry above the diagonal                */
+#define GLTRSV_ESINGULAR  -3   /* diagonal missing, not last, or zero        */
+#define GLTRSV_EUNSORTED  -4   /* off-diagonal columns not strictly rising   */
+#define GLTRSV_ERANGE     -5   /* index out of range, or n too large         */
+#define GLTRSV_ENOMEM     -6   /* host or device allocation failed           */
+#define GLTRSV_EAGAIN     -7   /* server: request does not fit the budget    */
+#define GLTRSV_EHIP       -8   /* a HIP runtime call failed                  */
+#define GLTRSV_ETIMEDOUT  -9   /* a device-side wait exceeded its spin limit */
+#define GLTRSV_ENOTSUP   -10   /* not supported on this device/build         */
+
+/* Text for the last error on the calling thread (never NULL). */
+const char *gltrsv_last_error(void);
+
+/* Library version, e.g. "0.1.0". */
+const char *gltrsv_version(void);
+
+/* ---------------------------------------------------------------- inputs */
+typedef struct gltrsv_csr {
+    int64_t n;               /* rows = columns                                */
+    int64_t nnz;             /* stored entries, diagonal included             */
+    const int64_t *row_ptr;  /* [n+1], row_ptr[0] = 0, row_ptr[n] = nnz       */
+    const int32_t *col;      /* [nnz]                                         */
+    const double *val;       /* [nnz]; may be NULL for pattern-only calls     */
+} gltrsv_csr;
+
+/* Checks the conventions above.  Returns GLTRSV_OK or the first violation
+ * (ENOTLOWER, ESINGULAR, EUNSORTED, ERANGE, EINVAL).  n is limited to
+ * 2^30 - 1 rows (the device stream packs a row index into 30 bits). */
+int gltrsv_check_csr(const gltrsv_csr *A);
+
+/* ------------------------------------------------------------- schedules */
+#define GLTRSV_SCHED_GROWLOCAL 0   /* Algorithm 3.1                           */
+#define GLTRSV_SCHED_WAVEFRONT 1   /* level sets: one superstep per wavefront */
+
+typedef struct gltrsv_plan_opts {
+    int32_t k;              /* cores of the BSP schedule (Def. 2.1), >= 1     */
+    double L;               /* barrier cost in weight units (Sec. 3, Eq. 3.1) */
+    double alpha0;          /* first superstep length parameter, >= 1         */
+    double growth;          /* alpha growth factor, > 1                       */
+    double accept;          /* worthy iff beta >= accept * best beta          */
+    int32_t schedule_kind;  /* GLTRSV_SCHED_*                                 */
+    int32_t reorder;        /* reserved; the device layout is always in the
+                               schedule order of Sec. 5 and b/x stay in the
+                               original numbering (see gltrsv_solve)          */
+    int32_t block_size;     /* device threads per workgroup (64..1024, a
+                               multiple of 64); 0 = library default           */
+    int32_t grid_blocks;    /* workgroups of the persistent kernel;
+                               0 = all that can be co-resident                */
+} gltrsv_plan_opts;
+
+/* Fills the paper's parameters: k = 22 (the core count of the main
+ * experiments, Sec. 7.1), L = 500 (Sec. 3, footnote), alpha0 = 20 and
+ * growth 1.5 (Sec. 3), accept = 0.97 (proof of Theorem 3.1, Appendix B),
+ * GrowLocal, defaults for the device fields. */
+void gltrsv_default_opts(gltrsv_plan_opts *opts);
+
+/* Wavefronts (Sec. 1, Fig. 1.1; Sec. 6.2): level[i] = 1 for a row with no
+ * off-diagonal, else 1 + the largest level among its columns.  level may be
+ * NULL.  *nlevels = number of wavefronts (= vertices on a longest path).
+ * Host only. */
+int gltrsv_levels(const gltrsv_csr *A, int32_t *level, int32_t *nlevels);
+
+/* Builds the BSP schedule of A (Def. 2.1) with opts->schedule_kind:
+ *  GROWLOCAL -- Algorithm 3.1 with Rule I: cores filled in order; core 0
+ *     takes up to floor(alpha) vertices, every later core up to the weight of
+ *     core 0; the smallest-ID vertex exclusive to the core first, else the
+ *     smallest-ID vertex free at the barrier; beta of Eq. (3.1); alpha grows
+ *     by opts->growth while the iteration stays worthy; the last worthy
+ *     iteration becomes the superstep.  Vertex weight = stored entries of the
+ *     row (Sec. 2.2).
+ *  WAVEFRONT -- superstep = level - 1, core = rank of the row in its level.
+ * Outputs (host arrays of n int32, caller-owned): core[i] in [0, k) (for
+ * WAVEFRONT in [0, widest level)), superstep[i] in [0, S), *S = supersteps.
+ * Host only; does not touch the GPU. */
+int gltrsv_schedule(const gltrsv_csr *A, const gltrsv_plan_opts *opts,
+                    int32_t *core, int32_t *superstep, int32_t *S);
+
+/* Permutation of Sec. 5: perm[t] = the row at position t when rows are
+ * listed by superstep, then core, then original index.  Host only. */
+int gltrsv_reorder(int64_t n, const int32_t *core, const int32_t *superstep, int32_t *perm);
+
+/* ------------------------------------------------------------------ plans */
+typedef struct gltrsv_plan gltrsv_plan;
+
+typedef struct gltrsv_plan_info {
+    int64_t n, nnz;
+    int32_t supersteps;     /* S of the schedule                             */
+    int32_t wavefronts;     /* number of levels of the DAG                    */
+    int64_t tasks;          /* non-empty (superstep, core) pairs              */
+    int64_t chunks;         /* 64-task device work units                      */
+    int64_t stream_slots;   /* packed entries incl. padding (>= nnz)          */
+    int64_t device_bytes;   /* device memory held by the plan                 */
+    int64_t analysis_ns;    /* host time of plan creation                     */
+    uint64_t pattern_key;   /* hash of (n, row_ptr, col)                      */
+    int32_t grid_blocks;    /* persistent-kernel workgroups                   */
+    int32_t block_size;     /* threads per workgroup                          */
+    int64_t max_task_rows;  /* longest row sequence on one core in a superstep */
+} gltrsv_plan_info;
+
+/* Analyses A (checks, schedule, Sec. 5 order) and uploads the packed matrix
+ * to the current HIP device.  The values of A are captured; a plan is
+ * immutable afterwards, so solves on different streams may share it.
+ * *out is owned by the library until gltrsv_plan_destroy. */
+int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv_plan **out);
+
+int gltrsv_plan_info_get(const gltrsv_plan *plan, gltrsv_plan_info *out);
+
+/* Copies the plan's schedule to host arrays of n int32 (any may be NULL). */
+int gltrsv_plan_schedule(const gltrsv_plan *plan, int32_t *core, int32_t *superstep, int32_t *perm);
+
+int gltrsv_plan_destroy(gltrsv_plan *plan);
+
+/* ----------------------------------------------------------------- solves */
+/* Persistent solve: one cooperative launch runs every superstep; the barrier
+ * between supersteps (Def. 2.1) is a device-scope counter.  b and x are
+ * device arrays in the original numbering; b may alias x (in-place solve).
+ * Reading b and writing x fuse the permutation of Sec. 5. */
+int gltrsv_solve(gltrsv_plan *plan, const double *b, double *x, void *stream);
+
+/* Baseline: one kernel launch per superstep; the kernel boundary is the
+ * barrier.  Same arguments and results as gltrsv_solve. */
+int gltrsv_solve_plain(gltrsv_plan *plan, const double *b, double *x, void *stream);
+
+/* Device-side error word of the last persistent solve on this plan (0 = none,
+ * 1 = spin limit hit).  Synchronises the plan's last stream. */
+int gltrsv_plan_device_status(gltrsv_plan *plan, int32_t *status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLTRSV_H */

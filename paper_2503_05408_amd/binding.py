@@ -1,0 +1,256 @@
+"""ctypes binding of ``libgltrsv.so`` (declared in ``include/gltrsv.h``).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels, and the scheduling/packing in its host C++.  PyTorch provides device
+memory and streams.  If the library cannot be loaded the calls raise; there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+from . import build as _build
+
+_lock = threading.Lock()
+_lib = None
+
+P = ctypes.c_void_p
+i32, i64, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+
+GLTRSV_OK = 0
+ERRORS = {
+    -1: "EINVAL", -2: "ENOTLOWER", -3: "ESINGULAR", -4: "EUNSORTED", -5: "ERANGE",
+    -6: "ENOMEM", -7: "EAGAIN", -8: "EHIP", -9: "ETIMEDOUT", -10: "ENOTSUP",
+}
+SCHED_GROWLOCAL = 0
+SCHED_WAVEFRONT = 1
+
+
+class GltrsvError(RuntimeError):
+    def __init__(self, code: int, where: str, text: str):
+        super().__init__(f"{where}: {ERRORS.get(code, code)} ({text})")
+        self.code = code
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", i64), ("nnz", i64), ("row_ptr", P), ("col", P), ("val", P)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("k", i32), ("L", dbl), ("alpha0", dbl), ("growth", dbl), ("accept", dbl),
+                ("schedule_kind", i32), ("reorder", i32), ("block_size", i32), ("grid_blocks", i32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n", i64), ("nnz", i64), ("supersteps", i32), ("wavefronts", i32), ("tasks", i64),
+                ("chunks", i64), ("stream_slots", i64), ("device_bytes", i64), ("analysis_ns", i64),
+                ("pattern_key", u64), ("grid_blocks", i32), ("block_size", i32), ("max_task_rows", i64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# function name -> (argtypes, restype)
+SIGNATURES = {
+    "gltrsv_last_error": ([], ctypes.c_char_p),
+    "gltrsv_version": ([], ctypes.c_char_p),
+    "gltrsv_check_csr": ([P], i32),
+    "gltrsv_default_opts": ([P], None),
+    "gltrsv_levels": ([P, P, P], i32),
+    "gltrsv_schedule": ([P, P, P, P, P], i32),
+    "gltrsv_reorder": ([i64, P, P, P], i32),
+    "gltrsv_plan_create": ([P, P, P], i32),
+    "gltrsv_plan_info_get": ([P, P], i32),
+    "gltrsv_plan_schedule": ([P, P, P, P], i32),
+    "gltrsv_plan_destroy": ([P], i32),
+    "gltrsv_solve": ([P, P, P, P], i32),
+    "gltrsv_solve_plain": ([P, P, P, P], i32),
+    "gltrsv_plan_device_status": ([P, P], i32),
+}
+
+
+def lib_path() -> str:
+    return _build.LIB
+
+
+def load(build_if_missing: bool = True):
+    """Loads the HIP library (building it only if no build exists)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_build.LIB):
+                if not build_if_missing:
+                    raise RuntimeError(f"{_build.LIB} is not built")
+                _build.build()
+            lib = ctypes.CDLL(_build.LIB)
+            for name, (argt, rest) in SIGNATURES.items():
+                f = getattr(lib, name)
+                f.argtypes = argt
+                f.restype = rest
+            _lib = lib
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != GLTRSV_OK:
+        raise GltrsvError(rc, where, load().gltrsv_last_error().decode())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(P)
+
+
+class _HostCsr:
+    """Keeps numpy arrays alive while a Csr struct points at them."""
+
+    def __init__(self, m):
+        self.rp = np.ascontiguousarray(m.row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(m.col, dtype=np.int32)
+        self.val = None if m.val is None else np.ascontiguousarray(m.val, dtype=np.float64)
+        self.s = Csr(int(m.n), int(self.rp[-1]) if self.rp.size else 0, _np_ptr(self.rp), _np_ptr(self.col),
+                     None if self.val is None else _np_ptr(self.val))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def default_opts(**overrides) -> PlanOpts:
+    o = PlanOpts()
+    load().gltrsv_default_opts(ctypes.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def gpu_opts(**overrides) -> PlanOpts:
+    """Schedule parameters sized for the GPU: many lane-cores, a barrier cost
+    L expressed in the weight units of one lane, and alpha starting at 1."""
+    base = dict(k=1 << 16, L=50.0, alpha0=1.0)
+    base.update(overrides)
+    return default_opts(**base)
+
+
+def check_csr(m) -> int:
+    h = _HostCsr(m)
+    return int(load().gltrsv_check_csr(h.ref))
+
+
+def levels(m):
+    h = _HostCsr(m)
+    lv = np.empty(m.n, dtype=np.int32)
+    nl = ctypes.c_int32(0)
+    _check(load().gltrsv_levels(h.ref, _np_ptr(lv), ctypes.byref(nl)), "gltrsv_levels")
+    return lv, nl.value
+
+
+def schedule(m, opts: PlanOpts | None = None):
+    h = _HostCsr(m)
+    opts = opts or default_opts()
+    core = np.empty(m.n, dtype=np.int32)
+    sup = np.empty(m.n, dtype=np.int32)
+    S = ctypes.c_int32(0)
+    _check(load().gltrsv_schedule(h.ref, ctypes.byref(opts), _np_ptr(core), _np_ptr(sup), ctypes.byref(S)),
+           "gltrsv_schedule")
+    return core, sup, S.value
+
+
+def reorder(core, superstep):
+    core = np.ascontiguousarray(core, dtype=np.int32)
+    superstep = np.ascontiguousarray(superstep, dtype=np.int32)
+    perm = np.empty(core.size, dtype=np.int32)
+    _check(load().gltrsv_reorder(core.size, _np_ptr(core), _np_ptr(superstep), _np_ptr(perm)), "gltrsv_reorder")
+    return perm
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, n):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("expected a CUDA float64 tensor")
+    if t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous tensor of {n} values")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A matrix analysed and resident on the current device."""
+
+    def __init__(self, m, opts: PlanOpts | None = None):
+        self.n = int(m.n)
+        self.opts = opts or default_opts()
+        h = _HostCsr(m)
+        ptr = ctypes.c_void_p()
+        _check(load().gltrsv_plan_create(h.ref, ctypes.byref(self.opts), ctypes.byref(ptr)), "gltrsv_plan_create")
+        self._p = ptr
+
+    def close(self):
+        if self._p:
+            load().gltrsv_plan_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._p
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(load().gltrsv_plan_info_get(self._p, ctypes.byref(inf)), "gltrsv_plan_info_get")
+        return inf.as_dict()
+
+    def schedule(self):
+        core = np.empty(self.n, dtype=np.int32)
+        sup = np.empty(self.n, dtype=np.int32)
+        perm = np.empty(self.n, dtype=np.int32)
+        _check(load().gltrsv_plan_schedule(self._p, _np_ptr(core), _np_ptr(sup), _np_ptr(perm)),
+               "gltrsv_plan_schedule")
+        return core, sup, perm
+
+    def solve(self, b, x=None, stream=None):
+        """Persistent solve; returns x (allocated if not given)."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        _check(load().gltrsv_solve(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
+               "gltrsv_solve")
+        return x
+
+    def solve_plain(self, b, x=None, stream=None):
+        """One kernel launch per superstep."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        _check(load().gltrsv_solve_plain(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
+               "gltrsv_solve_plain")
+        return x
+
+    def device_status(self) -> int:
+        st = ctypes.c_int32(0)
+        _check(load().gltrsv_plan_device_status(self._p, ctypes.byref(st)), "gltrsv_plan_device_status")
+        return st.value

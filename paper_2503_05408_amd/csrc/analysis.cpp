@@ -1,0 +1,367 @@
+// Host-side analysis: CSR checks, wavefronts, GrowLocal (Algorithm 3.1),
+// the schedule order of Sec. 5 and the packed layout of the device stream.
+#include "analysis.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <numeric>
+
+#include "../../include/gltrsv.h"
+
+namespace gltrsv {
+
+int check_csr(const CsrView &A, bool need_values, std::string *msg)
+{
+    auto fail = [&](int code, const std::string &m) {
+        if (msg) *msg = m;
+        return code;
+    };
+    if (A.n < 0 || A.nnz < 0) return fail(GLTRSV_EINVAL, "negative size");
+    if (A.n > kMaxRows) return fail(GLTRSV_ERANGE, "n exceeds 2^30 - 1");
+    if (A.n == 0) return GLTRSV_OK;
+    if (!A.row_ptr || !A.col) return fail(GLTRSV_EINVAL, "null row_ptr or col");
+    if (need_values && !A.val) return fail(GLTRSV_EINVAL, "null values");
+    if (A.row_ptr[0] != 0 || A.row_ptr[A.n] != A.nnz)
+        return fail(GLTRSV_ERANGE, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+    for (int64_t i = 0; i < A.n; i++) {
+        const int64_t lo = A.row_ptr[i], hi = A.row_ptr[i + 1];
+        if (hi < lo) return fail(GLTRSV_ERANGE, "row_ptr decreases at row " + std::to_string(i));
+        if (hi == lo) return fail(GLTRSV_ESINGULAR, "row " + std::to_string(i) + " has no diagonal");
+        int32_t prev = -1;
+        for (int64_t e = lo; e < hi; e++) {
+            const int32_t c = A.col[e];
+            if (c < 0 || c >= A.n) return fail(GLTRSV_ERANGE, "column out of range in row " + std::to_string(i));
+            if (c > i) return fail(GLTRSV_ENOTLOWER, "entry above the diagonal in row " + std::to_string(i));
+            if (c <= prev) return fail(GLTRSV_EUNSORTED, "columns not strictly rising in row " + std::to_string(i));
+            prev = c;
+        }
+        if (A.col[hi - 1] != i) return fail(GLTRSV_ESINGULAR, "row " + std::to_string(i) + " has no diagonal");
+        if (need_values && A.val[hi - 1] == 0.0)
+            return fail(GLTRSV_ESINGULAR, "zero diagonal in row " + std::to_string(i));
+    }
+    return GLTRSV_OK;
+}
+
+int32_t wavefront_levels(const CsrView &A, std::vector<int32_t> &level)
+{
+    level.assign(A.n, 0);
+    int32_t top = 0;
+    for (int64_t i = 0; i < A.n; i++) {
+        int32_t best = 0;
+        const int64_t last = A.row_ptr[i + 1] - 1;
+        for (int64_t e = A.row_ptr[i]; e < last; e++) best = std::max(best, level[A.col[e]]);
+        level[i] = best + 1;
+        top = std::max(top, best + 1);
+    }
+    return top;
+}
+
+Schedule schedule_wavefront(const CsrView &A)
+{
+    Schedule s;
+    std::vector<int32_t> level;
+    s.S = wavefront_levels(A, level);
+    s.core.resize(A.n);
+    s.superstep.resize(A.n);
+    std::vector<int32_t> width(s.S + 1, 0);
+    for (int64_t i = 0; i < A.n; i++) {
+        const int32_t lv = level[i] - 1;
+        s.superstep[i] = lv;
+        s.core[i] = width[lv]++;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// GrowLocal
+// ---------------------------------------------------------------------------
+namespace {
+
+class GrowLocalScheduler {
+public:
+    GrowLocalScheduler(const CsrView &A, const SchedParams &p) : A_(A), p_(p)
+    {
+        const int64_t n = A.n;
+        weight_.resize(n);
+        waiting_.resize(n);
+        kids_begin_.assign(n + 1, 0);
+        for (int64_t v = 0; v < n; v++) {
+            const int64_t lo = A.row_ptr[v], hi = A.row_ptr[v + 1];
+            weight_[v] = hi - lo;                 // stored entries, diagonal included
+            waiting_[v] = int32_t(hi - lo - 1);   // parents = stored off-diagonals
+            for (int64_t e = lo; e < hi - 1; e++) kids_begin_[A.col[e] + 1]++;
+        }
+        std::partial_sum(kids_begin_.begin(), kids_begin_.end(), kids_begin_.begin());
+        kids_.resize(kids_begin_[n]);
+        std::vector<int64_t> pos(kids_begin_.begin(), kids_begin_.end() - 1);
+        for (int64_t v = 0; v < n; v++)
+            for (int64_t e = A.row_ptr[v]; e < A.row_ptr[v + 1] - 1; e++) kids_[pos[A.col[e]]++] = int32_t(v);
+        seen_.assign(n, 0);
+        tmp_wait_.resize(n);
+        tmp_owner_.resize(n);
+        for (int64_t v = 0; v < n; v++)
+            if (waiting_[v] == 0) free_.push_back(int32_t(v));
+    }
+
+    Schedule run()
+    {
+        Schedule out;
+        out.core.assign(A_.n, -1);
+        out.superstep.assign(A_.n, -1);
+        int64_t done = 0;
+        int32_t s = 0;
+        std::vector<int32_t> picked_v, picked_p;
+        while (done < A_.n) {
+            // grow alpha while the iterations stay worthy (Algorithm 3.1)
+            double alpha = p_.alpha0, best = 0.0, keep_alpha = p_.alpha0;
+            for (int it = 0;; it++) {
+                const Trial t = trial(alpha, nullptr, nullptr);
+                const bool worthy = (it == 0) || (t.beta >= p_.accept * best);
+                if (!worthy) break;
+                keep_alpha = alpha;
+                if (it == 0 || t.beta > best) best = t.beta;
+                if (t.first_core_count < int64_t(std::floor(alpha))) break;  // saturated
+                alpha = p_.growth * alpha;
+            }
+            // replay the kept iteration and commit it as superstep s
+            picked_v.clear();
+            picked_p.clear();
+            trial(keep_alpha, &picked_v, &picked_p);
+            commit(picked_v, picked_p, s, out);
+            done += int64_t(picked_v.size());
+            s++;
+        }
+        out.S = s;
+        return out;
+    }
+
+private:
+    struct Trial {
+        double beta;
+        int64_t first_core_count;
+    };
+
+    // One iteration from the barrier state; optionally records the picks.
+    Trial trial(double alpha, std::vector<int32_t> *pv, std::vector<int32_t> *pp)
+    {
+        epoch_++;
+        const int64_t limit = int64_t(std::floor(alpha));
+        size_t next_free = 0;
+        int64_t w_first = 0, total = 0, heaviest = 0, first_count = 0;
+        for (int32_t core = 0; core < p_.k; core++) {
+            excl_.clear();
+            int64_t count = 0, load = 0;
+            while (core == 0 ? count < limit : load < w_first) {
+                int32_t v;
+                if (!excl_.empty()) {
+                    std::pop_heap(excl_.begin(), excl_.end(), std::greater<int32_t>());
+                    v = excl_.back();
+                    excl_.pop_back();
+                } else if (next_free < free_.size()) {
+                    v = free_[next_free++];
+                } else {
+                    break;
+                }
+                if (pv) {
+                    pv->push_back(v);
+                    pp->push_back(core);
+                }
+                count++;
+                load += weight_[v];
+                for (int64_t e = kids_begin_[v]; e < kids_begin_[v + 1]; e++) {
+                    const int32_t u = kids_[e];
+                    if (seen_[u] != epoch_) {
+                        seen_[u] = epoch_;
+                        tmp_wait_[u] = waiting_[u];
+                        tmp_owner_[u] = core;   // first parent placed in this superstep
+                    } else if (tmp_owner_[u] != core) {
+                        tmp_owner_[u] = -2;     // parents on two or more cores
+                    }
+                    if (--tmp_wait_[u] == 0 && tmp_owner_[u] == core) {
+                        excl_.push_back(u);
+                        std::push_heap(excl_.begin(), excl_.end(), std::greater<int32_t>());
+                    }
+                }
+            }
+            if (core == 0) {
+                w_first = load;
+                first_count = count;
+            }
+            total += load;
+            heaviest = std::max(heaviest, load);
+            if (next_free >= free_.size()) break;  // nothing left for later cores
+        }
+        Trial t;
+        t.beta = double(total) / (double(heaviest) + p_.L);
+        t.first_core_count = first_count;
+        return t;
+    }
+
+    void commit(const std::vector<int32_t> &pv, const std::vector<int32_t> &pp, int32_t s, Schedule &out)
+    {
+        for (size_t i = 0; i < pv.size(); i++) {
+            out.core[pv[i]] = pp[i];
+            out.superstep[pv[i]] = s;
+        }
+        fresh_.clear();
+        for (int32_t v : pv)
+            for (int64_t e = kids_begin_[v]; e < kids_begin_[v + 1]; e++) {
+                const int32_t u = kids_[e];
+                if (--waiting_[u] == 0 && out.superstep[u] < 0) fresh_.push_back(u);
+            }
+        std::sort(fresh_.begin(), fresh_.end());
+        merged_.clear();
+        merged_.reserve(free_.size() + fresh_.size());
+        auto keep = [&](int32_t v) { return out.superstep[v] < 0; };
+        size_t a = 0, b = 0;
+        while (a < free_.size() || b < fresh_.size()) {
+            if (a < free_.size() && !keep(free_[a])) { a++; continue; }
+            if (b == fresh_.size() || (a < free_.size() && free_[a] < fresh_[b])) merged_.push_back(free_[a++]);
+            else merged_.push_back(fresh_[b++]);
+        }
+        free_.swap(merged_);
+    }
+
+    const CsrView &A_;
+    SchedParams p_;
+    std::vector<int64_t> weight_;
+    std::vector<int32_t> waiting_;     // unassigned parents at the barrier
+    std::vector<int64_t> kids_begin_;
+    std::vector<int32_t> kids_;
+    std::vector<int32_t> free_;        // free at the barrier, rising IDs
+    std::vector<int32_t> fresh_, merged_;
+    std::vector<int32_t> excl_;        // min-heap of vertices exclusive to the core
+    std::vector<uint64_t> seen_;
+    uint64_t epoch_ = 0;
+    std::vector<int32_t> tmp_wait_, tmp_owner_;
+};
+
+}  // namespace
+
+Schedule schedule_growlocal(const CsrView &A, const SchedParams &p)
+{
+    if (A.n == 0) return Schedule{};
+    GrowLocalScheduler g(A, p);
+    return g.run();
+}
+
+std::vector<int32_t> schedule_order(int64_t n, const int32_t *core, const int32_t *superstep, int32_t S)
+{
+    // two stable counting passes: by core, then by superstep
+    int32_t kmax = 0;
+    for (int64_t i = 0; i < n; i++) kmax = std::max(kmax, core[i]);
+    std::vector<int64_t> cnt(std::max<int64_t>(kmax + 1, S) + 1, 0);
+    std::vector<int32_t> by_core(n), out(n);
+    for (int64_t i = 0; i < n; i++) cnt[core[i] + 1]++;
+    for (size_t c = 1; c < cnt.size(); c++) cnt[c] += cnt[c - 1];
+    for (int64_t i = 0; i < n; i++) by_core[cnt[core[i]]++] = int32_t(i);
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t i = 0; i < n; i++) cnt[superstep[i] + 1]++;
+    for (size_t c = 1; c < cnt.size(); c++) cnt[c] += cnt[c - 1];
+    for (int64_t t = 0; t < n; t++) {
+        const int32_t v = by_core[t];
+        out[cnt[superstep[v]]++] = v;
+    }
+    return out;
+}
+
+Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm)
+{
+    Packed pk;
+    pk.S = sch.S;
+    const int64_t n = A.n;
+    // tasks = maximal runs of equal (superstep, core) in the order
+    std::vector<int64_t> task_begin;
+    for (int64_t t = 0; t < n; t++) {
+        const int32_t v = perm[t];
+        if (t == 0 || sch.superstep[v] != sch.superstep[perm[t - 1]] || sch.core[v] != sch.core[perm[t - 1]])
+            task_begin.push_back(t);
+    }
+    const int64_t T = int64_t(task_begin.size());
+    task_begin.push_back(n);
+    pk.tasks = T;
+    std::vector<int64_t> task_len(T);  // stream entries = stored entries of its rows
+    for (int64_t j = 0; j < T; j++) {
+        int64_t e = 0;
+        for (int64_t t = task_begin[j]; t < task_begin[j + 1]; t++) e += A.row_ptr[perm[t] + 1] - A.row_ptr[perm[t]];
+        task_len[j] = e;
+        pk.max_task_rows = std::max(pk.max_task_rows, task_begin[j + 1] - task_begin[j]);
+    }
+    // per superstep: tasks longest first, 64 per chunk
+    pk.super_chunk.assign(sch.S + 1, 0);
+    std::vector<int64_t> order;
+    std::vector<int64_t> lane_task;  // task of each (chunk, lane), -1 for none
+    int64_t j0 = 0;
+    for (int32_t s = 0; s < sch.S; s++) {
+        int64_t j1 = j0;
+        while (j1 < T && sch.superstep[perm[task_begin[j1]]] == s) j1++;
+        order.resize(j1 - j0);
+        std::iota(order.begin(), order.end(), j0);
+        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return task_len[a] > task_len[b]; });
+        for (size_t q = 0; q < order.size(); q += kLanes) {
+            int64_t len = 0;
+            for (size_t l = 0; l < size_t(kLanes); l++) {
+                const int64_t task = (q + l < order.size()) ? order[q + l] : -1;
+                lane_task.push_back(task);
+                if (task >= 0) len = std::max(len, task_len[task]);
+            }
+            pk.chunk_len.push_back(int32_t(len));
+        }
+        pk.super_chunk[s + 1] = int32_t(pk.chunk_len.size());
+        j0 = j1;
+    }
+    const int64_t C = int64_t(pk.chunk_len.size());
+    pk.chunk_base.resize(C);
+    int64_t slots = 0;
+    for (int64_t c = 0; c < C; c++) {
+        pk.chunk_base[c] = slots;
+        slots += int64_t(kLanes) * pk.chunk_len[c];
+    }
+    pk.word.assign(slots, kPadWord);
+    pk.value.assign(slots, 0.0);
+    for (int64_t c = 0; c < C; c++) {
+        for (int l = 0; l < kLanes; l++) {
+            const int64_t task = lane_task[c * kLanes + l];
+            if (task < 0) continue;
+            int64_t t = 0;
+            const int32_t s = sch.superstep[perm[task_begin[task]]];
+            const int32_t p = sch.core[perm[task_begin[task]]];
+            for (int64_t r = task_begin[task]; r < task_begin[task + 1]; r++) {
+                const int32_t row = perm[r];
+                const int64_t lo = A.row_ptr[row], hi = A.row_ptr[row + 1] - 1;
+                int64_t at = pk.chunk_base[c] + int64_t(kLanes) * t + l;
+                pk.word[at] = kHdrBit | uint32_t(row);
+                pk.value[at] = A.val ? A.val[hi] : 1.0;
+                t++;
+                for (int64_t e = lo; e < hi; e++) {
+                    const int32_t col = A.col[e];
+                    const bool internal = sch.superstep[col] == s && sch.core[col] == p;
+                    at = pk.chunk_base[c] + int64_t(kLanes) * t + l;
+                    pk.word[at] = uint32_t(col) | (internal ? kIntBit : 0u);
+                    pk.value[at] = A.val ? A.val[e] : 0.0;
+                    t++;
+                }
+            }
+        }
+    }
+    return pk;
+}
+
+uint64_t pattern_key(const CsrView &A)
+{
+    // 64-bit multiply-xorshift mix over n, row pointers and columns
+    uint64_t h = 0x9E3779B97F4A7C15ull ^ uint64_t(A.n);
+    auto mix = [&](uint64_t x) {
+        h ^= x + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 31;
+    };
+    for (int64_t i = 0; i <= A.n; i++) mix(uint64_t(A.row_ptr[i]));
+    for (int64_t e = 0; e + 1 < A.nnz; e += 2) mix(uint64_t(uint32_t(A.col[e])) | (uint64_t(uint32_t(A.col[e + 1])) << 32));
+    if (A.nnz & 1) mix(uint64_t(uint32_t(A.col[A.nnz - 1])));
+    return h;
+}
+
+}  // namespace gltrsv

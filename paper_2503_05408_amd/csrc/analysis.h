@@ -1,0 +1,76 @@
+// Host-side analysis of a sparse lower-triangular matrix: checks, wavefronts,
+// the GrowLocal schedule (Algorithm 3.1), the schedule order of Sec. 5 and the
+// packed device layout the solve kernels read.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace gltrsv {
+
+// Stream word encoding of the packed layout (see pack_stream):
+//   bit 31 set            -> row header; bits 0..29 = original row index and
+//                            the paired value is the diagonal A_ii.
+//   0xFFFFFFFF            -> padding / end of a lane's rows.
+//   bit 30 set (31 clear) -> off-diagonal whose column was computed earlier in
+//                            the same (superstep, core) task; bits 0..29 = col.
+//   otherwise             -> off-diagonal whose column belongs to an earlier
+//                            superstep; the word is the column.
+constexpr uint32_t kHdrBit = 0x80000000u;
+constexpr uint32_t kIntBit = 0x40000000u;
+constexpr uint32_t kIdxMask = 0x3FFFFFFFu;
+constexpr uint32_t kPadWord = 0xFFFFFFFFu;
+constexpr int64_t kMaxRows = (int64_t(1) << 30) - 1;
+constexpr int kLanes = 64;  // tasks per chunk = lanes of a wavefront
+
+struct CsrView {
+    int64_t n = 0, nnz = 0;
+    const int64_t *row_ptr = nullptr;
+    const int32_t *col = nullptr;
+    const double *val = nullptr;
+};
+
+struct SchedParams {
+    int32_t k = 22;
+    double L = 500.0, alpha0 = 20.0, growth = 1.5, accept = 0.97;
+    int32_t kind = 0;  // 0 GrowLocal, 1 wavefront
+};
+
+struct Schedule {
+    std::vector<int32_t> core, superstep;
+    int32_t S = 0;
+};
+
+// Returns 0 or a negative GLTRSV_E* code; msg receives a description.
+int check_csr(const CsrView &A, bool need_values, std::string *msg);
+
+// level[i] in 1..; returns the number of wavefronts.
+int32_t wavefront_levels(const CsrView &A, std::vector<int32_t> &level);
+
+Schedule schedule_wavefront(const CsrView &A);
+Schedule schedule_growlocal(const CsrView &A, const SchedParams &p);
+
+// perm[t] = row at position t in (superstep, core, index) order.
+std::vector<int32_t> schedule_order(int64_t n, const int32_t *core, const int32_t *superstep, int32_t S);
+
+// Device layout.  Tasks of a superstep are sorted by length (longest first)
+// and grouped 64 at a time into chunks; chunk c occupies stream slots
+// [chunk_base[c], chunk_base[c] + 64 * chunk_len[c]), entry t of lane l at
+// chunk_base[c] + 64 * t + l.
+struct Packed {
+    int32_t S = 0;
+    std::vector<int32_t> super_chunk;   // [S+1] chunk range of each superstep
+    std::vector<int64_t> chunk_base;    // [C]
+    std::vector<int32_t> chunk_len;     // [C]
+    std::vector<uint32_t> word;         // [slots]
+    std::vector<double> value;          // [slots]
+    int64_t tasks = 0;
+    int64_t max_task_rows = 0;
+};
+
+Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm);
+
+uint64_t pattern_key(const CsrView &A);
+
+}  // namespace gltrsv
