@@ -170,6 +170,12 @@ int gltrsv_solve_plain(gltrsv_plan *plan, const double *b, double *x, void *stre
  * 1 = spin limit hit).  Synchronises the plan's last stream. */
 int gltrsv_plan_device_status(gltrsv_plan *plan, int32_t *status);
 
+/* Diagnostics of builds compiled with GLTRSV_TRACE (otherwise returns
+ * GLTRSV_ENOTSUP): copies up to `count` int64 wall-clock stamps of the last
+ * persistent solve, laid out [superstep][workgroup][3] = start of work, end
+ * of work, end of the barrier.  Synchronises the plan's last stream. */
+int gltrsv_debug_trace(gltrsv_plan *plan, int64_t *out, int64_t count);
+
 #ifdef __cplusplus
 }
 #endif

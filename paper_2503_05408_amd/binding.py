@@ -70,6 +70,7 @@ SIGNATURES = {
     "gltrsv_solve": ([P, P, P, P], i32),
     "gltrsv_solve_plain": ([P, P, P, P], i32),
     "gltrsv_plan_device_status": ([P, P], i32),
+    "gltrsv_debug_trace": ([P, P, i64], i32),
 }
 
 
@@ -249,6 +250,15 @@ class Plan:
         _check(load().gltrsv_solve_plain(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
                "gltrsv_solve_plain")
         return x
+
+    def debug_trace(self):
+        """[S, grid, 3] wall-clock stamps of the last persistent solve (trace
+        builds only)."""
+        inf = self.info()
+        S, G = inf["supersteps"], inf["grid_blocks"]
+        out = np.zeros(S * G * 3, dtype=np.int64)
+        _check(load().gltrsv_debug_trace(self._p, _np_ptr(out), out.size), "gltrsv_debug_trace")
+        return out.reshape(S, G, 3)
 
     def device_status(self) -> int:
         st = ctypes.c_int32(0)

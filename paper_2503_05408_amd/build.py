@@ -34,7 +34,9 @@ def is_stale() -> bool:
     return any(os.path.getmtime(s) > t for s in sources())
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str | None = None, defines=()) -> str:
+    """Compiles the library to ``out`` (default: the in-package path)."""
+    out = out or LIB
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
@@ -46,15 +48,16 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd))
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", *common,
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           *[f"-D{d}" for d in defines],
            "-shared", *[os.path.join(CSRC, s) for s in SOURCES_HIP], "-x", "none", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -321,6 +321,10 @@ Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int3
     }
     pk.word.assign(slots, kPadWord);
     pk.value.assign(slots, 0.0);
+    // position of every row inside its task (the order of Sec. 5)
+    std::vector<int32_t> pos(n);
+    for (int64_t j = 0; j < T; j++)
+        for (int64_t t = task_begin[j]; t < task_begin[j + 1]; t++) pos[perm[t]] = int32_t(t - task_begin[j]);
     for (int64_t c = 0; c < C; c++) {
         for (int l = 0; l < kLanes; l++) {
             const int64_t task = lane_task[c * kLanes + l];
@@ -337,9 +341,13 @@ Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int3
                 t++;
                 for (int64_t e = lo; e < hi; e++) {
                     const int32_t col = A.col[e];
-                    const bool internal = sch.superstep[col] == s && sch.core[col] == p;
+                    uint32_t w = uint32_t(col);
+                    if (sch.superstep[col] == s && sch.core[col] == p) {
+                        const int32_t back = pos[row] - pos[col];
+                        if (back < kRing) w = kIntBit | uint32_t(back);
+                    }
                     at = pk.chunk_base[c] + int64_t(kLanes) * t + l;
-                    pk.word[at] = uint32_t(col) | (internal ? kIntBit : 0u);
+                    pk.word[at] = w;
                     pk.value[at] = A.val ? A.val[e] : 0.0;
                     t++;
                 }

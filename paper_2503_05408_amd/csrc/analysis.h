@@ -13,14 +13,19 @@ namespace gltrsv {
 //   bit 31 set            -> row header; bits 0..29 = original row index and
 //                            the paired value is the diagonal A_ii.
 //   0xFFFFFFFF            -> padding / end of a lane's rows.
-//   bit 30 set (31 clear) -> off-diagonal whose column was computed earlier in
-//                            the same (superstep, core) task; bits 0..29 = col.
-//   otherwise             -> off-diagonal whose column belongs to an earlier
-//                            superstep; the word is the column.
+//   bit 30 set (31 clear) -> off-diagonal whose column is one of the last
+//                            kRing rows computed earlier in the same
+//                            (superstep, core) task; bits 0..29 = how many
+//                            rows back (1 = the previous row).
+//   otherwise             -> off-diagonal whose value is already in memory
+//                            when the lane's current batch starts (an earlier
+//                            superstep, or a row of the same task at least
+//                            kRing rows back); the word is the column.
 constexpr uint32_t kHdrBit = 0x80000000u;
 constexpr uint32_t kIntBit = 0x40000000u;
 constexpr uint32_t kIdxMask = 0x3FFFFFFFu;
 constexpr uint32_t kPadWord = 0xFFFFFFFFu;
+constexpr int kRing = 16;  // recent rows of a lane kept on chip
 constexpr int64_t kMaxRows = (int64_t(1) << 30) - 1;
 constexpr int kLanes = 64;  // tasks per chunk = lanes of a wavefront
 

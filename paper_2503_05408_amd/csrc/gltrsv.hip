@@ -32,104 +32,229 @@ constexpr uint32_t MASK = 0x3FFFFFFFu;
 constexpr uint32_t PAD = 0xFFFFFFFFu;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kUnroll = 8;
+#ifndef GLTRSV_UNROLL
+#define GLTRSV_UNROLL 8
+#endif
+constexpr int kUnroll = GLTRSV_UNROLL;
+using gltrsv::kRing;
 constexpr int kGenOffset = 32;   // the generation word sits 128 B after the count
 
-// One lane processes the packed entries of its task: words at
-// word[base + 64 t + lane], t < len.
-__device__ __forceinline__ void run_lane(const uint32_t *__restrict__ word, const double *__restrict__ value,
-                                         int64_t base, int32_t len, int lane, const double *b, double *x)
+// One lane processes the packed entries of its task: entry t at
+// word/value[base + 64 t + lane], t < len.  Entries are handled in batches of
+// kUnroll through a two-deep pipeline:
+//   while batch i is processed, the gathers of batch i+1 and the words and
+//   values of batch i+2 are in flight;
+//   every operand that is final before batch i+1 starts (x of an earlier
+//   superstep, b of a new row, a row of this task at least kRing rows back)
+//   is gathered from memory; rows of this task fewer than kRing rows back come
+//   from an on-chip ring (a register for the previous row, LDS for older);
+//   the x values finished in a batch are stored after the batch, so no store
+//   sits in front of a wait.
+// A row read from memory by batch j finished at least kRing >= 2 kUnroll
+// entries earlier, i.e. in batch j-2 or before, whose stores precede the
+// gathers of batch j in the lane's program order.
+// Loads are issued unconditionally (padding slots re-read the chunk's first
+// slot, non-gathered operands re-read b[0]) so their count per iteration is
+// fixed and the compiler can wait for exactly the batch it needs.
+static_assert(2 * kUnroll <= gltrsv::kRing, "the ring must cover two batches");
+
+struct Batch {
+    uint32_t w[kUnroll];
+    double v[kUnroll];
+};
+
+struct LaneCursor {
+    const uint32_t *wp;   // word + base + lane
+    const double *vp;
+    int32_t len;
+};
+
+__device__ __forceinline__ LaneCursor make_cursor(const uint32_t *__restrict__ word, const double *__restrict__ value,
+                                                  int64_t base, int32_t len, int lane)
 {
-    double acc = 0.0, diag = 1.0, last_y = 0.0;
-    int32_t cur = -1, last = -1;
-    const uint32_t *wp = word + base + lane;
-    const double *vp = value + base + lane;
-    for (int32_t t0 = 0; t0 < len; t0 += kUnroll) {
-        uint32_t w[kUnroll];
-        double v[kUnroll], g[kUnroll];
-#pragma unroll
-        for (int j = 0; j < kUnroll; j++) {
-            if (t0 + j < len) {
-                w[j] = __builtin_nontemporal_load(wp + int64_t(t0 + j) * 64);
-                v[j] = __builtin_nontemporal_load(vp + int64_t(t0 + j) * 64);
-            } else {
-                w[j] = PAD;
-                v[j] = 0.0;
-            }
-        }
-        // operands that are final before this superstep: columns of earlier
-        // supersteps and the right-hand side of each new row
-#pragma unroll
-        for (int j = 0; j < kUnroll; j++) {
-            const uint32_t c = w[j];
-            if ((c & (HDR | INTL)) == 0) g[j] = x[c];
-            else if ((c & HDR) && c != PAD) g[j] = b[c & MASK];
-            else g[j] = 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < kUnroll; j++) {
-            const uint32_t c = w[j];
-            if (c & HDR) {
-                if (cur >= 0) {
-                    const double y = acc / diag;
-                    x[cur] = y;
-                    last = cur;
-                    last_y = y;
-                }
-                if (c == PAD) {
-                    cur = -1;
-                } else {
-                    cur = int32_t(c & MASK);
-                    diag = v[j];
-                    acc = g[j];
-                }
-            } else {
-                double xv;
-                if (c & INTL) {
-                    // computed earlier on this lane in this superstep
-                    const int32_t cc = int32_t(c & MASK);
-                    xv = (cc == last) ? last_y : x[cc];
-                } else {
-                    xv = g[j];
-                }
-                const double prod = v[j] * xv;
-                acc = acc - prod;
-            }
-        }
-    }
-    if (cur >= 0) x[cur] = acc / diag;
+    LaneCursor c;
+    c.wp = word + base + lane;
+    c.vp = value + base + lane;
+    c.len = len;
+    return c;
 }
+
+__device__ __forceinline__ void load_batch(const LaneCursor &c, int32_t t0, Batch &B)
+{
+#pragma unroll
+    for (int j = 0; j < kUnroll; j++) {
+        const bool in = t0 + j < c.len;
+        const int64_t off = in ? int64_t(t0 + j) * 64 : 0;
+        const uint32_t w = __builtin_nontemporal_load(c.wp + off);
+        const double v = __builtin_nontemporal_load(c.vp + off);
+        B.w[j] = in ? w : PAD;
+        B.v[j] = v;
+    }
+}
+
+__device__ __forceinline__ void gather_batch(const Batch &B, const double *b, const double *x, double (&g)[kUnroll])
+{
+#pragma unroll
+    for (int j = 0; j < kUnroll; j++) {
+        const uint32_t c = B.w[j];
+        const bool ext = (c & (HDR | INTL)) == 0;
+        const bool hdr = (c & HDR) && c != PAD;
+        const double *src = ext ? x + c : (hdr ? b + (c & MASK) : b);
+        g[j] = *src;
+    }
+}
+
+struct LaneState {
+    double acc, diag, last_y;
+    int32_t cur;
+    uint32_t pos;
+};
+
+// Ring of the lane's recent rows in LDS: slot r % kRing holds row r of the
+// task; slot kRing takes the writes of entries that finish no row, so the
+// write needs no branch.
+using Ring = double (*)[kBlock];
+
+// Handles kUnroll entries in order.  Every entry runs the same instruction
+// sequence: the division that closes a row is evaluated for every entry and
+// kept only at row headers, so the wave never splits on the entry kind.
+__device__ __forceinline__ void process_batch(const Batch &B, const double (&g)[kUnroll], LaneState &st, double *x,
+                                              Ring ring)
+{
+    double ys[kUnroll];
+    int32_t yrow[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; j++) {
+        const uint32_t c = B.w[j];
+        const bool hdr = (c & HDR) != 0;           // row header or padding
+        const bool intl = (c >> 30) == 1u;         // same task, a few rows back
+        const bool fin = hdr && st.cur >= 0;       // closes the current row
+        const double y = st.acc / st.diag;
+        ys[j] = y;
+        yrow[j] = fin ? st.cur : -1;
+        st.last_y = fin ? y : st.last_y;
+        ring[fin ? (st.pos % kRing) : kRing][threadIdx.x] = y;
+        st.pos += fin ? 1u : 0u;
+        const uint32_t back = c & MASK;
+        double xv = g[j];
+        if (intl && back >= 2u) xv = ring[(st.pos - back) % kRing][threadIdx.x];
+        xv = (intl && back == 1u) ? st.last_y : xv;
+        const double prod = B.v[j] * xv;
+        const double nacc = st.acc - prod;
+        st.acc = hdr ? g[j] : nacc;
+        st.diag = hdr ? B.v[j] : st.diag;
+        st.cur = hdr ? (c == PAD ? -1 : int32_t(back)) : st.cur;
+    }
+#pragma unroll
+    for (int j = 0; j < kUnroll; j++)
+        if (yrow[j] >= 0) x[yrow[j]] = ys[j];
+}
+
+// One pipeline step: gathers of `nxt`, words/values of the batch after it
+// into `fut`, then the work of `now`.
+#define GLTRSV_STEP(NOW, GNOW, NXT, GNXT, FUT, T0)                                                       \
+    do {                                                                                                 \
+        gather_batch(NXT, b, x, GNXT);                                                                   \
+        load_batch(cur, (T0) + 2 * kUnroll, FUT);                                                        \
+        process_batch(NOW, GNOW, st, x, ring);                                                           \
+    } while (0)
+
+// Runs one lane's task.  b0/b1 hold the task's first two batches (already
+// loaded by the caller, possibly before the superstep's barrier).  The loop
+// is unrolled three times so the three batch buffers change roles without
+// register copies.
+__device__ __forceinline__ void run_lane(const LaneCursor &cur, Batch &b0, Batch &b1, const double *b, double *x,
+                                         Ring ring)
+{
+    LaneState st;
+    st.acc = 0.0;
+    st.diag = 1.0;
+    st.last_y = 0.0;
+    st.cur = -1;
+    st.pos = 0;
+    Batch b2;
+    double g0[kUnroll], g1[kUnroll], g2[kUnroll];
+    gather_batch(b0, b, x, g0);
+    int32_t t0 = 0;
+    for (;;) {
+        GLTRSV_STEP(b0, g0, b1, g1, b2, t0);
+        t0 += kUnroll;
+        if (t0 >= cur.len) break;
+        GLTRSV_STEP(b1, g1, b2, g2, b0, t0);
+        t0 += kUnroll;
+        if (t0 >= cur.len) break;
+        GLTRSV_STEP(b2, g2, b0, g0, b1, t0);
+        t0 += kUnroll;
+        if (t0 >= cur.len) break;
+    }
+    if (st.cur >= 0) x[st.cur] = st.acc / st.diag;
+}
+#undef GLTRSV_STEP
 
 __global__ __launch_bounds__(kBlock) void trsv_superstep_plain(
     const uint32_t *__restrict__ word, const double *__restrict__ value, const int64_t *__restrict__ chunk_base,
     const int32_t *__restrict__ chunk_len, int32_t c0, int32_t c1, const double *b, double *x)
 {
+    __shared__ double ring[kRing + 1][kBlock];
     const int32_t c = c0 + int32_t((blockIdx.x * kBlock + threadIdx.x) >> 6);
     if (c >= c1) return;
-    run_lane(word, value, chunk_base[c], chunk_len[c], threadIdx.x & 63, b, x);
+    const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], threadIdx.x & 63);
+    Batch b0, b1;
+    load_batch(cur, 0, b0);
+    load_batch(cur, kUnroll, b1);
+    run_lane(cur, b0, b1, b, x, ring);
 }
 
-// Barrier over all workgroups of the grid.  bar[0] counts arrivals,
-// bar[kGenOffset] is a generation number; the last arrival resets the count
-// and advances the generation.  Returns false if the spin limit was hit or
-// another workgroup reported an error; then the whole workgroup must exit.
-__device__ __forceinline__ bool grid_barrier(uint32_t *bar, int32_t *err, int64_t spin_limit)
+// Barrier over all workgroups of the grid, in two halves so that work that
+// does not depend on other workgroups can run while waiting.
+// bar[0] counts arrivals, bar[kGenOffset] is the generation; the last arrival
+// resets the count and advances the generation.
+struct BarrierTicket {
+    uint32_t gen;
+    bool last;
+};
+
+__device__ __forceinline__ BarrierTicket barrier_arrive(uint32_t *bar)
 {
-    __shared__ int32_t ok;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Every wave waits until its own stores have reached L2 (the vector L1 is
+    // write-through); thread 0's agent-scope release below then writes L2
+    // back, so the stores of all waves are visible before the arrival.
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
+    __shared__ uint32_t s_gen;
+    __shared__ int32_t s_last;
     if (threadIdx.x == 0) {
         uint32_t *count = bar;
         uint32_t *gen = bar + kGenOffset;
         const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        int32_t good = 1;
-        if (old == gridDim.x - 1) {
+        const bool last = old == gridDim.x - 1;
+        if (last) {
             __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        }
+        s_gen = g;
+        s_last = last;
+    }
+    __syncthreads();
+    BarrierTicket t;
+    t.gen = s_gen;
+    t.last = s_last != 0;
+    return t;
+}
+
+// Returns false if the spin limit was hit or another workgroup reported an
+// error; then the whole workgroup must exit.
+__device__ __forceinline__ bool barrier_wait(uint32_t *bar, BarrierTicket t, int32_t *err, int64_t spin_limit)
+{
+    __shared__ int32_t ok;
+    if (threadIdx.x == 0) {
+        int32_t good = 1;
+        if (!t.last) {
+            const uint32_t *gen = bar + kGenOffset;
             int64_t it = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == t.gen) {
                 __builtin_amdgcn_s_sleep(1);
                 if (++it > spin_limit) {
                     __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -146,23 +271,55 @@ __device__ __forceinline__ bool grid_barrier(uint32_t *bar, int32_t *err, int64_
         ok = good;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return ok != 0;
 }
 
 __global__ __launch_bounds__(kBlock) void trsv_persistent(
     const uint32_t *__restrict__ word, const double *__restrict__ value, const int64_t *__restrict__ chunk_base,
     const int32_t *__restrict__ chunk_len, const int32_t *__restrict__ super_chunk, int32_t S, const double *b,
-    double *x, uint32_t *bar, int32_t *err, int64_t spin_limit)
+    double *x, uint32_t *bar, int32_t *err, int64_t spin_limit, int64_t *trace)
 {
     const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
     const int32_t wave = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    __shared__ double ring[kRing + 1][kBlock];
+    // first chunk of this wave in superstep 0, and its first two batches
+    int32_t c = super_chunk[0] + wave;
+    int32_t c_end = super_chunk[1];
+    LaneCursor cur = make_cursor(word, value, c < c_end ? chunk_base[c] : 0, c < c_end ? chunk_len[c] : 0, lane);
+    Batch b0, b1;
+    load_batch(cur, 0, b0);
+    load_batch(cur, kUnroll, b1);
     for (int32_t s = 0; s < S; s++) {
-        const int32_t c1 = super_chunk[s + 1];
-        for (int32_t c = super_chunk[s] + wave; c < c1; c += waves)
-            run_lane(word, value, chunk_base[c], chunk_len[c], lane, b, x);
-        if (s + 1 < S && !grid_barrier(bar, err, spin_limit)) return;
+#ifdef GLTRSV_TRACE
+        if (threadIdx.x == 0) trace[(int64_t(s) * gridDim.x + blockIdx.x) * 3 + 0] = wall_clock64();
+#endif
+        while (c < c_end) {
+            run_lane(cur, b0, b1, b, x, ring);
+            c += waves;
+            if (c < c_end) {
+                cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
+                load_batch(cur, 0, b0);
+                load_batch(cur, kUnroll, b1);
+            }
+        }
+#ifdef GLTRSV_TRACE
+        if (threadIdx.x == 0) trace[(int64_t(s) * gridDim.x + blockIdx.x) * 3 + 1] = wall_clock64();
+#endif
+        if (s + 1 < S) {
+            const BarrierTicket t = barrier_arrive(bar);
+            // the matrix stream of the next superstep does not depend on x:
+            // fetch it while the other workgroups finish
+            c = super_chunk[s + 1] + wave;
+            c_end = super_chunk[s + 2];
+            cur = make_cursor(word, value, c < c_end ? chunk_base[c] : 0, c < c_end ? chunk_len[c] : 0, lane);
+            load_batch(cur, 0, b0);
+            load_batch(cur, kUnroll, b1);
+            if (!barrier_wait(bar, t, err, spin_limit)) return;
+        }
+#ifdef GLTRSV_TRACE
+        if (threadIdx.x == 0) trace[(int64_t(s) * gridDim.x + blockIdx.x) * 3 + 2] = wall_clock64();
+#endif
     }
 }
 
@@ -261,6 +418,7 @@ struct gltrsv_plan {
     int32_t *d_super_chunk = nullptr;
     uint32_t *d_bar = nullptr;   // barrier words (256 B)
     int32_t *d_err = nullptr;
+    int64_t *d_trace = nullptr;  // per-superstep timestamps (trace builds only)
     hipStream_t last_stream = nullptr;
     int64_t spin_limit = 20000000;
 };
@@ -348,6 +506,7 @@ int gltrsv_plan_destroy(gltrsv_plan *p)
     (void)hipFree(p->d_super_chunk);
     (void)hipFree(p->d_bar);
     (void)hipFree(p->d_err);
+    (void)hipFree(p->d_trace);
     delete p;
     return GLTRSV_OK;
 }
@@ -419,6 +578,15 @@ int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv
     const int64_t useful = (widest + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
     grid = int(std::max<int64_t>(1, std::min<int64_t>(grid, useful)));
     p->grid = grid;
+#ifdef GLTRSV_TRACE
+    {
+        std::vector<int64_t> tr(size_t(p->S) * grid * 3, 0);
+        if ((rc = upload(&p->d_trace, tr, &bytes))) {
+            gltrsv_plan_destroy(p);
+            return rc;
+        }
+    }
+#endif
     p->analysis_ns =
         std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
     *out = p;
@@ -485,10 +653,30 @@ int gltrsv_solve(gltrsv_plan *p, const double *b, double *x, void *stream)
     uint32_t *bar = p->d_bar;
     int32_t *err = p->d_err;
     int64_t lim = p->spin_limit;
-    void *args[] = {&w, &v, &cb, &cl, &sc, &S, &b, &x, &bar, &err, &lim};
+    int64_t *tr = p->d_trace;
+    void *args[] = {&w, &v, &cb, &cl, &sc, &S, &b, &x, &bar, &err, &lim, &tr};
+#ifdef GLTRSV_NONCOOP
+    (void)args;
+    hipLaunchKernelGGL(dev::trsv_persistent, dim3(p->grid), dim3(dev::kBlock), 0, st, w, v, cb, cl, sc, S, b, x, bar,
+                       err, lim, tr);
+    HIP_TRY(hipGetLastError());
+#else
     HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(dev::trsv_persistent), dim3(p->grid),
                                        dim3(dev::kBlock), args, 0, st));
+#endif
     p->last_stream = st;
+    return GLTRSV_OK;
+}
+
+// Trace builds only: copies S * grid * 3 timestamps (wall clock ticks) of the
+// last persistent solve: start of work, end of work, end of barrier.
+int gltrsv_debug_trace(gltrsv_plan *p, int64_t *out, int64_t count)
+{
+    if (!p || !out) return set_error(GLTRSV_EINVAL, "null argument");
+    if (!p->d_trace) return set_error(GLTRSV_ENOTSUP, "not a trace build");
+    const int64_t have = int64_t(p->S) * p->grid * 3;
+    HIP_TRY(hipStreamSynchronize(p->last_stream));
+    HIP_TRY(hipMemcpy(out, p->d_trace, sizeof(int64_t) * std::min(count, have), hipMemcpyDeviceToHost));
     return GLTRSV_OK;
 }
 
