@@ -90,7 +90,13 @@ typedef struct gltrsv_plan_opts {
     int32_t block_size;     /* device threads per workgroup (64..1024, a
                                multiple of 64); 0 = library default           */
     int32_t grid_blocks;    /* workgroups of the persistent kernel;
-                               0 = all that can be co-resident                */
+                               0 = all that can be co-resident (<= 2048)      */
+    int32_t cooperative;    /* 1: launch the persistent kernel with
+                               hipLaunchCooperativeKernel (co-residency
+                               guaranteed by the runtime); 0: plain launch of
+                               an occupancy-sized grid (lower launch cost; a
+                               workgroup kept from starting by other work on
+                               the device ends the solve with ETIMEDOUT)     */
 } gltrsv_plan_opts;
 
 /* Fills the paper's parameters: k = 22 (the core count of the main

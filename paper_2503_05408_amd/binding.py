@@ -42,7 +42,8 @@ class Csr(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("k", i32), ("L", dbl), ("alpha0", dbl), ("growth", dbl), ("accept", dbl),
-                ("schedule_kind", i32), ("reorder", i32), ("block_size", i32), ("grid_blocks", i32)]
+                ("schedule_kind", i32), ("reorder", i32), ("block_size", i32), ("grid_blocks", i32),
+                ("cooperative", i32)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -37,7 +37,6 @@ constexpr int kWavesPerBlock = kBlock / 64;
 #endif
 constexpr int kUnroll = GLTRSV_UNROLL;
 using gltrsv::kRing;
-constexpr int kGenOffset = 32;   // the generation word sits 128 B after the count
 
 // One lane processes the packed entries of its task: entry t at
 // word/value[base + 64 t + lane], t < len.  Entries are handled in batches of
@@ -62,6 +61,38 @@ struct Batch {
     uint32_t w[kUnroll];
     double v[kUnroll];
 };
+
+// Cross-workgroup data protocol.  x is the only array written during a
+// solve.  Every access to it (and to b, which may alias it) is an agent-scope
+// atomic access; on this GPU family those are the L2-coherent (sc1) loads and
+// stores, so a value stored by any XCD is what any other XCD loads once the
+// store has completed.  The barrier therefore needs no L2 write-back or
+// invalidation: an arrival waits for the workgroup's stores to complete, and
+// the gathers of the next superstep are issued after the new generation has
+// been observed.  Building with GLTRSV_FENCED uses plain accesses and
+// agent-scope release/acquire fences around the barrier instead (slower:
+// each fence writes back or invalidates the XCD's whole L2).
+__device__ __forceinline__ double load_x(const double *p)
+{
+#ifndef GLTRSV_FENCED
+    const unsigned long long u =
+        __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double(static_cast<long long>(u));
+#else
+    return *p;
+#endif
+}
+
+__device__ __forceinline__ void store_x(double *p, double v)
+{
+#ifndef GLTRSV_FENCED
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                       static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+#else
+    *p = v;
+#endif
+}
 
 struct LaneCursor {
     const uint32_t *wp;   // word + base + lane
@@ -100,7 +131,7 @@ __device__ __forceinline__ void gather_batch(const Batch &B, const double *b, co
         const bool ext = (c & (HDR | INTL)) == 0;
         const bool hdr = (c & HDR) && c != PAD;
         const double *src = ext ? x + c : (hdr ? b + (c & MASK) : b);
-        g[j] = *src;
+        g[j] = load_x(src);
     }
 }
 
@@ -147,7 +178,7 @@ __device__ __forceinline__ void process_batch(const Batch &B, const double (&g)[
     }
 #pragma unroll
     for (int j = 0; j < kUnroll; j++)
-        if (yrow[j] >= 0) x[yrow[j]] = ys[j];
+        if (yrow[j] >= 0) store_x(x + yrow[j], ys[j]);
 }
 
 // One pipeline step: gathers of `nxt`, words/values of the batch after it
@@ -187,7 +218,7 @@ __device__ __forceinline__ void run_lane(const LaneCursor &cur, Batch &b0, Batch
         t0 += kUnroll;
         if (t0 >= cur.len) break;
     }
-    if (st.cur >= 0) x[st.cur] = st.acc / st.diag;
+    if (st.cur >= 0) store_x(x + st.cur, st.acc / st.diag);
 }
 #undef GLTRSV_STEP
 
@@ -206,33 +237,65 @@ __global__ __launch_bounds__(kBlock) void trsv_superstep_plain(
 }
 
 // Barrier over all workgroups of the grid, in two halves so that work that
-// does not depend on other workgroups can run while waiting.
-// bar[0] counts arrivals, bar[kGenOffset] is the generation; the last arrival
-// resets the count and advances the generation.
+// does not depend on other workgroups can run while waiting.  Arrivals are
+// counted in two levels: workgroups of a group of kGroup count on the group's
+// word; the last of each group counts on the top word; the last of those
+// advances the generation word that every workgroup waits on.  No word sees
+// more than max(kGroup, groups) arrivals, and every word sits on its own
+// 128-byte line.  Each last arrival resets the word it completed before
+// moving up, so the words are ready for the next barrier.
+constexpr int kGroup = 16;
+constexpr int kBarGen = 0;          // word index of the generation
+constexpr int kBarTop = 32;         // word index of the top count
+constexpr int kBarGroups = 64;      // group g counts at kBarGroups + 32 g
+constexpr int kBarWords = kBarGroups + 32 * 128;   // up to 128 groups
+
 struct BarrierTicket {
     uint32_t gen;
     bool last;
 };
 
+#ifndef GLTRSV_FENCED
+#define GLTRSV_ARRIVE_ORDER __ATOMIC_RELAXED
+#define GLTRSV_NO_FENCES 1
+#else
+#define GLTRSV_ARRIVE_ORDER __ATOMIC_RELEASE
+#endif
+
 __device__ __forceinline__ BarrierTicket barrier_arrive(uint32_t *bar)
 {
-    // Every wave waits until its own stores have reached L2 (the vector L1 is
-    // write-through); thread 0's agent-scope release below then writes L2
-    // back, so the stores of all waves are visible before the arrival.
+    // Every wave waits until its own stores have completed (with fences:
+    // reached L2, which thread 0's agent-scope release then writes back).
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     __shared__ uint32_t s_gen;
     __shared__ int32_t s_last;
     if (threadIdx.x == 0) {
-        uint32_t *count = bar;
-        uint32_t *gen = bar + kGenOffset;
+        const uint32_t G = gridDim.x;
+        const uint32_t grp = blockIdx.x / kGroup;
+        const uint32_t groups = (G + kGroup - 1) / kGroup;
+        const uint32_t gsize = min(uint32_t(kGroup), G - grp * kGroup);
+        uint32_t *gen = bar + kBarGen;
+        uint32_t *top = bar + kBarTop;
+        uint32_t *cnt = bar + kBarGroups + 32 * grp;
         const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const bool last = old == gridDim.x - 1;
-        if (last) {
-            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        bool last = false;
+        const uint32_t old = __hip_atomic_fetch_add(cnt, 1u, GLTRSV_ARRIVE_ORDER, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == gsize - 1) {
+#ifndef GLTRSV_NO_FENCES
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#endif
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t old2 = __hip_atomic_fetch_add(top, 1u, GLTRSV_ARRIVE_ORDER, __HIP_MEMORY_SCOPE_AGENT);
+            if (old2 == groups - 1) {
+#ifndef GLTRSV_NO_FENCES
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#endif
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(gen, 1u, GLTRSV_ARRIVE_ORDER, __HIP_MEMORY_SCOPE_AGENT);
+                last = true;
+            }
         }
         s_gen = g;
         s_last = last;
@@ -252,7 +315,7 @@ __device__ __forceinline__ bool barrier_wait(uint32_t *bar, BarrierTicket t, int
     if (threadIdx.x == 0) {
         int32_t good = 1;
         if (!t.last) {
-            const uint32_t *gen = bar + kGenOffset;
+            const uint32_t *gen = bar + kBarGen;
             int64_t it = 0;
             while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == t.gen) {
                 __builtin_amdgcn_s_sleep(1);
@@ -267,7 +330,9 @@ __device__ __forceinline__ bool barrier_wait(uint32_t *bar, BarrierTicket t, int
                 }
             }
         }
+#ifndef GLTRSV_NO_FENCES
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#endif
         ok = good;
     }
     __syncthreads();
@@ -416,11 +481,12 @@ struct gltrsv_plan {
     int64_t *d_chunk_base = nullptr;
     int32_t *d_chunk_len = nullptr;
     int32_t *d_super_chunk = nullptr;
-    uint32_t *d_bar = nullptr;   // barrier words (256 B)
+    uint32_t *d_bar = nullptr;   // barrier words (dev::kBarWords)
     int32_t *d_err = nullptr;
     int64_t *d_trace = nullptr;  // per-superstep timestamps (trace builds only)
     hipStream_t last_stream = nullptr;
-    int64_t spin_limit = 20000000;
+    int64_t spin_limit = 5000000;   // about 5 s of polling
+    int cooperative = 0;
 };
 
 extern "C" {
@@ -442,6 +508,7 @@ void gltrsv_default_opts(gltrsv_plan_opts *o)
     o->reorder = 1;
     o->block_size = 0;
     o->grid_blocks = 0;
+    o->cooperative = 0;
 }
 
 int gltrsv_check_csr(const gltrsv_csr *A)
@@ -552,7 +619,7 @@ int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv
         return rc;
     }
     {
-        std::vector<uint32_t> bar(64, 0u);
+        std::vector<uint32_t> bar(dev::kBarWords, 0u);
         std::vector<int32_t> err(1, 0);
         if ((rc = upload(&p->d_bar, bar, &bytes)) || (rc = upload(&p->d_err, err, &bytes))) {
             gltrsv_plan_destroy(p);
@@ -569,8 +636,9 @@ int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv
         gltrsv_plan_destroy(p);
         return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
     }
-    int grid = per_cu * cus;
+    int grid = std::min(per_cu * cus, dev::kGroup * 128);
     if (opts->grid_blocks > 0) grid = std::min(grid, opts->grid_blocks);
+    p->cooperative = opts->cooperative != 0;
     // no more workgroups than the widest superstep can use
     int64_t widest = 0;
     for (int32_t q = 0; q < p->S; q++)
@@ -655,15 +723,18 @@ int gltrsv_solve(gltrsv_plan *p, const double *b, double *x, void *stream)
     int64_t lim = p->spin_limit;
     int64_t *tr = p->d_trace;
     void *args[] = {&w, &v, &cb, &cl, &sc, &S, &b, &x, &bar, &err, &lim, &tr};
-#ifdef GLTRSV_NONCOOP
-    (void)args;
-    hipLaunchKernelGGL(dev::trsv_persistent, dim3(p->grid), dim3(dev::kBlock), 0, st, w, v, cb, cl, sc, S, b, x, bar,
-                       err, lim, tr);
-    HIP_TRY(hipGetLastError());
-#else
-    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(dev::trsv_persistent), dim3(p->grid),
-                                       dim3(dev::kBlock), args, 0, st));
-#endif
+    if (p->cooperative) {
+        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(dev::trsv_persistent), dim3(p->grid),
+                                           dim3(dev::kBlock), args, 0, st));
+    } else {
+        // The grid fits the device's co-resident capacity (occupancy query at
+        // plan creation).  Should other work on the device keep workgroups
+        // from starting, the waiting ones reach the spin limit and the solve
+        // reports GLTRSV_ETIMEDOUT through gltrsv_plan_device_status.
+        hipLaunchKernelGGL(dev::trsv_persistent, dim3(p->grid), dim3(dev::kBlock), 0, st, w, v, cb, cl, sc, S, b, x,
+                           bar, err, lim, tr);
+        HIP_TRY(hipGetLastError());
+    }
     p->last_stream = st;
     return GLTRSV_OK;
 }
@@ -689,7 +760,7 @@ int gltrsv_plan_device_status(gltrsv_plan *p, int32_t *status)
     *status = e;
     if (e) {
         // a workgroup left the barrier early: clear the words for the next solve
-        HIP_TRY(hipMemset(p->d_bar, 0, 64 * sizeof(uint32_t)));
+        HIP_TRY(hipMemset(p->d_bar, 0, dev::kBarWords * sizeof(uint32_t)));
         HIP_TRY(hipMemset(p->d_err, 0, sizeof(int32_t)));
     }
     return GLTRSV_OK;
