@@ -57,6 +57,31 @@ def algorithmic_bytes(n: int, nnz: int) -> int:
     return 12 * nnz + 16 * n
 
 
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2503_05408_amd/csrc/gltrsv.hip", "paper_2503_05408_amd/csrc/analysis.cpp",
+              "paper_2503_05408_amd/csrc/analysis.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name: str, kernel: str):
+    """HBM-side bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated with the copy kernel), or None when no
+    summary exists for this workload or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"trsv_{workload_name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_sources_hash") != kernel_sources_hash() or kernel not in t.get("per_launch", {}):
+        return None
+    k = t["per_launch"][kernel]
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
 def cpu_baseline(m, budget_s: float = 15.0):
     import oracle
     b = np.ones(m.n)
@@ -158,11 +183,27 @@ def main():
     torch.cuda.synchronize()
     ms_plain = p0.elapsed_time(p1) / args.plain_steps
 
+    # achievable copy bandwidth (read + write of 1 GiB) with the library's copy kernel
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    B.copy_probe(src, dst)
+    torch.cuda.synchronize()
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        B.copy_probe(src, dst)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+
     rows_s = m.n / (ms * 1e-3) if exact else 0.0
     rows_s_plain = m.n / (ms_plain * 1e-3) if exact_plain else 0.0
     alg = algorithmic_bytes(m.n, m.nnz)
     kern_ms = float(np.mean(per))
     achieved = alg / (kern_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, "trsv_persistent") if args.schedule == "growlocal" else None
     out = {
         "metric": "reduced elements/sec (exact) at 1 MI355X vs plain launch; p50/p99 latency",
         "value": rows_s,
@@ -190,8 +231,10 @@ def main():
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "trsv_persistent", "alg_bytes_per_launch": alg, "kernel_ms": kern_ms,
+            "copy_probe_GBs": copy_gbs,
+            "traffic_GBs": (traffic / (kern_ms * 1e-3) / 1e9) if traffic else None,
         },
     }
     if not args.no_cpu_baseline:

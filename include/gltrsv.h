@@ -176,6 +176,12 @@ int gltrsv_solve_plain(gltrsv_plan *plan, const double *b, double *x, void *stre
  * 1 = spin limit hit).  Synchronises the plan's last stream. */
 int gltrsv_plan_device_status(gltrsv_plan *plan, int32_t *status);
 
+/* Plain device-to-device copy of `bytes` (a multiple of 16) from src to dst
+ * (device pointers, caller-owned, non-overlapping), asynchronous on `stream`.
+ * The achievable-bandwidth reference for the solve kernels and the
+ * calibration kernel for memory-traffic counters. */
+int gltrsv_copy_probe(const void *src, void *dst, int64_t bytes, void *stream);
+
 /* Diagnostics of builds compiled with GLTRSV_TRACE (otherwise returns
  * GLTRSV_ENOTSUP): copies up to `count` int64 wall-clock stamps of the last
  * persistent solve, laid out [superstep][workgroup][3] = start of work, end

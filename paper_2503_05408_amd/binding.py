@@ -72,6 +72,7 @@ SIGNATURES = {
     "gltrsv_solve_plain": ([P, P, P, P], i32),
     "gltrsv_plan_device_status": ([P, P], i32),
     "gltrsv_debug_trace": ([P, P, i64], i32),
+    "gltrsv_copy_probe": ([P, P, i64, P], i32),
 }
 
 
@@ -187,6 +188,15 @@ def _dev_ptr(t, n):
     if t.numel() != n or not t.is_contiguous():
         raise ValueError(f"expected a contiguous tensor of {n} values")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def copy_probe(src, dst, stream=None):
+    """Device copy of src into dst (CUDA tensors of equal byte size)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not src.is_cuda or not dst.is_cuda:
+        raise ValueError("copy_probe needs two CUDA tensors of the same size")
+    _check(load().gltrsv_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                                    _stream_ptr(stream)), "gltrsv_copy_probe")
 
 
 class Plan:

@@ -388,6 +388,15 @@ __global__ __launch_bounds__(kBlock) void trsv_persistent(
     }
 }
 
+// Plain copy of 16-byte elements, grid-stride: the achievable-bandwidth
+// reference and the calibration kernel of the memory-traffic counters.
+__global__ __launch_bounds__(kBlock) void copy_probe(const double2 *__restrict__ src, double2 *__restrict__ dst,
+                                                     int64_t n16)
+{
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
 }  // namespace dev
 }  // namespace gltrsv
 
@@ -736,6 +745,21 @@ int gltrsv_solve(gltrsv_plan *p, const double *b, double *x, void *stream)
         HIP_TRY(hipGetLastError());
     }
     p->last_stream = st;
+    return GLTRSV_OK;
+}
+
+int gltrsv_copy_probe(const void *src, void *dst, int64_t bytes, void *stream)
+{
+    if (!src || !dst || bytes < 0 || (bytes % 16) != 0) return set_error(GLTRSV_EINVAL, "bad copy arguments");
+    if (bytes == 0) return GLTRSV_OK;
+    int cus = 0, dev_id = 0;
+    HIP_TRY(hipGetDevice(&dev_id));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
+    const int64_t n16 = bytes / 16;
+    const int64_t blocks = std::min<int64_t>(int64_t(cus) * 8, (n16 + dev::kBlock - 1) / dev::kBlock);
+    hipLaunchKernelGGL(dev::copy_probe, dim3(unsigned(blocks)), dim3(dev::kBlock), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const double2 *>(src), static_cast<double2 *>(dst), n16);
+    HIP_TRY(hipGetLastError());
     return GLTRSV_OK;
 }
 

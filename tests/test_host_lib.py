@@ -1,0 +1,106 @@
+"""Host side of the HIP library, on the CPU: the shared library loads and
+exports every function include/gltrsv.h declares; CSR checks return the
+documented codes; the library's wavefronts, GrowLocal schedule and Sec. 5
+order equal the oracle's bit for bit (two independent implementations)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_05408_amd import binding as B
+from paper_2503_05408_amd import gen
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "gltrsv.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gltrsv_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = B.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in B.SIGNATURES, f"{name} has no binding"
+
+
+def test_version_and_defaults():
+    assert B.load().gltrsv_version().decode().count(".") == 2
+    o = B.default_opts()
+    assert (o.k, o.L, o.alpha0, o.growth, o.accept) == (22, 500.0, 20.0, 1.5, 0.97)
+    assert o.schedule_kind == B.SCHED_GROWLOCAL
+
+
+def _csr(n, rp, col, val):
+    return gen.CSR(n, np.asarray(rp, np.int64), np.asarray(col, np.int32), np.asarray(val, np.float64))
+
+
+@pytest.mark.parametrize("case,code", [
+    (lambda: _csr(2, [0, 1, 3], [0, 1, 1], [1.0, 2.0, 1.0]), -4),      # duplicate column
+    (lambda: _csr(2, [0, 2, 3], [0, 1, 1], [1.0, 2.0, 1.0]), -2),      # above the diagonal
+    (lambda: _csr(2, [0, 1, 2], [0, 0], [1.0, 1.0]), -3),              # row 1 lacks its diagonal
+    (lambda: _csr(2, [0, 1, 2], [0, 1], [1.0, 0.0]), -3),              # zero diagonal
+    (lambda: _csr(2, [0, 1, 2], [0, 5], [1.0, 1.0]), -5),              # column out of range
+    (lambda: _csr(2, [0, 1, 3], [0, 1, 0], [1.0, 1.0, 1.0]), -4),      # columns fall
+])
+def test_check_csr_codes(case, code):
+    assert B.check_csr(case()) == code
+
+
+def test_bad_options_rejected():
+    m = gen.fig_1_1()
+    for bad in (dict(k=0), dict(alpha0=0.5), dict(growth=1.0), dict(L=-1.0), dict(schedule_kind=7)):
+        with pytest.raises(B.GltrsvError):
+            B.schedule(m, B.default_opts(**bad))
+
+
+def cases():
+    out = [gen.fig_1_1(), gen.fig_3_1(), gen.edgeless(1000), gen.chain(300), gen.stencil_2d5(25, 9),
+           gen.random_lower(1, 0.5, 1)]
+    for s in range(12):
+        out.append(gen.random_lower(150, 0.02 + 0.02 * (s % 4), 40 + s, band=None if s % 2 else 5))
+    out += gen.small_set(3000)
+    return out
+
+
+PARAMS = [dict(), dict(k=1), dict(k=3, L=0.0), dict(k=4096, L=50.0, alpha0=1.0),
+          dict(k=100, L=10.0, alpha0=2.0, growth=2.0, accept=0.9), dict(k=1 << 16, L=5.0, alpha0=1.0)]
+
+
+@pytest.mark.parametrize("pidx", range(len(PARAMS)))
+def test_growlocal_equals_oracle(pidx):
+    p = PARAMS[pidx]
+    for m in cases():
+        o = B.default_opts(**p)
+        core, sup, S = B.schedule(m, o)
+        pi, sg, S2 = oracle.growlocal(m, o.k, L=o.L, alpha0=o.alpha0, growth=o.growth, theta=o.accept)
+        assert S == S2 and np.array_equal(core, pi) and np.array_equal(sup, sg), m.name
+
+
+def test_levels_wavefront_and_order_equal_oracle():
+    for m in cases():
+        lv, nl = B.levels(m)
+        lv2, nl2 = oracle.levels(m)
+        assert nl == nl2 and np.array_equal(lv, lv2)
+        core, sup, S = B.schedule(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT))
+        pi, sg, S2 = oracle.wavefront_schedule(m)
+        assert S == S2 and np.array_equal(core, pi) and np.array_equal(sup, sg)
+        core, sup, S = B.schedule(m, B.gpu_opts())
+        perm = B.reorder(core, sup)
+        perm2, _ = oracle.reorder(m, core, sup)
+        assert np.array_equal(perm, perm2)
+        assert oracle.validate(m, 1 << 16, core, sup, S) == oracle.VALID
+
+
+def test_empty_matrix():
+    m = gen.CSR(0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    assert B.check_csr(m) == 0
+    core, sup, S = B.schedule(m)
+    assert S == 0
