@@ -176,6 +176,46 @@ int gltrsv_solve_plain(gltrsv_plan *plan, const double *b, double *x, void *stre
  * 1 = spin limit hit).  Synchronises the plan's last stream. */
 int gltrsv_plan_device_status(gltrsv_plan *plan, int32_t *status);
 
+/* ---------------------------------------------------------------- batches */
+/* Many independent systems in one persistent launch (the schedules compose:
+ * systems share no data, so each advances through its own supersteps,
+ * Sec. 3.1 and Def. 2.1).  Waves claim `per_claim` 64-task chunks at a time
+ * from whichever system has an open superstep; the wave that completes a
+ * superstep opens the next one.  No grid-wide barrier is used, so the launch
+ * needs no co-residency. */
+typedef struct gltrsv_batch gltrsv_batch;
+
+typedef struct gltrsv_batch_opts {
+    int32_t per_claim;     /* chunks claimed per atomic, >= 1                 */
+    int32_t grid_blocks;   /* 0 = occupancy-sized grid                        */
+    int32_t use_graph;     /* 1: the reset + solve kernels are captured once
+                              into a hipGraph per stream and replayed         */
+} gltrsv_batch_opts;
+
+void gltrsv_default_batch_opts(gltrsv_batch_opts *opts);
+
+/* Binds `count` plans (library-owned, created on the current device; they
+ * must outlive the batch).  Plans with n = 0 are skipped. */
+int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_batch_opts *opts,
+                        gltrsv_batch **out);
+
+/* Solves system i with b[i] -> x[i] (host arrays of `count` device pointers,
+ * original numbering, b[i] may alias x[i]), asynchronously on `stream`.  Calls
+ * on one batch must not overlap (they share its device state). */
+int gltrsv_batch_solve(gltrsv_batch *batch, const double *const *b, double *const *x, void *stream);
+
+/* 0, or 1 if a wave went without work longer than the idle limit (~10 s).
+ * Synchronises the last stream. */
+int gltrsv_batch_status(gltrsv_batch *batch, int32_t *status);
+
+int gltrsv_batch_info(const gltrsv_batch *batch, int32_t *systems, int32_t *grid_blocks);
+
+int gltrsv_batch_destroy(gltrsv_batch *batch);
+
+/* One-shot form: create, solve, synchronise `stream`, destroy. */
+int gltrsv_solve_batched(gltrsv_plan *const *plans, const double *const *b, double *const *x, int32_t count,
+                         void *stream);
+
 /* Plain device-to-device copy of `bytes` (a multiple of 16) from src to dst
  * (device pointers, caller-owned, non-overlapping), asynchronous on `stream`.
  * The achievable-bandwidth reference for the solve kernels and the

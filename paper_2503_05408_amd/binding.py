@@ -46,6 +46,10 @@ class PlanOpts(ctypes.Structure):
                 ("cooperative", i32)]
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("per_claim", i32), ("grid_blocks", i32), ("use_graph", i32)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n", i64), ("nnz", i64), ("supersteps", i32), ("wavefronts", i32), ("tasks", i64),
                 ("chunks", i64), ("stream_slots", i64), ("device_bytes", i64), ("analysis_ns", i64),
@@ -73,6 +77,13 @@ SIGNATURES = {
     "gltrsv_plan_device_status": ([P, P], i32),
     "gltrsv_debug_trace": ([P, P, i64], i32),
     "gltrsv_copy_probe": ([P, P, i64, P], i32),
+    "gltrsv_default_batch_opts": ([P], None),
+    "gltrsv_batch_create": ([P, i32, P, P], i32),
+    "gltrsv_batch_solve": ([P, P, P, P], i32),
+    "gltrsv_batch_status": ([P, P], i32),
+    "gltrsv_batch_info": ([P, P, P], i32),
+    "gltrsv_batch_destroy": ([P], i32),
+    "gltrsv_solve_batched": ([P, P, P, i32, P], i32),
 }
 
 
@@ -275,3 +286,67 @@ class Plan:
         st = ctypes.c_int32(0)
         _check(load().gltrsv_plan_device_status(self._p, ctypes.byref(st)), "gltrsv_plan_device_status")
         return st.value
+
+
+def _ptr_array(tensors, n_of):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = _dev_ptr(t, n_of(i)).value
+    return arr
+
+
+class Batch:
+    """Several plans solved together in one persistent launch."""
+
+    def __init__(self, plans, per_claim: int = 1, use_graph: bool = True, grid_blocks: int = 0):
+        self.plans = list(plans)
+        o = BatchOpts()
+        load().gltrsv_default_batch_opts(ctypes.byref(o))
+        o.per_claim, o.use_graph, o.grid_blocks = int(per_claim), int(bool(use_graph)), int(grid_blocks)
+        handles = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        ptr = ctypes.c_void_p()
+        _check(load().gltrsv_batch_create(handles, len(self.plans), ctypes.byref(o), ctypes.byref(ptr)),
+               "gltrsv_batch_create")
+        self._p = ptr
+
+    def close(self):
+        if self._p:
+            load().gltrsv_batch_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def info(self):
+        s, g = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(load().gltrsv_batch_info(self._p, ctypes.byref(s), ctypes.byref(g)), "gltrsv_batch_info")
+        return {"systems": s.value, "grid_blocks": g.value}
+
+    def solve(self, bs, xs, stream=None):
+        bp = _ptr_array(bs, lambda i: self.plans[i].n)
+        xp = _ptr_array(xs, lambda i: self.plans[i].n)
+        _check(load().gltrsv_batch_solve(self._p, bp, xp, _stream_ptr(stream)), "gltrsv_batch_solve")
+        return xs
+
+    def status(self) -> int:
+        st = ctypes.c_int32(0)
+        _check(load().gltrsv_batch_status(self._p, ctypes.byref(st)), "gltrsv_batch_status")
+        return st.value
+
+
+def solve_batched(plans, bs, xs, stream=None):
+    """One-shot batched solve (synchronises the stream)."""
+    handles = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    bp = _ptr_array(bs, lambda i: plans[i].n)
+    xp = _ptr_array(xs, lambda i: plans[i].n)
+    _check(load().gltrsv_solve_batched(handles, bp, xp, len(plans), _stream_ptr(stream)), "gltrsv_solve_batched")
+    return xs

@@ -388,6 +388,135 @@ __global__ __launch_bounds__(kBlock) void trsv_persistent(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batched solve: many independent systems in one launch.
+//
+// Every system i has a 64-bit state word: high half = its open superstep,
+// low half = chunks of that superstep claimed so far.  A wave claims chunks
+// with one atomic add on the state word; a claim whose low half is beyond the
+// superstep's chunk count finds no work.  The wave that completes the last
+// chunk of superstep s (per-superstep done counters) publishes s+1 by
+// exchanging the state word to (s+1, 0): increments that land before the
+// exchange belonged to the exhausted superstep, those after it are claims of
+// s+1.  Systems never wait for each other, and a wave only waits for chunks
+// that running waves hold, so the grid needs no co-residency.
+// ---------------------------------------------------------------------------
+struct SysDesc {
+    const uint32_t *word;
+    const double *value;
+    const int64_t *chunk_base;
+    const int32_t *chunk_len;
+    const int32_t *super_chunk;
+    const double *b;
+    double *x;
+    int32_t S;
+    int32_t done_off;   // first per-superstep done counter of this system
+};
+
+__global__ __launch_bounds__(kBlock) void batch_reset(unsigned long long *state, uint32_t *done, int32_t count,
+                                                      int32_t ndone, uint32_t *finished, int32_t *err)
+{
+    const int32_t i = int32_t(blockIdx.x) * kBlock + int32_t(threadIdx.x);
+    if (i < count) state[i] = 0ull;
+    for (int32_t j = i; j < ndone; j += int32_t(gridDim.x) * kBlock) done[j] = 0u;
+    if (i == 0) {
+        *finished = 0u;
+        *err = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void trsv_batched(const SysDesc *__restrict__ sys, int32_t count,
+                                                       unsigned long long *state, uint32_t *done,
+                                                       uint32_t *finished, int32_t *err, int64_t spin_limit,
+                                                       int32_t per_claim)
+// spin_limit: wall-clock ticks a wave may go without finding work
+{
+    __shared__ double ring[kRing + 1][kBlock];
+    const int lane = threadIdx.x & 63;
+    const int32_t wave = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
+    int32_t home = count > 0 ? wave % count : 0;
+    int64_t idle_since = -1;   // wall-clock tick when this wave last found no work
+    for (;;) {
+        int32_t found = -1, fs = 0, c0 = 0, c1 = 0, quit = 0;
+        if (lane == 0) {
+            for (int32_t t = 0; t < count && found < 0; t++) {
+                const int32_t i = home + t < count ? home + t : home + t - count;
+                const int32_t S = sys[i].S;
+                const unsigned long long st =
+                    __hip_atomic_load(state + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int32_t s = int32_t(st >> 32);
+                if (s >= S) continue;
+                const int32_t *sc = sys[i].super_chunk;
+                const int32_t nch = sc[s + 1] - sc[s];
+                if (int64_t(st & 0xffffffffull) >= nch) continue;
+                const unsigned long long got = __hip_atomic_fetch_add(state + i, (unsigned long long)per_claim,
+                                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int32_t gs = int32_t(got >> 32);
+                const int64_t gc = int64_t(got & 0xffffffffull);
+                if (gs != s) {
+                    // the superstep advanced meanwhile: a valid claim of gs if in range
+                    if (gs >= S) continue;
+                    const int32_t n2 = sc[gs + 1] - sc[gs];
+                    if (gc >= n2) continue;
+                    found = i;
+                    fs = gs;
+                    c0 = sc[gs] + int32_t(gc);
+                    c1 = sc[gs] + int32_t(min<int64_t>(gc + per_claim, n2));
+                } else if (gc < nch) {
+                    found = i;
+                    fs = s;
+                    c0 = sc[s] + int32_t(gc);
+                    c1 = sc[s] + int32_t(min<int64_t>(gc + per_claim, nch));
+                }
+            }
+            if (found < 0) {
+                if (__hip_atomic_load(finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= uint32_t(count) ||
+                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                    quit = 1;
+            }
+        }
+        found = __shfl(found, 0);
+        quit = __shfl(quit, 0);
+        if (quit) return;
+        if (found < 0) {
+            if (lane == 0) {
+                __builtin_amdgcn_s_sleep(2);
+                const int64_t now = int64_t(wall_clock64());
+                if (idle_since < 0) idle_since = now;
+                else if (now - idle_since > spin_limit)
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            continue;
+        }
+        idle_since = -1;
+        fs = __shfl(fs, 0);
+        c0 = __shfl(c0, 0);
+        c1 = __shfl(c1, 0);
+        home = found;
+        const SysDesc d = sys[found];
+        for (int32_t c = c0; c < c1; c++) {
+            const LaneCursor cur = make_cursor(d.word, d.value, d.chunk_base[c], d.chunk_len[c], lane);
+            Batch b0, b1;
+            load_batch(cur, 0, b0);
+            load_batch(cur, kUnroll, b1);
+            run_lane(cur, b0, b1, d.b, d.x, ring);
+        }
+        // the chunks' x stores are complete before they are counted as done
+        __builtin_amdgcn_s_waitcnt(0);
+        if (lane == 0) {
+            const int32_t nch = d.super_chunk[fs + 1] - d.super_chunk[fs];
+            const uint32_t old = __hip_atomic_fetch_add(done + d.done_off + fs, uint32_t(c1 - c0),
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (int64_t(old) + (c1 - c0) == nch) {
+                __hip_atomic_exchange(state + found, (unsigned long long)(fs + 1) << 32, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                if (fs + 1 == d.S)
+                    __hip_atomic_fetch_add(finished, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
 // Plain copy of 16-byte elements, grid-stride: the achievable-bandwidth
 // reference and the calibration kernel of the memory-traffic counters.
 __global__ __launch_bounds__(kBlock) void copy_probe(const double2 *__restrict__ src, double2 *__restrict__ dst,
@@ -496,6 +625,31 @@ struct gltrsv_plan {
     hipStream_t last_stream = nullptr;
     int64_t spin_limit = 5000000;   // about 5 s of polling
     int cooperative = 0;
+};
+
+struct gltrsv_batch {
+    int32_t count = 0;                 // systems with n > 0
+    std::vector<gltrsv_plan *> plans;
+    std::vector<int32_t> slot;         // caller index of each kept system
+    int32_t ncalls = 0;                // caller's count
+    int device = 0;
+    int grid = 0;
+    int32_t per_claim = 1;
+    int32_t ndone = 0;
+    bool use_graph = true;
+    dev::SysDesc *d_desc = nullptr;
+    dev::SysDesc *h_desc[2] = {nullptr, nullptr};   // pinned staging, double-buffered
+    hipEvent_t staged[2] = {nullptr, nullptr};
+    int32_t flip = 0;
+    unsigned long long *d_state = nullptr;
+    uint32_t *d_done = nullptr;
+    uint32_t *d_finished = nullptr;
+    int32_t *d_err = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    hipStream_t last_stream = nullptr;
+    int64_t idle_ticks = 1000000000;   // 10 s of the 100 MHz wall clock
 };
 
 extern "C" {
@@ -788,6 +942,211 @@ int gltrsv_plan_device_status(gltrsv_plan *p, int32_t *status)
         HIP_TRY(hipMemset(p->d_err, 0, sizeof(int32_t)));
     }
     return GLTRSV_OK;
+}
+
+void gltrsv_default_batch_opts(gltrsv_batch_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->per_claim = 1;
+    o->grid_blocks = 0;
+    o->use_graph = 1;
+}
+
+int gltrsv_batch_destroy(gltrsv_batch *bt)
+{
+    if (!bt) return GLTRSV_OK;
+    if (bt->graph_exec) (void)hipGraphExecDestroy(bt->graph_exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    for (int k = 0; k < 2; k++) {
+        if (bt->staged[k]) (void)hipEventDestroy(bt->staged[k]);
+        if (bt->h_desc[k]) (void)hipHostFree(bt->h_desc[k]);
+    }
+    (void)hipFree(bt->d_desc);
+    (void)hipFree(bt->d_state);
+    (void)hipFree(bt->d_done);
+    (void)hipFree(bt->d_finished);
+    (void)hipFree(bt->d_err);
+    delete bt;
+    return GLTRSV_OK;
+}
+
+int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_batch_opts *opts,
+                        gltrsv_batch **out)
+{
+    if (!plans || !out || count < 0) return set_error(GLTRSV_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    gltrsv_batch_opts dflt;
+    gltrsv_default_batch_opts(&dflt);
+    if (!opts) opts = &dflt;
+    if (opts->per_claim < 1 || opts->grid_blocks < 0) return set_error(GLTRSV_EINVAL, "bad batch options");
+    int dev_id = 0;
+    HIP_TRY(hipGetDevice(&dev_id));
+    gltrsv_batch *bt = new (std::nothrow) gltrsv_batch();
+    if (!bt) return set_error(GLTRSV_ENOMEM, "host allocation");
+    bt->device = dev_id;
+    bt->ncalls = count;
+    bt->per_claim = opts->per_claim;
+    bt->use_graph = opts->use_graph != 0;
+    for (int32_t i = 0; i < count; i++) {
+        if (!plans[i]) {
+            gltrsv_batch_destroy(bt);
+            return set_error(GLTRSV_EINVAL, "null plan in batch");
+        }
+        if (plans[i]->device != dev_id) {
+            gltrsv_batch_destroy(bt);
+            return set_error(GLTRSV_EINVAL, "plans of a batch must live on the current device");
+        }
+        if (plans[i]->n == 0) continue;
+        bt->plans.push_back(plans[i]);
+        bt->slot.push_back(i);
+        bt->ndone += plans[i]->S;
+    }
+    bt->count = int32_t(bt->plans.size());
+    const size_t ndesc = std::max<size_t>(1, bt->plans.size());
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&bt->d_desc), ndesc * sizeof(dev::SysDesc));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_state), ndesc * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_done), std::max(1, bt->ndone) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_finished), sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_err), sizeof(int32_t));
+    for (int k = 0; k < 2 && e == hipSuccess; k++) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&bt->h_desc[k]), ndesc * sizeof(dev::SysDesc), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->staged[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        gltrsv_batch_destroy(bt);
+        return set_error(e == hipErrorOutOfMemory ? GLTRSV_ENOMEM : GLTRSV_EHIP,
+                         std::string("batch allocation: ") + hipGetErrorString(e));
+    }
+    int32_t off = 0;
+    for (int k = 0; k < 2; k++) {
+        off = 0;
+        for (int32_t i = 0; i < bt->count; i++) {
+            const gltrsv_plan *pl = bt->plans[i];
+            dev::SysDesc &d = bt->h_desc[k][i];
+            d.word = pl->d_word;
+            d.value = pl->d_value;
+            d.chunk_base = pl->d_chunk_base;
+            d.chunk_len = pl->d_chunk_len;
+            d.super_chunk = pl->d_super_chunk;
+            d.b = nullptr;
+            d.x = nullptr;
+            d.S = pl->S;
+            d.done_off = off;
+            off += pl->S;
+        }
+    }
+    int per_cu = 0, cus = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dev::trsv_batched, dev::kBlock, 0);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
+    if (e != hipSuccess) {
+        gltrsv_batch_destroy(bt);
+        return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
+    }
+    int64_t chunks = 0;
+    for (auto *pl : bt->plans) chunks += pl->chunks;
+    int grid = std::max(1, per_cu * cus);
+    if (opts->grid_blocks > 0) grid = std::min(grid, opts->grid_blocks);
+    grid = int(std::max<int64_t>(1, std::min<int64_t>(grid, (chunks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
+    bt->grid = grid;
+    *out = bt;
+    return GLTRSV_OK;
+}
+
+static int batch_enqueue(gltrsv_batch *bt, hipStream_t st)
+{
+    hipLaunchKernelGGL(dev::batch_reset, dim3(unsigned(std::max(1, (bt->count + dev::kBlock - 1) / dev::kBlock))),
+                       dim3(dev::kBlock), 0, st, bt->d_state, bt->d_done, bt->count, bt->ndone, bt->d_finished,
+                       bt->d_err);
+    hipLaunchKernelGGL(dev::trsv_batched, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st, bt->d_desc, bt->count,
+                       bt->d_state, bt->d_done, bt->d_finished, bt->d_err, bt->idle_ticks, bt->per_claim);
+    HIP_TRY(hipGetLastError());
+    return GLTRSV_OK;
+}
+
+int gltrsv_batch_solve(gltrsv_batch *bt, const double *const *b, double *const *x, void *stream)
+{
+    if (!bt || (bt->ncalls && (!b || !x))) return set_error(GLTRSV_EINVAL, "null argument");
+    if (bt->count == 0) return GLTRSV_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int k = bt->flip;
+    bt->flip ^= 1;
+    // the copy issued from this staging buffer two calls ago has finished
+    HIP_TRY(hipEventSynchronize(bt->staged[k]));
+    for (int32_t i = 0; i < bt->count; i++) {
+        const int32_t j = bt->slot[i];
+        if (!b[j] || !x[j]) return set_error(GLTRSV_EINVAL, "null vector in batch");
+        bt->h_desc[k][i].b = b[j];
+        bt->h_desc[k][i].x = x[j];
+    }
+    HIP_TRY(hipMemcpyAsync(bt->d_desc, bt->h_desc[k], sizeof(dev::SysDesc) * bt->count, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(bt->staged[k], st));
+    if (bt->use_graph && st != nullptr) {   // the null stream cannot be captured
+        if (!bt->graph_exec || bt->graph_stream != st) {
+            if (bt->graph_exec) {
+                HIP_TRY(hipGraphExecDestroy(bt->graph_exec));
+                bt->graph_exec = nullptr;
+            }
+            if (bt->graph) {
+                HIP_TRY(hipGraphDestroy(bt->graph));
+                bt->graph = nullptr;
+            }
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            const int rc = batch_enqueue(bt, st);
+            hipGraph_t g = nullptr;
+            const hipError_t ce = hipStreamEndCapture(st, &g);
+            if (rc) return rc;
+            if (ce != hipSuccess) return set_error(GLTRSV_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+            bt->graph = g;
+            HIP_TRY(hipGraphInstantiate(&bt->graph_exec, bt->graph, nullptr, nullptr, 0));
+            bt->graph_stream = st;
+        }
+        HIP_TRY(hipGraphLaunch(bt->graph_exec, st));
+    } else {
+        const int rc = batch_enqueue(bt, st);
+        if (rc) return rc;
+    }
+    bt->last_stream = st;
+    return GLTRSV_OK;
+}
+
+int gltrsv_batch_status(gltrsv_batch *bt, int32_t *status)
+{
+    if (!bt || !status) return set_error(GLTRSV_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(bt->last_stream));
+    int32_t e = 0;
+    HIP_TRY(hipMemcpy(&e, bt->d_err, sizeof(int32_t), hipMemcpyDeviceToHost));
+    *status = e;
+    return GLTRSV_OK;
+}
+
+int gltrsv_batch_info(const gltrsv_batch *bt, int32_t *systems, int32_t *grid_blocks)
+{
+    if (!bt) return set_error(GLTRSV_EINVAL, "null batch");
+    if (systems) *systems = bt->count;
+    if (grid_blocks) *grid_blocks = bt->grid;
+    return GLTRSV_OK;
+}
+
+int gltrsv_solve_batched(gltrsv_plan *const *plans, const double *const *b, double *const *x, int32_t count,
+                         void *stream)
+{
+    gltrsv_batch_opts o;
+    gltrsv_default_batch_opts(&o);
+    o.use_graph = 0;
+    gltrsv_batch *bt = nullptr;
+    int rc = gltrsv_batch_create(plans, count, &o, &bt);
+    if (rc) return rc;
+    rc = gltrsv_batch_solve(bt, b, x, stream);
+    if (rc == GLTRSV_OK) {
+        const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) rc = set_error(GLTRSV_EHIP, std::string("batched solve: ") + hipGetErrorString(e));
+    }
+    int32_t status = 0;
+    if (rc == GLTRSV_OK && (rc = gltrsv_batch_status(bt, &status)) == GLTRSV_OK && status)
+        rc = set_error(GLTRSV_ETIMEDOUT, "batched solve: a wave found no work for longer than the idle limit");
+    gltrsv_batch_destroy(bt);
+    return rc;
 }
 
 }  // extern "C"

@@ -1,0 +1,84 @@
+"""Batched solves (many systems, one persistent launch): every system's x is
+bit-identical to the oracle's, alone or in the batch, for several claim
+sizes, with and without hipGraph replay (replays interleaved with other
+device work, each one checked)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_05408_amd import binding as B
+from paper_2503_05408_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def systems():
+    ms = gen.small_set(3000)
+    ms += [gen.fig_1_1(), gen.edgeless(70), gen.chain(130), gen.random_lower(65, 0.1, 3)]
+    kinds = [B.gpu_opts()] * len(ms)
+    ms += [gen.stencil_2d5(30, 20), gen.stencil_3d7(9)]
+    kinds += [B.default_opts(schedule_kind=B.SCHED_WAVEFRONT)] * 2
+    ms.append(gen.narrow_band(2000, 0.03, 42.0, 5))
+    kinds.append(B.default_opts(k=8, L=20.0))
+    return ms, kinds
+
+
+@pytest.fixture(scope="module")
+def plans():
+    ms, kinds = systems()
+    ps = [B.Plan(m, o) for m, o in zip(ms, kinds)]
+    yield ms, ps
+    for p in ps:
+        p.close()
+
+
+@pytest.mark.parametrize("per_claim", [1, 4])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_matches_oracle(plans, per_claim, use_graph):
+    import torch
+    ms, ps = plans
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with B.Batch(ps, per_claim=per_claim, use_graph=use_graph) as bt:
+            assert bt.info()["systems"] == len(ps)
+            for rep in range(3):
+                bs = [gen.rhs_uniform(m.n, 100 * rep + i) for i, m in enumerate(ms)]
+                bd = [torch.from_numpy(b).cuda() for b in bs]
+                xd = [torch.full((m.n,), float("nan"), dtype=torch.float64, device="cuda") for m in ms]
+                bt.solve(bd, xd, stream)
+                stream.synchronize()
+                assert bt.status() == 0
+                for i, m in enumerate(ms):
+                    assert oracle.same_bits(xd[i].cpu().numpy(), oracle.solve(m, bs[i])), (rep, m.name)
+                # unrelated device work between replays
+                junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+                (junk * 2).sum().item()
+
+
+def test_one_shot_and_in_place(plans):
+    import torch
+    ms, ps = plans
+    bs = [gen.rhs_ones(m.n) for m in ms]
+    xd = [torch.from_numpy(b).cuda() for b in bs]       # b aliases x
+    B.solve_batched(ps, xd, xd)
+    for i, m in enumerate(ms):
+        assert oracle.same_bits(xd[i].cpu().numpy(), oracle.solve(m, bs[i])), m.name
+
+
+def test_batch_mix_small():
+    """The batching workload generator at small sizes (n = 10^2..10^4)."""
+    import torch
+    ms = gen.batch_mix(12, lo_exp=2.0, hi_exp=4.0)
+    ps = [B.Plan(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT) if m.meta.get("family") == "stencil"
+                 else B.gpu_opts()) for m in ms]
+    bs = [gen.rhs_uniform(m.n, i) for i, m in enumerate(ms)]
+    bd = [torch.from_numpy(b).cuda() for b in bs]
+    xd = [torch.empty_like(b) for b in bd]
+    with B.Batch(ps, per_claim=2) as bt:
+        bt.solve(bd, xd)
+        torch.cuda.synchronize()
+        assert bt.status() == 0
+    for i, m in enumerate(ms):
+        assert oracle.same_bits(xd[i].cpu().numpy(), oracle.solve(m, bs[i])), m.name
+    for p in ps:
+        p.close()
