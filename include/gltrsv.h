@@ -216,6 +216,55 @@ int gltrsv_batch_destroy(gltrsv_batch *batch);
 int gltrsv_solve_batched(gltrsv_plan *const *plans, const double *const *b, double *const *x, int32_t count,
                          void *stream);
 
+/* ---------------------------------------------------------------- serving */
+/* Continuous batching of solve requests against resident plans.  A worker
+ * thread owned by the server runs the batched kernel in time quanta; every
+ * admitted request advances through its supersteps in whichever quanta it
+ * is on the device, and requests submitted meanwhile join at the next
+ * quantum.  Results are bit-identical to gltrsv_solve (same per-row
+ * operations), alone or in any mix. */
+typedef struct gltrsv_server gltrsv_server;
+
+typedef struct gltrsv_server_opts {
+    int64_t budget_bytes;   /* in-flight budget: 16 n + 4 S + 64 bytes per
+                               request (its b and x plus its counters)        */
+    int32_t max_slots;      /* requests on the device at once                 */
+    int32_t per_claim;      /* chunks claimed per atomic                      */
+    double quantum_us;      /* device time per launch before new admissions   */
+    int32_t counter_words;  /* capacity of the per-superstep counter arena    */
+    int32_t grid_blocks;    /* 0 = occupancy-sized grid                       */
+} gltrsv_server_opts;
+
+typedef struct gltrsv_server_stats {
+    int64_t submitted, completed, failed, launches, rows_completed, queued, inflight_bytes;
+} gltrsv_server_stats;
+
+void gltrsv_default_server_opts(gltrsv_server_opts *opts);
+
+/* Creates a server on the current device and starts its worker thread. */
+int gltrsv_server_create(const gltrsv_server_opts *opts, gltrsv_server **out);
+
+/* Queues the solve b -> x with `plan` (device pointers, original numbering;
+ * b must be fully written before the call and b, x and the plan must stay
+ * valid until the ticket completes).  Returns GLTRSV_EAGAIN when the request
+ * would exceed the in-flight budget (retry after completions), ERANGE if it
+ * can never fit.  Thread-safe. */
+int gltrsv_server_submit(gltrsv_server *server, gltrsv_plan *plan, const double *b, double *x, uint64_t *ticket);
+
+/* Moves up to `max` completed tickets (and, if done_ns is not NULL, the
+ * gltrsv_clock_ns time at which the server saw each complete) to the caller;
+ * *ndone receives the count.  A completed ticket's x is final and visible to
+ * any later stream work.  Thread-safe. */
+int gltrsv_server_poll(gltrsv_server *server, uint64_t *tickets, int64_t *done_ns, int32_t max, int32_t *ndone);
+
+int gltrsv_server_get_stats(gltrsv_server *server, gltrsv_server_stats *out);
+
+/* Monotonic host clock used for completion times, in nanoseconds. */
+int64_t gltrsv_clock_ns(void);
+
+/* Waits until every accepted request has completed, then frees the server. */
+int gltrsv_server_destroy(gltrsv_server *server);
+
 /* Plain device-to-device copy of `bytes` (a multiple of 16) from src to dst
  * (device pointers, caller-owned, non-overlapping), asynchronous on `stream`.
  * The achievable-bandwidth reference for the solve kernels and the

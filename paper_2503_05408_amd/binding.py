@@ -50,6 +50,19 @@ class BatchOpts(ctypes.Structure):
     _fields_ = [("per_claim", i32), ("grid_blocks", i32), ("use_graph", i32)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", i64), ("max_slots", i32), ("per_claim", i32), ("quantum_us", dbl),
+                ("counter_words", i32), ("grid_blocks", i32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", i64), ("completed", i64), ("failed", i64), ("launches", i64),
+                ("rows_completed", i64), ("queued", i64), ("inflight_bytes", i64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n", i64), ("nnz", i64), ("supersteps", i32), ("wavefronts", i32), ("tasks", i64),
                 ("chunks", i64), ("stream_slots", i64), ("device_bytes", i64), ("analysis_ns", i64),
@@ -84,6 +97,13 @@ SIGNATURES = {
     "gltrsv_batch_info": ([P, P, P], i32),
     "gltrsv_batch_destroy": ([P], i32),
     "gltrsv_solve_batched": ([P, P, P, i32, P], i32),
+    "gltrsv_default_server_opts": ([P], None),
+    "gltrsv_server_create": ([P, P], i32),
+    "gltrsv_server_submit": ([P, P, P, P, P], i32),
+    "gltrsv_server_poll": ([P, P, P, i32, P], i32),
+    "gltrsv_server_get_stats": ([P, P], i32),
+    "gltrsv_clock_ns": ([], i64),
+    "gltrsv_server_destroy": ([P], i32),
 }
 
 
@@ -350,3 +370,65 @@ def solve_batched(plans, bs, xs, stream=None):
     xp = _ptr_array(xs, lambda i: plans[i].n)
     _check(load().gltrsv_solve_batched(handles, bp, xp, len(plans), _stream_ptr(stream)), "gltrsv_solve_batched")
     return xs
+
+
+GLTRSV_EAGAIN = -7
+
+
+def clock_ns() -> int:
+    return int(load().gltrsv_clock_ns())
+
+
+class Server:
+    """Continuous-batching solve server (worker thread inside the library)."""
+
+    def __init__(self, **overrides):
+        o = ServerOpts()
+        load().gltrsv_default_server_opts(ctypes.byref(o))
+        for k, v in overrides.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        self.opts = o
+        ptr = ctypes.c_void_p()
+        _check(load().gltrsv_server_create(ctypes.byref(o), ctypes.byref(ptr)), "gltrsv_server_create")
+        self._p = ptr
+
+    def submit(self, plan, b, x):
+        """Returns a ticket, or None when the in-flight budget is full (EAGAIN)."""
+        t = ctypes.c_uint64(0)
+        rc = load().gltrsv_server_submit(self._p, plan.handle, _dev_ptr(b, plan.n), _dev_ptr(x, plan.n),
+                                         ctypes.byref(t))
+        if rc == GLTRSV_EAGAIN:
+            return None
+        _check(rc, "gltrsv_server_submit")
+        return t.value
+
+    def poll(self, max_items: int = 4096):
+        tk = (ctypes.c_uint64 * max_items)()
+        ns = (ctypes.c_int64 * max_items)()
+        k = ctypes.c_int32(0)
+        _check(load().gltrsv_server_poll(self._p, tk, ns, max_items, ctypes.byref(k)), "gltrsv_server_poll")
+        return [(tk[i], ns[i]) for i in range(k.value)]
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().gltrsv_server_get_stats(self._p, ctypes.byref(st)), "gltrsv_server_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        if self._p:
+            load().gltrsv_server_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

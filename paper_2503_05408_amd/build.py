@@ -17,13 +17,13 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgltrsv.so")
 SOURCES_HOST = ["analysis.cpp"]
-SOURCES_HIP = ["gltrsv.hip"]
+SOURCES_HIP = ["gltrsv.hip", "serve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GLTRSV_ARCH", "gfx950")
 
 
 def sources():
-    return [os.path.join(CSRC, f) for f in SOURCES_HOST + SOURCES_HIP + ["analysis.h"]] + [
+    return [os.path.join(CSRC, f) for f in SOURCES_HOST + SOURCES_HIP + ["analysis.h", "internal.h"]] + [
         os.path.join(ROOT, "include", "gltrsv.h")]
 
 

@@ -20,6 +20,7 @@
 
 #include "../../include/gltrsv.h"
 #include "analysis.h"
+#include "internal.h"
 
 #pragma clang fp contract(off)
 
@@ -30,8 +31,6 @@ constexpr uint32_t HDR = 0x80000000u;
 constexpr uint32_t INTL = 0x40000000u;
 constexpr uint32_t MASK = 0x3FFFFFFFu;
 constexpr uint32_t PAD = 0xFFFFFFFFu;
-constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / 64;
 #ifndef GLTRSV_UNROLL
 #define GLTRSV_UNROLL 8
 #endif
@@ -401,17 +400,7 @@ __global__ __launch_bounds__(kBlock) void trsv_persistent(
 // s+1.  Systems never wait for each other, and a wave only waits for chunks
 // that running waves hold, so the grid needs no co-residency.
 // ---------------------------------------------------------------------------
-struct SysDesc {
-    const uint32_t *word;
-    const double *value;
-    const int64_t *chunk_base;
-    const int32_t *chunk_len;
-    const int32_t *super_chunk;
-    const double *b;
-    double *x;
-    int32_t S;
-    int32_t done_off;   // first per-superstep done counter of this system
-};
+
 
 __global__ __launch_bounds__(kBlock) void batch_reset(unsigned long long *state, uint32_t *done, int32_t count,
                                                       int32_t ndone, uint32_t *finished, int32_t *err)
@@ -425,21 +414,27 @@ __global__ __launch_bounds__(kBlock) void batch_reset(unsigned long long *state,
     }
 }
 
+// spin_limit: wall-clock ticks a wave may go without finding work.
+// target: the launch ends once `finished` reaches it (systems completed in
+// this launch).  quantum: wall-clock ticks after which waves stop claiming
+// (<= 0: no limit); claimed chunks are always completed, so every state word
+// is consistent when the launch ends and a later launch continues from it.
 __global__ __launch_bounds__(kBlock) void trsv_batched(const SysDesc *__restrict__ sys, int32_t count,
                                                        unsigned long long *state, uint32_t *done,
                                                        uint32_t *finished, int32_t *err, int64_t spin_limit,
-                                                       int32_t per_claim)
-// spin_limit: wall-clock ticks a wave may go without finding work
+                                                       int32_t per_claim, int32_t target, int64_t quantum)
 {
     __shared__ double ring[kRing + 1][kBlock];
     const int lane = threadIdx.x & 63;
     const int32_t wave = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
     int32_t home = count > 0 ? wave % count : 0;
     int64_t idle_since = -1;   // wall-clock tick when this wave last found no work
+    const int64_t deadline = quantum > 0 ? int64_t(wall_clock64()) + quantum : -1;
     for (;;) {
         int32_t found = -1, fs = 0, c0 = 0, c1 = 0, quit = 0;
         if (lane == 0) {
-            for (int32_t t = 0; t < count && found < 0; t++) {
+            const bool late = deadline >= 0 && int64_t(wall_clock64()) > deadline;
+            for (int32_t t = 0; t < count && found < 0 && !late; t++) {
                 const int32_t i = home + t < count ? home + t : home + t - count;
                 const int32_t S = sys[i].S;
                 const unsigned long long st =
@@ -470,7 +465,8 @@ __global__ __launch_bounds__(kBlock) void trsv_batched(const SysDesc *__restrict
                 }
             }
             if (found < 0) {
-                if (__hip_atomic_load(finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= uint32_t(count) ||
+                if (late ||
+                    __hip_atomic_load(finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= uint32_t(target) ||
                     __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
                     quit = 1;
             }
@@ -538,19 +534,15 @@ namespace {
 
 thread_local std::string g_last_error = "no error";
 
-int set_error(int code, const std::string &msg)
+}  // namespace
+
+int gltrsv::set_error(int code, const std::string &msg)
 {
     g_last_error = msg;
     return code;
 }
 
-#define HIP_TRY(expr)                                                                                   \
-    do {                                                                                                \
-        hipError_t e_ = (expr);                                                                         \
-        if (e_ != hipSuccess)                                                                           \
-            return set_error(e_ == hipErrorOutOfMemory ? GLTRSV_ENOMEM : GLTRSV_EHIP,                   \
-                             std::string(#expr) + ": " + hipGetErrorString(e_));                        \
-    } while (0)
+namespace {
 
 CsrView view_of(const gltrsv_csr *A)
 {
@@ -605,27 +597,7 @@ int upload(T **dst, const std::vector<T> &src, int64_t *bytes)
 
 }  // namespace
 
-struct gltrsv_plan {
-    int64_t n = 0, nnz = 0;
-    int32_t S = 0, wavefronts = 0;
-    int64_t tasks = 0, chunks = 0, slots = 0, max_task_rows = 0;
-    int64_t analysis_ns = 0, device_bytes = 0;
-    uint64_t key = 0;
-    int device = 0;
-    int grid = 0;
-    std::vector<int32_t> core, superstep, perm, super_chunk_host;
-    uint32_t *d_word = nullptr;
-    double *d_value = nullptr;
-    int64_t *d_chunk_base = nullptr;
-    int32_t *d_chunk_len = nullptr;
-    int32_t *d_super_chunk = nullptr;
-    uint32_t *d_bar = nullptr;   // barrier words (dev::kBarWords)
-    int32_t *d_err = nullptr;
-    int64_t *d_trace = nullptr;  // per-superstep timestamps (trace builds only)
-    hipStream_t last_stream = nullptr;
-    int64_t spin_limit = 5000000;   // about 5 s of polling
-    int cooperative = 0;
-};
+
 
 struct gltrsv_batch {
     int32_t count = 0;                 // systems with n > 0
@@ -1059,7 +1031,8 @@ static int batch_enqueue(gltrsv_batch *bt, hipStream_t st)
                        dim3(dev::kBlock), 0, st, bt->d_state, bt->d_done, bt->count, bt->ndone, bt->d_finished,
                        bt->d_err);
     hipLaunchKernelGGL(dev::trsv_batched, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st, bt->d_desc, bt->count,
-                       bt->d_state, bt->d_done, bt->d_finished, bt->d_err, bt->idle_ticks, bt->per_claim);
+                       bt->d_state, bt->d_done, bt->d_finished, bt->d_err, bt->idle_ticks, bt->per_claim, bt->count,
+                       int64_t(0));
     HIP_TRY(hipGetLastError());
     return GLTRSV_OK;
 }

@@ -1,0 +1,378 @@
+// Continuous-batching server for repeated solves against resident plans.
+//
+// Requests (plan, b, x) are queued by gltrsv_server_submit and admitted into
+// device slots while the in-flight budget allows.  A worker thread runs the
+// batched kernel in time quanta: waves claim chunks from every admitted
+// request's open superstep and stop claiming at the quantum's deadline; a
+// request's state word and done counters are consistent at the end of every
+// launch, so it simply continues in the next one.  Between quanta the worker
+// harvests finished requests (their superstep reached S), frees their slots
+// and admits queued ones, so requests that arrive while others run join the
+// device work at the next quantum.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+using namespace gltrsv;
+
+namespace {
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Request {
+    uint64_t ticket = 0;
+    gltrsv_plan *plan = nullptr;
+    const double *b = nullptr;
+    double *x = nullptr;
+    int64_t bytes = 0;
+};
+
+struct Slot {
+    bool busy = false;
+    bool fresh = false;     // admitted since the last launch
+    Request req;
+    int32_t done_off = 0;
+};
+
+// First-fit allocator of per-superstep done counters inside one device array.
+class CounterArena {
+public:
+    explicit CounterArena(int32_t words) { free_[0] = words; }
+    int32_t take(int32_t n)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                const int32_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > n) free_[off + n] = len - n;
+                return off;
+            }
+        }
+        return -1;
+    }
+    void give(int32_t off, int32_t n)
+    {
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    std::map<int32_t, int32_t> free_;
+};
+
+}  // namespace
+
+struct gltrsv_server {
+    gltrsv_server_opts opts{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int grid = 1;
+    dev::SysDesc *d_desc = nullptr;
+    unsigned long long *d_state = nullptr;
+    uint32_t *d_done = nullptr;
+    uint32_t *d_finished = nullptr;
+    int32_t *d_err = nullptr;
+    dev::SysDesc *h_desc = nullptr;          // pinned
+    unsigned long long *h_state = nullptr;   // pinned
+    CounterArena *arena = nullptr;
+
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request> queue;
+    std::vector<Slot> slots;
+    std::vector<std::pair<uint64_t, int64_t>> completed;
+    int64_t inflight_bytes = 0;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    int failure = 0;   // first error of the worker (GLTRSV_E*), sticky
+    std::string failure_text;
+    gltrsv_server_stats stats{};
+    std::thread worker;
+};
+
+namespace {
+
+int free_server_memory(gltrsv_server *sv)
+{
+    (void)hipFree(sv->d_desc);
+    (void)hipFree(sv->d_state);
+    (void)hipFree(sv->d_done);
+    (void)hipFree(sv->d_finished);
+    (void)hipFree(sv->d_err);
+    if (sv->h_desc) (void)hipHostFree(sv->h_desc);
+    if (sv->h_state) (void)hipHostFree(sv->h_state);
+    if (sv->stream) (void)hipStreamDestroy(sv->stream);
+    delete sv->arena;
+    return GLTRSV_OK;
+}
+
+// One quantum: upload the descriptors of newly admitted requests, launch,
+// read back every state word.  Runs on the worker thread without the lock.
+int run_quantum(gltrsv_server *sv, int32_t used, int32_t busy)
+{
+    for (int32_t i = 0; i < used; i++) {
+        Slot &sl = sv->slots[i];
+        if (!sl.fresh) continue;
+        sl.fresh = false;
+        HIP_TRY(hipMemcpyAsync(sv->d_desc + i, sv->h_desc + i, sizeof(dev::SysDesc), hipMemcpyHostToDevice,
+                               sv->stream));
+        HIP_TRY(hipMemsetAsync(sv->d_state + i, 0, sizeof(unsigned long long), sv->stream));
+        HIP_TRY(hipMemsetAsync(sv->d_done + sl.done_off, 0, sizeof(uint32_t) * size_t(sl.req.plan->S), sv->stream));
+    }
+    HIP_TRY(hipMemsetAsync(sv->d_finished, 0, sizeof(uint32_t), sv->stream));
+    const int64_t quantum = int64_t(sv->opts.quantum_us * 100.0);   // 100 MHz wall clock
+    hipLaunchKernelGGL(dev::trsv_batched, dim3(unsigned(sv->grid)), dim3(dev::kBlock), 0, sv->stream, sv->d_desc, used,
+                       sv->d_state, sv->d_done, sv->d_finished, sv->d_err, int64_t(1000000000), sv->opts.per_claim,
+                       busy, std::max<int64_t>(quantum, 1));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(sv->h_state, sv->d_state, sizeof(unsigned long long) * size_t(used), hipMemcpyDeviceToHost,
+                           sv->stream));
+    int32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, sv->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, sv->stream));
+    HIP_TRY(hipStreamSynchronize(sv->stream));
+    if (err) return set_error(GLTRSV_ETIMEDOUT, "server: a wave went without work past the idle limit");
+    return GLTRSV_OK;
+}
+
+void worker_main(gltrsv_server *sv)
+{
+    if (hipSetDevice(sv->device) != hipSuccess) {
+        std::lock_guard<std::mutex> g(sv->mu);
+        sv->failure = GLTRSV_EHIP;
+        sv->failure_text = "server: hipSetDevice failed";
+        return;
+    }
+    for (;;) {
+        int32_t used = 0, busy = 0;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            // admit queued requests into the lowest free slots
+            while (!sv->queue.empty()) {
+                int32_t free_slot = -1;
+                for (int32_t i = 0; i < int32_t(sv->slots.size()); i++)
+                    if (!sv->slots[i].busy) {
+                        free_slot = i;
+                        break;
+                    }
+                if (free_slot < 0) break;
+                Request &r = sv->queue.front();
+                const int32_t off = sv->arena->take(std::max(1, r.plan->S));
+                if (off < 0) break;
+                Slot &sl = sv->slots[free_slot];
+                sl.busy = true;
+                sl.fresh = true;
+                sl.req = r;
+                sl.done_off = off;
+                dev::SysDesc &d = sv->h_desc[free_slot];
+                d.word = r.plan->d_word;
+                d.value = r.plan->d_value;
+                d.chunk_base = r.plan->d_chunk_base;
+                d.chunk_len = r.plan->d_chunk_len;
+                d.super_chunk = r.plan->d_super_chunk;
+                d.b = r.b;
+                d.x = r.x;
+                d.S = r.plan->S;
+                d.done_off = off;
+                sv->queue.pop_front();
+            }
+            for (int32_t i = 0; i < int32_t(sv->slots.size()); i++)
+                if (sv->slots[i].busy) {
+                    busy++;
+                    used = i + 1;
+                }
+            if (busy == 0) {
+                if (sv->stop) return;
+                sv->cv.wait_for(lk, std::chrono::milliseconds(1));
+                continue;
+            }
+        }
+        const int rc = run_quantum(sv, used, busy);
+        const int64_t t = now_ns();
+        std::lock_guard<std::mutex> g(sv->mu);
+        sv->stats.launches++;
+        if (rc) {
+            sv->failure = rc;
+            sv->failure_text = gltrsv_last_error();
+            // fail every request on the device and in the queue
+            for (auto &sl : sv->slots)
+                if (sl.busy) {
+                    sl.busy = false;
+                    sv->stats.failed++;
+                }
+            sv->stats.failed += int64_t(sv->queue.size());
+            sv->queue.clear();
+            sv->inflight_bytes = 0;
+            return;
+        }
+        for (int32_t i = 0; i < used; i++) {
+            Slot &sl = sv->slots[i];
+            if (!sl.busy) continue;
+            if (int32_t(sv->h_state[i] >> 32) >= sl.req.plan->S) {
+                sv->completed.emplace_back(sl.req.ticket, t);
+                sv->stats.completed++;
+                sv->stats.rows_completed += sl.req.plan->n;
+                sv->inflight_bytes -= sl.req.bytes;
+                sv->arena->give(sl.done_off, std::max(1, sl.req.plan->S));
+                sl.busy = false;
+                sv->h_desc[i].S = 0;
+                sl.fresh = true;   // upload the emptied descriptor with the next launch
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void gltrsv_default_server_opts(gltrsv_server_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->budget_bytes = int64_t(4) << 30;
+    o->max_slots = 256;
+    o->per_claim = 1;
+    o->quantum_us = 200.0;
+    o->counter_words = 1 << 22;
+    o->grid_blocks = 0;
+}
+
+int gltrsv_server_create(const gltrsv_server_opts *opts, gltrsv_server **out)
+{
+    if (!out) return set_error(GLTRSV_EINVAL, "null argument");
+    *out = nullptr;
+    gltrsv_server_opts dflt;
+    gltrsv_default_server_opts(&dflt);
+    if (!opts) opts = &dflt;
+    if (opts->budget_bytes <= 0 || opts->max_slots < 1 || opts->per_claim < 1 || !(opts->quantum_us > 0.0) ||
+        opts->counter_words < 1 || opts->grid_blocks < 0)
+        return set_error(GLTRSV_EINVAL, "bad server options");
+    gltrsv_server *sv = new (std::nothrow) gltrsv_server();
+    if (!sv) return set_error(GLTRSV_ENOMEM, "host allocation");
+    sv->opts = *opts;
+    hipError_t e = hipGetDevice(&sv->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    const size_t ns = size_t(opts->max_slots);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_desc), ns * sizeof(dev::SysDesc));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_state), ns * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_done), size_t(opts->counter_words) * 4);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_finished), sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_err), sizeof(int32_t));
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_desc), ns * sizeof(dev::SysDesc), 0);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_state), ns * sizeof(unsigned long long), 0);
+    if (e == hipSuccess) e = hipMemset(sv->d_err, 0, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(sv->d_desc, 0, ns * sizeof(dev::SysDesc));
+    int per_cu = 0, cus = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dev::trsv_batched, dev::kBlock, 0);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, sv->device);
+    if (e != hipSuccess) {
+        free_server_memory(sv);
+        delete sv;
+        return set_error(e == hipErrorOutOfMemory ? GLTRSV_ENOMEM : GLTRSV_EHIP,
+                         std::string("server creation: ") + hipGetErrorString(e));
+    }
+    std::memset(sv->h_desc, 0, ns * sizeof(dev::SysDesc));
+    sv->grid = std::max(1, per_cu * cus);
+    if (opts->grid_blocks > 0) sv->grid = std::min(sv->grid, opts->grid_blocks);
+    sv->slots.resize(ns);
+    sv->arena = new CounterArena(opts->counter_words);
+    sv->worker = std::thread(worker_main, sv);
+    *out = sv;
+    return GLTRSV_OK;
+}
+
+int gltrsv_server_submit(gltrsv_server *sv, gltrsv_plan *plan, const double *b, double *x, uint64_t *ticket)
+{
+    if (!sv || !plan || !ticket || (plan->n && (!b || !x))) return set_error(GLTRSV_EINVAL, "null argument");
+    if (plan->device != sv->device) return set_error(GLTRSV_EINVAL, "plan lives on another device");
+    if (plan->S > sv->opts.counter_words) return set_error(GLTRSV_ERANGE, "plan has more supersteps than counters");
+    const int64_t bytes = 16 * plan->n + 4 * int64_t(std::max(1, plan->S)) + int64_t(sizeof(dev::SysDesc));
+    std::lock_guard<std::mutex> g(sv->mu);
+    if (sv->failure) return set_error(sv->failure, sv->failure_text);
+    if (bytes > sv->opts.budget_bytes) return set_error(GLTRSV_ERANGE, "request larger than the whole budget");
+    if (sv->inflight_bytes + bytes > sv->opts.budget_bytes)
+        return set_error(GLTRSV_EAGAIN, "in-flight budget exhausted; retry after completions");
+    *ticket = sv->next_ticket++;
+    sv->stats.submitted++;
+    if (plan->n == 0 || plan->S == 0) {
+        sv->completed.emplace_back(*ticket, now_ns());
+        sv->stats.completed++;
+        return GLTRSV_OK;
+    }
+    Request r;
+    r.ticket = *ticket;
+    r.plan = plan;
+    r.b = b;
+    r.x = x;
+    r.bytes = bytes;
+    sv->inflight_bytes += bytes;
+    sv->queue.push_back(r);
+    sv->cv.notify_one();
+    return GLTRSV_OK;
+}
+
+int gltrsv_server_poll(gltrsv_server *sv, uint64_t *tickets, int64_t *done_ns, int32_t max, int32_t *ndone)
+{
+    if (!sv || !ndone || max < 0 || (max > 0 && !tickets)) return set_error(GLTRSV_EINVAL, "bad poll arguments");
+    std::lock_guard<std::mutex> g(sv->mu);
+    const int32_t k = int32_t(std::min<size_t>(size_t(max), sv->completed.size()));
+    for (int32_t i = 0; i < k; i++) {
+        tickets[i] = sv->completed[i].first;
+        if (done_ns) done_ns[i] = sv->completed[i].second;
+    }
+    sv->completed.erase(sv->completed.begin(), sv->completed.begin() + k);
+    *ndone = k;
+    if (sv->failure && k == 0) return set_error(sv->failure, sv->failure_text);
+    return GLTRSV_OK;
+}
+
+int gltrsv_server_get_stats(gltrsv_server *sv, gltrsv_server_stats *out)
+{
+    if (!sv || !out) return set_error(GLTRSV_EINVAL, "null argument");
+    std::lock_guard<std::mutex> g(sv->mu);
+    *out = sv->stats;
+    out->queued = int64_t(sv->queue.size());
+    out->inflight_bytes = sv->inflight_bytes;
+    return GLTRSV_OK;
+}
+
+int64_t gltrsv_clock_ns(void) { return now_ns(); }
+
+int gltrsv_server_destroy(gltrsv_server *sv)
+{
+    if (!sv) return GLTRSV_OK;
+    {
+        std::lock_guard<std::mutex> g(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    free_server_memory(sv);
+    delete sv;
+    return GLTRSV_OK;
+}
+
+}  // extern "C"

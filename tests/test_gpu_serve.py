@@ -1,0 +1,99 @@
+"""Serving (continuous batching): requests against resident plans, submitted
+while others are on the device, give x bit-identical to the oracle and to the
+same request solved alone; the in-flight budget is enforced."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_05408_amd import binding as B
+from paper_2503_05408_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pool():
+    ms = gen.small_set(2500) + [gen.fig_3_1(), gen.chain(200), gen.edgeless(100)]
+    opts = [B.gpu_opts()] * len(ms)
+    ms += [gen.stencil_2d5(40, 25)]
+    opts += [B.default_opts(schedule_kind=B.SCHED_WAVEFRONT)]
+    plans = [B.Plan(m, o) for m, o in zip(ms, opts)]
+    yield ms, plans
+    for p in plans:
+        p.close()
+
+
+def drain(server, pending, timeout=30.0):
+    done = {}
+    t0 = time.time()
+    while len(done) < pending and time.time() - t0 < timeout:
+        for tk, ns in server.poll():
+            done[tk] = ns
+        time.sleep(0.0005)
+    return done
+
+
+@pytest.mark.parametrize("quantum_us", [50.0, 400.0])
+def test_mixed_requests_match_oracle_and_alone(pool, quantum_us):
+    import torch
+    ms, plans = pool
+    rng = np.random.default_rng(7)
+    reqs = []
+    with B.Server(quantum_us=quantum_us, max_slots=16) as sv:
+        for r in range(60):
+            i = int(rng.integers(0, len(ms)))
+            b = gen.rhs_uniform(ms[i].n, 1000 + r)
+            bd = torch.from_numpy(b).cuda()
+            xd = torch.full((ms[i].n,), float("nan"), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()           # b is written before submit
+            tk = sv.submit(plans[i], bd, xd)
+            assert tk is not None
+            reqs.append((tk, i, b, bd, xd))
+            if r % 7 == 0:
+                time.sleep(0.001)              # let some complete while others arrive
+        done = drain(sv, len(reqs))
+        assert len(done) == len(reqs), sv.stats()
+        st = sv.stats()
+        assert st["completed"] == len(reqs) and st["failed"] == 0
+    for tk, i, b, bd, xd in reqs:
+        got = xd.cpu().numpy()
+        assert oracle.same_bits(got, oracle.solve(ms[i], b)), ms[i].name
+        alone = plans[i].solve(bd)
+        torch.cuda.synchronize()
+        assert oracle.same_bits(got, alone.cpu().numpy())
+
+
+def test_budget_admission(pool):
+    import torch
+    ms, plans = pool
+    i = 0
+    n = ms[i].n
+    per_request = 16 * n + 4 * plans[i].info()["supersteps"] + 64
+    with B.Server(budget_bytes=2 * per_request + 10, quantum_us=100.0) as sv:
+        bd = torch.ones(n, dtype=torch.float64, device="cuda")
+        xs = [torch.empty_like(bd) for _ in range(3)]
+        torch.cuda.synchronize()
+        t1 = sv.submit(plans[i], bd, xs[0])
+        t2 = sv.submit(plans[i], bd, xs[1])
+        assert t1 is not None and t2 is not None
+        deadline = time.time() + 10
+        t3 = sv.submit(plans[i], bd, xs[2])
+        while t3 is None and time.time() < deadline:   # over budget until one completes
+            time.sleep(0.001)
+            t3 = sv.submit(plans[i], bd, xs[2])
+        assert t3 is not None
+        assert len(drain(sv, 3)) == 3
+    want = oracle.solve(ms[i], np.ones(n))
+    for x in xs:
+        assert oracle.same_bits(x.cpu().numpy(), want)
+
+
+def test_request_larger_than_budget_rejected(pool):
+    import torch
+    ms, plans = pool
+    with B.Server(budget_bytes=64) as sv:
+        bd = torch.ones(ms[0].n, dtype=torch.float64, device="cuda")
+        with pytest.raises(B.GltrsvError):
+            sv.submit(plans[0], bd, torch.empty_like(bd))
