@@ -76,6 +76,7 @@ int gltrsv_check_csr(const gltrsv_csr *A);
 /* ------------------------------------------------------------- schedules */
 #define GLTRSV_SCHED_GROWLOCAL 0   /* Algorithm 3.1                           */
 #define GLTRSV_SCHED_WAVEFRONT 1   /* level sets: one superstep per wavefront */
+#define GLTRSV_SCHED_AUTO      2   /* both; keep the lower predicted time     */
 
 typedef struct gltrsv_plan_opts {
     int32_t k;              /* cores of the BSP schedule (Def. 2.1), >= 1     */
@@ -120,6 +121,10 @@ int gltrsv_levels(const gltrsv_csr *A, int32_t *level, int32_t *nlevels);
  *     iteration becomes the superstep.  Vertex weight = stored entries of the
  *     row (Sec. 2.2).
  *  WAVEFRONT -- superstep = level - 1, core = rank of the row in its level.
+ *  AUTO -- builds both and keeps the one with the lower predicted device time
+ *     (gltrsv_plan_info.predicted_us); under the literal rules GrowLocal puts
+ *     a DAG whose ready vertices are all exclusive to core 1 (one source, e.g.
+ *     a natural-order grid) in a single serial superstep, which AUTO avoids.
  * Outputs (host arrays of n int32, caller-owned): core[i] in [0, k) (for
  * WAVEFRONT in [0, widest level)), superstep[i] in [0, S), *S = supersteps.
  * Host only; does not touch the GPU. */
@@ -146,6 +151,11 @@ typedef struct gltrsv_plan_info {
     int32_t grid_blocks;    /* persistent-kernel workgroups                   */
     int32_t block_size;     /* threads per workgroup                          */
     int64_t max_task_rows;  /* longest row sequence on one core in a superstep */
+    int32_t schedule_kind;  /* the schedule built (AUTO resolves to one)      */
+    double predicted_us;    /* cost-model prediction of one solve: per
+                               superstep 3 us plus the larger of 0.18 us per
+                               entry of its longest task and its entries at
+                               4e4 entries/us                                */
 } gltrsv_plan_info;
 
 /* Analyses A (checks, schedule, Sec. 5 order) and uploads the packed matrix

@@ -28,6 +28,7 @@ ERRORS = {
 }
 SCHED_GROWLOCAL = 0
 SCHED_WAVEFRONT = 1
+SCHED_AUTO = 2
 
 
 class GltrsvError(RuntimeError):
@@ -66,7 +67,8 @@ class ServerStats(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n", i64), ("nnz", i64), ("supersteps", i32), ("wavefronts", i32), ("tasks", i64),
                 ("chunks", i64), ("stream_slots", i64), ("device_bytes", i64), ("analysis_ns", i64),
-                ("pattern_key", u64), ("grid_blocks", i32), ("block_size", i32), ("max_task_rows", i64)]
+                ("pattern_key", u64), ("grid_blocks", i32), ("block_size", i32), ("max_task_rows", i64),
+                ("schedule_kind", i32), ("predicted_us", dbl)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -357,6 +357,29 @@ Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int3
     return pk;
 }
 
+double predict_cost_us(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm, const CostModel &cm)
+{
+    double total = 0.0;
+    int64_t t = 0;
+    const int64_t n = A.n;
+    while (t < n) {
+        const int32_t s = sch.superstep[perm[t]];
+        int64_t longest = 0, entries = 0;
+        while (t < n && sch.superstep[perm[t]] == s) {
+            const int32_t p = sch.core[perm[t]];
+            int64_t task = 0;
+            while (t < n && sch.superstep[perm[t]] == s && sch.core[perm[t]] == p) {
+                task += A.row_ptr[perm[t] + 1] - A.row_ptr[perm[t]];
+                t++;
+            }
+            longest = std::max(longest, task);
+            entries += task;
+        }
+        total += cm.superstep_us + std::max(cm.entry_us * double(longest), double(entries) / cm.entries_per_us);
+    }
+    return total;
+}
+
 uint64_t pattern_key(const CsrView &A)
 {
     // 64-bit multiply-xorshift mix over n, row pointers and columns

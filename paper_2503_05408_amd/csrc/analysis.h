@@ -76,6 +76,17 @@ struct Packed {
 
 Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm);
 
+// Predicted device time of one solve under `sch`, in microseconds: per
+// superstep a fixed cost (barrier and one dependent memory round trip) plus
+// the larger of the longest task (one lane walks it entry by entry) and the
+// superstep's entries at the device's entry throughput.
+struct CostModel {
+    double superstep_us = 3.0;     // barrier + first gather round trip
+    double entry_us = 0.18;        // one lane, one stored entry
+    double entries_per_us = 4.0e4; // whole device, random gathers
+};
+double predict_cost_us(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm, const CostModel &cm);
+
 uint64_t pattern_key(const CsrView &A);
 
 }  // namespace gltrsv

@@ -558,9 +558,10 @@ CsrView view_of(const gltrsv_csr *A)
 int check_opts(const gltrsv_plan_opts *o)
 {
     if (!o) return set_error(GLTRSV_EINVAL, "null options");
-    if (o->schedule_kind != GLTRSV_SCHED_GROWLOCAL && o->schedule_kind != GLTRSV_SCHED_WAVEFRONT)
+    if (o->schedule_kind != GLTRSV_SCHED_GROWLOCAL && o->schedule_kind != GLTRSV_SCHED_WAVEFRONT &&
+        o->schedule_kind != GLTRSV_SCHED_AUTO)
         return set_error(GLTRSV_EINVAL, "unknown schedule kind");
-    if (o->schedule_kind == GLTRSV_SCHED_GROWLOCAL) {
+    if (o->schedule_kind != GLTRSV_SCHED_WAVEFRONT) {
         if (o->k < 1) return set_error(GLTRSV_EINVAL, "k must be >= 1");
         if (!(o->alpha0 >= 1.0)) return set_error(GLTRSV_EINVAL, "alpha0 must be >= 1");
         if (!(o->growth > 1.0)) return set_error(GLTRSV_EINVAL, "growth must be > 1");
@@ -595,9 +596,41 @@ int upload(T **dst, const std::vector<T> &src, int64_t *bytes)
     return GLTRSV_OK;
 }
 
+// GROWLOCAL, WAVEFRONT, or AUTO: both, keeping the lower predicted device
+// time (ties go to GrowLocal).  Returns the order of Sec. 5 in *perm and the
+// prediction in *cost_us.
+Schedule build_schedule(const CsrView &V, const gltrsv_plan_opts *o, std::vector<int32_t> *perm, double *cost_us,
+                        int32_t *chosen)
+{
+    const CostModel cm;
+    if (o->schedule_kind == GLTRSV_SCHED_WAVEFRONT) {
+        Schedule w = schedule_wavefront(V);
+        *perm = schedule_order(V.n, w.core.data(), w.superstep.data(), w.S);
+        *cost_us = predict_cost_us(V, w, *perm, cm);
+        *chosen = GLTRSV_SCHED_WAVEFRONT;
+        return w;
+    }
+    Schedule g = schedule_growlocal(V, params_of(o));
+    std::vector<int32_t> pg = schedule_order(V.n, g.core.data(), g.superstep.data(), g.S);
+    const double cg = predict_cost_us(V, g, pg, cm);
+    if (o->schedule_kind == GLTRSV_SCHED_AUTO) {
+        Schedule w = schedule_wavefront(V);
+        std::vector<int32_t> pw = schedule_order(V.n, w.core.data(), w.superstep.data(), w.S);
+        const double cw = predict_cost_us(V, w, pw, cm);
+        if (cw < cg) {
+            *perm = std::move(pw);
+            *cost_us = cw;
+            *chosen = GLTRSV_SCHED_WAVEFRONT;
+            return w;
+        }
+    }
+    *perm = std::move(pg);
+    *cost_us = cg;
+    *chosen = GLTRSV_SCHED_GROWLOCAL;
+    return g;
+}
+
 }  // namespace
-
-
 
 struct gltrsv_batch {
     int32_t count = 0;                 // systems with n > 0
@@ -675,8 +708,10 @@ int gltrsv_schedule(const gltrsv_csr *A, const gltrsv_plan_opts *opts, int32_t *
     std::string msg;
     rc = check_csr(view_of(A), false, &msg);
     if (rc) return set_error(rc, msg);
-    Schedule s = opts->schedule_kind == GLTRSV_SCHED_WAVEFRONT ? schedule_wavefront(view_of(A))
-                                                               : schedule_growlocal(view_of(A), params_of(opts));
+    std::vector<int32_t> perm;
+    double cost = 0.0;
+    int32_t chosen = 0;
+    Schedule s = build_schedule(view_of(A), opts, &perm, &cost, &chosen);
     if (A->n) {
         std::memcpy(core, s.core.data(), sizeof(int32_t) * A->n);
         std::memcpy(superstep, s.superstep.data(), sizeof(int32_t) * A->n);
@@ -729,11 +764,9 @@ int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv
     if (!p) return set_error(GLTRSV_ENOMEM, "host allocation");
     p->n = A->n;
     p->nnz = A->nnz;
-    Schedule s = opts->schedule_kind == GLTRSV_SCHED_WAVEFRONT ? schedule_wavefront(V)
-                                                               : schedule_growlocal(V, params_of(opts));
+    Schedule s = build_schedule(V, opts, &p->perm, &p->predicted_us, &p->schedule_kind);
     std::vector<int32_t> lv;
     p->wavefronts = wavefront_levels(V, lv);
-    p->perm = schedule_order(A->n, s.core.data(), s.superstep.data(), s.S);
     Packed pk = pack_stream(V, s, p->perm);
     p->S = s.S;
     p->core = std::move(s.core);
@@ -813,6 +846,8 @@ int gltrsv_plan_info_get(const gltrsv_plan *p, gltrsv_plan_info *o)
     o->grid_blocks = p->grid;
     o->block_size = dev::kBlock;
     o->max_task_rows = p->max_task_rows;
+    o->schedule_kind = p->schedule_kind;
+    o->predicted_us = p->predicted_us;
     return GLTRSV_OK;
 }
 

@@ -68,6 +68,8 @@ struct gltrsv_plan {
     int32_t *d_err = nullptr;
     int64_t *d_trace = nullptr;  // per-superstep timestamps (trace builds only)
     hipStream_t last_stream = nullptr;
-    int64_t spin_limit = 5000000;   // about 5 s of polling
+    int64_t spin_limit = 5000000;
+    int32_t schedule_kind = 0;      // the schedule actually built
+    double predicted_us = 0.0;      // cost-model prediction of one solve   // about 5 s of polling
     int cooperative = 0;
 };

@@ -39,6 +39,7 @@ OPTS = {
     "gpu": dict(k=1 << 16, L=50.0, alpha0=1.0),
     "k3": dict(k=3, L=0.0),
     "wavefront": dict(schedule_kind=B.SCHED_WAVEFRONT),
+    "auto": dict(k=1 << 16, L=50.0, alpha0=1.0, schedule_kind=B.SCHED_AUTO),
 }
 
 

@@ -104,3 +104,20 @@ def test_empty_matrix():
     assert B.check_csr(m) == 0
     core, sup, S = B.schedule(m)
     assert S == 0
+
+
+def test_auto_schedule_avoids_serial_grid_and_stays_valid():
+    grid = gen.stencil_2d5(60)
+    _, _, S_gl = B.schedule(grid, B.gpu_opts())
+    core, sup, S = B.schedule(grid, B.gpu_opts(schedule_kind=B.SCHED_AUTO))
+    _, nl = oracle.levels(grid)
+    assert S_gl == 1 and S == nl                      # wavefront chosen for the one-source grid
+    assert oracle.validate(grid, int(core.max()) + 1, core, sup, S) == oracle.VALID
+    for m in cases():
+        core, sup, S = B.schedule(m, B.gpu_opts(schedule_kind=B.SCHED_AUTO))
+        k = int(core.max()) + 1 if m.n else 1
+        assert oracle.validate(m, k, core, sup, S) == oracle.VALID, m.name
+        g = B.schedule(m, B.gpu_opts())
+        w = B.schedule(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT))
+        assert (np.array_equal(core, g[0]) and np.array_equal(sup, g[1])) or \
+               (np.array_equal(core, w[0]) and np.array_equal(sup, w[1]))
