@@ -267,9 +267,10 @@ std::vector<int32_t> schedule_order(int64_t n, const int32_t *core, const int32_
     return out;
 }
 
-Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm)
+PackLayout pack_layout(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm)
 {
-    Packed pk;
+    PackLayout lay;
+    Packed &pk = lay.pk;
     pk.S = sch.S;
     const int64_t n = A.n;
     // tasks = maximal runs of equal (superstep, core) in the order
@@ -319,42 +320,58 @@ Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int3
         pk.chunk_base[c] = slots;
         slots += int64_t(kLanes) * pk.chunk_len[c];
     }
-    pk.word.assign(slots, kPadWord);
-    pk.value.assign(slots, 0.0);
-    // position of every row inside its task (the order of Sec. 5)
-    std::vector<int32_t> pos(n);
-    for (int64_t j = 0; j < T; j++)
-        for (int64_t t = task_begin[j]; t < task_begin[j + 1]; t++) pos[perm[t]] = int32_t(t - task_begin[j]);
+    pk.slots = slots;
+    lay.pos_slot.assign(n, 0);
+    lay.pos_task0.assign(n, 0);
     for (int64_t c = 0; c < C; c++) {
         for (int l = 0; l < kLanes; l++) {
             const int64_t task = lane_task[c * kLanes + l];
             if (task < 0) continue;
-            int64_t t = 0;
-            const int32_t s = sch.superstep[perm[task_begin[task]]];
-            const int32_t p = sch.core[perm[task_begin[task]]];
-            for (int64_t r = task_begin[task]; r < task_begin[task + 1]; r++) {
-                const int32_t row = perm[r];
-                const int64_t lo = A.row_ptr[row], hi = A.row_ptr[row + 1] - 1;
-                int64_t at = pk.chunk_base[c] + int64_t(kLanes) * t + l;
-                pk.word[at] = kHdrBit | uint32_t(row);
-                pk.value[at] = A.val ? A.val[hi] : 1.0;
-                t++;
-                for (int64_t e = lo; e < hi; e++) {
-                    const int32_t col = A.col[e];
-                    uint32_t w = uint32_t(col);
-                    if (sch.superstep[col] == s && sch.core[col] == p) {
-                        const int32_t back = pos[row] - pos[col];
-                        if (back < kRing) w = kIntBit | uint32_t(back);
-                    }
-                    at = pk.chunk_base[c] + int64_t(kLanes) * t + l;
-                    pk.word[at] = w;
-                    pk.value[at] = A.val ? A.val[e] : 0.0;
-                    t++;
-                }
+            for (int64_t t = task_begin[task]; t < task_begin[task + 1]; t++) {
+                lay.pos_slot[t] = pk.chunk_base[c] + l;
+                lay.pos_task0[t] = int32_t(task_begin[task]);
             }
         }
     }
-    return pk;
+    return lay;
+}
+
+void pack_fill(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm, PackLayout &lay)
+{
+    Packed &pk = lay.pk;
+    const int64_t n = A.n;
+    pk.word.assign(pk.slots, kPadWord);
+    pk.value.assign(pk.slots, 0.0);
+    std::vector<int32_t> inv(n);
+    for (int64_t t = 0; t < n; t++) inv[perm[t]] = int32_t(t);
+    int64_t off = 0;   // entries of the current task before position t
+    for (int64_t t = 0; t < n; t++) {
+        if (t == lay.pos_task0[t]) off = 0;
+        const int32_t row = perm[t];
+        const int64_t lo = A.row_ptr[row], hi = A.row_ptr[row + 1] - 1;
+        const int64_t base = lay.pos_slot[t];
+        pk.word[base + int64_t(kLanes) * off] = kHdrBit | uint32_t(row);
+        pk.value[base + int64_t(kLanes) * off] = A.val ? A.val[hi] : 1.0;
+        for (int64_t e = lo; e < hi; e++) {
+            const int32_t col = A.col[e];
+            uint32_t w = uint32_t(col);
+            if (sch.superstep[col] == sch.superstep[row] && sch.core[col] == sch.core[row]) {
+                const int64_t back = t - inv[col];   // rows back inside the task
+                if (back < kRing) w = kIntBit | uint32_t(back);
+            }
+            const int64_t at = base + int64_t(kLanes) * (off + 1 + (e - lo));
+            pk.word[at] = w;
+            pk.value[at] = A.val ? A.val[e] : 0.0;
+        }
+        off += hi - lo + 1;
+    }
+}
+
+Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm)
+{
+    PackLayout lay = pack_layout(A, sch, perm);
+    pack_fill(A, sch, perm, lay);
+    return std::move(lay.pk);
 }
 
 double predict_cost_us(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm, const CostModel &cm)

@@ -72,8 +72,23 @@ struct Packed {
     std::vector<double> value;          // [slots]
     int64_t tasks = 0;
     int64_t max_task_rows = 0;
+    int64_t slots = 0;
 };
 
+// Layout part of the packing (O(n + tasks)): tasks, their chunk and lane,
+// chunk lengths and bases, and for every position t of the order the stream
+// slot of its lane (chunk base + lane) and the first position of its task.
+struct PackLayout {
+    Packed pk;                         // everything but word/value
+    std::vector<int64_t> pos_slot;     // [n]
+    std::vector<int32_t> pos_task0;    // [n]
+};
+PackLayout pack_layout(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm);
+
+// Fills word/value of `pk` (already sized) on the host, O(nnz).
+void pack_fill(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm, PackLayout &lay);
+
+// Layout + host fill.
 Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm);
 
 // Predicted device time of one solve under `sch`, in microseconds: per
