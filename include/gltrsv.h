@@ -98,6 +98,12 @@ typedef struct gltrsv_plan_opts {
                                an occupancy-sized grid (lower launch cost; a
                                workgroup kept from starting by other work on
                                the device ends the solve with ETIMEDOUT)     */
+    int32_t analysis_threads; /* host threads of the GrowLocal analysis: the
+                               iterations of one superstep (Algorithm 3.1)
+                               start from the same state and run
+                               concurrently; 0 = automatic (1 below 2e5 rows,
+                               else up to 8).  The schedule does not depend
+                               on it.                                        */
 } gltrsv_plan_opts;
 
 /* Fills the paper's parameters: k = 22 (the core count of the main

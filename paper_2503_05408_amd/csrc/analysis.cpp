@@ -4,6 +4,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
+#include <mutex>
+#include <thread>
 #include <cstring>
 #include <functional>
 #include <numeric>
@@ -79,18 +82,21 @@ Schedule schedule_wavefront(const CsrView &A)
 // ---------------------------------------------------------------------------
 namespace {
 
+// The iterations of one superstep (alpha, growth * alpha, ...) all start from
+// the same barrier state, so they are independent: a pool of workers runs
+// several of them at once, each with private trial state, and the acceptance
+// rule then reads their results in order.  The outcome does not depend on the
+// number of workers.
 class GrowLocalScheduler {
 public:
-    GrowLocalScheduler(const CsrView &A, const SchedParams &p) : A_(A), p_(p)
+    GrowLocalScheduler(const CsrView &A, const SchedParams &p, int workers) : A_(A), p_(p)
     {
         const int64_t n = A.n;
         weight_.resize(n);
-        waiting_.resize(n);
         kids_begin_.assign(n + 1, 0);
         for (int64_t v = 0; v < n; v++) {
             const int64_t lo = A.row_ptr[v], hi = A.row_ptr[v + 1];
             weight_[v] = hi - lo;                 // stored entries, diagonal included
-            waiting_[v] = int32_t(hi - lo - 1);   // parents = stored off-diagonals
             for (int64_t e = lo; e < hi - 1; e++) kids_begin_[A.col[e] + 1]++;
         }
         std::partial_sum(kids_begin_.begin(), kids_begin_.end(), kids_begin_.begin());
@@ -98,11 +104,25 @@ public:
         std::vector<int64_t> pos(kids_begin_.begin(), kids_begin_.end() - 1);
         for (int64_t v = 0; v < n; v++)
             for (int64_t e = A.row_ptr[v]; e < A.row_ptr[v + 1] - 1; e++) kids_[pos[A.col[e]]++] = int32_t(v);
-        seen_.assign(n, 0);
-        tmp_wait_.resize(n);
-        tmp_owner_.resize(n);
+        work_.resize(size_t(std::max(1, workers)));
+        for (Worker &w : work_) {
+            w.tmp.resize(n);
+            for (int64_t v = 0; v < n; v++)   // parents = stored off-diagonals
+                w.tmp[v] = Tmp{0u, 0, 0, int32_t(A.row_ptr[v + 1] - A.row_ptr[v] - 1)};
+        }
         for (int64_t v = 0; v < n; v++)
-            if (waiting_[v] == 0) free_.push_back(int32_t(v));
+            if (work_[0].tmp[v].waiting == 0) free_.push_back(int32_t(v));
+        for (size_t i = 1; i < work_.size(); i++) threads_.emplace_back([this, i] { serve(i); });
+    }
+
+    ~GrowLocalScheduler()
+    {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            quit_ = true;
+        }
+        cv_go_.notify_all();
+        for (std::thread &t : threads_) t.join();
     }
 
     Schedule run()
@@ -112,25 +132,47 @@ public:
         out.superstep.assign(A_.n, -1);
         int64_t done = 0;
         int32_t s = 0;
-        std::vector<int32_t> picked_v, picked_p;
+        const int width = int(work_.size());
         while (done < A_.n) {
-            // grow alpha while the iterations stay worthy (Algorithm 3.1)
-            double alpha = p_.alpha0, best = 0.0, keep_alpha = p_.alpha0;
-            for (int it = 0;; it++) {
-                const Trial t = trial(alpha, nullptr, nullptr);
-                const bool worthy = (it == 0) || (t.beta >= p_.accept * best);
-                if (!worthy) break;
-                keep_alpha = alpha;
-                if (it == 0 || t.beta > best) best = t.beta;
-                if (t.first_core_count < int64_t(std::floor(alpha))) break;  // saturated
-                alpha = p_.growth * alpha;
+            // grow alpha while the iterations stay worthy (Algorithm 3.1),
+            // `width` iterations per round
+            double alpha = p_.alpha0, best = 0.0;
+            int it = 0;
+            bool stop = false;
+            while (!stop) {
+                for (int i = 0; i < width; i++) {
+                    work_[i].alpha = alpha;
+                    alpha = p_.growth * alpha;
+                }
+                run_jobs(kTrial);
+                int kept = -1;
+                for (int i = 0; i < width; i++, it++) {
+                    const Worker &w = work_[i];
+                    const bool worthy = (it == 0) || (w.beta >= p_.accept * best);
+                    if (!worthy) {
+                        stop = true;
+                        break;
+                    }
+                    kept = i;
+                    if (it == 0 || w.beta > best) best = w.beta;
+                    if (w.first_count < int64_t(std::floor(w.alpha))) {  // saturated
+                        stop = true;
+                        break;
+                    }
+                }
+                if (kept >= 0) {
+                    win_v_.swap(work_[kept].pv);
+                    win_p_.swap(work_[kept].pp);
+                }
             }
-            // replay the kept iteration and commit it as superstep s
-            picked_v.clear();
-            picked_p.clear();
-            trial(keep_alpha, &picked_v, &picked_p);
-            commit(picked_v, picked_p, s, out);
-            done += int64_t(picked_v.size());
+            for (size_t i = 0; i < win_v_.size(); i++) {
+                out.core[win_v_[i]] = win_p_[i];
+                out.superstep[win_v_[i]] = s;
+            }
+            out_ = &out;
+            run_jobs(kCommit);
+            merge_free(out);
+            done += int64_t(win_v_.size());
             s++;
         }
         out.S = s;
@@ -138,50 +180,64 @@ public:
     }
 
 private:
-    struct Trial {
-        double beta;
-        int64_t first_core_count;
+    struct Tmp {
+        uint32_t epoch;
+        int32_t wait, owner;  // unassigned parents left; core of the parents placed (-2: several)
+        int32_t waiting;      // unassigned parents at the barrier
     };
+    struct Worker {
+        std::vector<Tmp> tmp;         // trial fields valid where epoch matches
+        uint32_t epoch = 0;
+        std::vector<int32_t> excl;    // min-heap of vertices exclusive to the core
+        std::vector<int32_t> pv, pp;  // picks (vertex, core) of its iteration
+        double alpha = 0.0, beta = 0.0;
+        int64_t first_count = 0;
+    };
+    enum Job { kTrial, kCommit };
 
-    // One iteration from the barrier state; optionally records the picks.
-    Trial trial(double alpha, std::vector<int32_t> *pv, std::vector<int32_t> *pp)
+    // One iteration from the barrier state with w.alpha.
+    void trial(Worker &w)
     {
-        epoch_++;
-        const int64_t limit = int64_t(std::floor(alpha));
+        if (++w.epoch == 0) {  // wrapped: forget every stale mark
+            for (Tmp &m : w.tmp) m.epoch = 0;
+            w.epoch = 1;
+        }
+        w.pv.clear();
+        w.pp.clear();
+        const int64_t limit = int64_t(std::floor(w.alpha));
         size_t next_free = 0;
         int64_t w_first = 0, total = 0, heaviest = 0, first_count = 0;
         for (int32_t core = 0; core < p_.k; core++) {
-            excl_.clear();
+            w.excl.clear();
             int64_t count = 0, load = 0;
             while (core == 0 ? count < limit : load < w_first) {
                 int32_t v;
-                if (!excl_.empty()) {
-                    std::pop_heap(excl_.begin(), excl_.end(), std::greater<int32_t>());
-                    v = excl_.back();
-                    excl_.pop_back();
+                if (!w.excl.empty()) {
+                    std::pop_heap(w.excl.begin(), w.excl.end(), std::greater<int32_t>());
+                    v = w.excl.back();
+                    w.excl.pop_back();
                 } else if (next_free < free_.size()) {
                     v = free_[next_free++];
                 } else {
                     break;
                 }
-                if (pv) {
-                    pv->push_back(v);
-                    pp->push_back(core);
-                }
+                w.pv.push_back(v);
+                w.pp.push_back(core);
                 count++;
                 load += weight_[v];
                 for (int64_t e = kids_begin_[v]; e < kids_begin_[v + 1]; e++) {
                     const int32_t u = kids_[e];
-                    if (seen_[u] != epoch_) {
-                        seen_[u] = epoch_;
-                        tmp_wait_[u] = waiting_[u];
-                        tmp_owner_[u] = core;   // first parent placed in this superstep
-                    } else if (tmp_owner_[u] != core) {
-                        tmp_owner_[u] = -2;     // parents on two or more cores
+                    Tmp &m = w.tmp[u];
+                    if (m.epoch != w.epoch) {
+                        m.epoch = w.epoch;
+                        m.wait = m.waiting;
+                        m.owner = core;         // first parent placed in this superstep
+                    } else if (m.owner != core) {
+                        m.owner = -2;           // parents on two or more cores
                     }
-                    if (--tmp_wait_[u] == 0 && tmp_owner_[u] == core) {
-                        excl_.push_back(u);
-                        std::push_heap(excl_.begin(), excl_.end(), std::greater<int32_t>());
+                    if (--m.wait == 0 && m.owner == core) {
+                        w.excl.push_back(u);
+                        std::push_heap(w.excl.begin(), w.excl.end(), std::greater<int32_t>());
                     }
                 }
             }
@@ -193,24 +249,26 @@ private:
             heaviest = std::max(heaviest, load);
             if (next_free >= free_.size()) break;  // nothing left for later cores
         }
-        Trial t;
-        t.beta = double(total) / (double(heaviest) + p_.L);
-        t.first_core_count = first_count;
-        return t;
+        w.beta = double(total) / (double(heaviest) + p_.L);
+        w.first_count = first_count;
     }
 
-    void commit(const std::vector<int32_t> &pv, const std::vector<int32_t> &pp, int32_t s, Schedule &out)
+    // The committed superstep's vertices release their children: every
+    // worker updates its own barrier counts; worker 0 collects the children
+    // that became free.
+    void commit(size_t i)
     {
-        for (size_t i = 0; i < pv.size(); i++) {
-            out.core[pv[i]] = pp[i];
-            out.superstep[pv[i]] = s;
-        }
-        fresh_.clear();
-        for (int32_t v : pv)
+        Worker &w = work_[i];
+        if (i == 0) fresh_.clear();
+        for (int32_t v : win_v_)
             for (int64_t e = kids_begin_[v]; e < kids_begin_[v + 1]; e++) {
                 const int32_t u = kids_[e];
-                if (--waiting_[u] == 0 && out.superstep[u] < 0) fresh_.push_back(u);
+                if (--w.tmp[u].waiting == 0 && i == 0 && out_->superstep[u] < 0) fresh_.push_back(u);
             }
+    }
+
+    void merge_free(const Schedule &out)
+    {
         std::sort(fresh_.begin(), fresh_.end());
         merged_.clear();
         merged_.reserve(free_.size() + fresh_.size());
@@ -224,26 +282,82 @@ private:
         free_.swap(merged_);
     }
 
+    void do_job(size_t i)
+    {
+        if (job_ == kTrial) trial(work_[i]);
+        else commit(i);
+    }
+
+    // Runs the job on every worker (worker 0 on the calling thread).
+    void run_jobs(Job j)
+    {
+        if (threads_.empty()) {
+            job_ = j;
+            do_job(0);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            job_ = j;
+            pending_ = int(threads_.size());
+            gen_++;
+        }
+        cv_go_.notify_all();
+        do_job(0);
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_done_.wait(lk, [&] { return pending_ == 0; });
+    }
+
+    void serve(size_t i)
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_go_.wait(lk, [&] { return quit_ || gen_ != seen; });
+                if (quit_) return;
+                seen = gen_;
+            }
+            do_job(i);
+            std::lock_guard<std::mutex> g(mu_);
+            if (--pending_ == 0) cv_done_.notify_one();
+        }
+    }
+
     const CsrView &A_;
     SchedParams p_;
     std::vector<int64_t> weight_;
-    std::vector<int32_t> waiting_;     // unassigned parents at the barrier
     std::vector<int64_t> kids_begin_;
     std::vector<int32_t> kids_;
     std::vector<int32_t> free_;        // free at the barrier, rising IDs
     std::vector<int32_t> fresh_, merged_;
-    std::vector<int32_t> excl_;        // min-heap of vertices exclusive to the core
-    std::vector<uint64_t> seen_;
-    uint64_t epoch_ = 0;
-    std::vector<int32_t> tmp_wait_, tmp_owner_;
+    std::vector<int32_t> win_v_, win_p_;  // picks of the kept iteration
+    std::vector<Worker> work_;
+    const Schedule *out_ = nullptr;
+    std::vector<std::thread> threads_;
+    std::mutex mu_;
+    std::condition_variable cv_go_, cv_done_;
+    Job job_ = kTrial;
+    uint64_t gen_ = 0;
+    int pending_ = 0;
+    bool quit_ = false;
 };
 
 }  // namespace
 
+int growlocal_workers(int64_t n, int32_t requested)
+{
+    if (requested > 0) return requested;
+    if (n < 200000) return 1;
+    const int hw = int(std::max(1u, std::thread::hardware_concurrency()));
+    const int64_t by_mem = std::max<int64_t>(1, (int64_t(4) << 30) / (16 * n));  // trial state <= 4 GiB
+    return int(std::min<int64_t>({8, hw, by_mem}));
+}
+
 Schedule schedule_growlocal(const CsrView &A, const SchedParams &p)
 {
     if (A.n == 0) return Schedule{};
-    GrowLocalScheduler g(A, p);
+    GrowLocalScheduler g(A, p, growlocal_workers(A.n, p.threads));
     return g.run();
 }
 

@@ -40,6 +40,7 @@ struct SchedParams {
     int32_t k = 22;
     double L = 500.0, alpha0 = 20.0, growth = 1.5, accept = 0.97;
     int32_t kind = 0;  // 0 GrowLocal, 1 wavefront
+    int32_t threads = 0;  // GrowLocal workers, 0 = automatic
 };
 
 struct Schedule {
@@ -55,6 +56,8 @@ int32_t wavefront_levels(const CsrView &A, std::vector<int32_t> &level);
 
 Schedule schedule_wavefront(const CsrView &A);
 Schedule schedule_growlocal(const CsrView &A, const SchedParams &p);
+// Workers GrowLocal uses for n rows when `requested` (0 = automatic) is given.
+int growlocal_workers(int64_t n, int32_t requested);
 
 // perm[t] = row at position t in (superstep, core, index) order.
 std::vector<int32_t> schedule_order(int64_t n, const int32_t *core, const int32_t *superstep, int32_t S);

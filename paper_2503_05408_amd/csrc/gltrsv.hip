@@ -571,6 +571,8 @@ int check_opts(const gltrsv_plan_opts *o)
     if (o->block_size != 0 && o->block_size != dev::kBlock)
         return set_error(GLTRSV_ENOTSUP, "block_size must be 0 or 256 in this build");
     if (o->grid_blocks < 0) return set_error(GLTRSV_EINVAL, "grid_blocks must be >= 0");
+    if (o->analysis_threads < 0 || o->analysis_threads > 64)
+        return set_error(GLTRSV_EINVAL, "analysis_threads must be in 0..64");
     return GLTRSV_OK;
 }
 
@@ -583,6 +585,7 @@ SchedParams params_of(const gltrsv_plan_opts *o)
     p.growth = o->growth;
     p.accept = o->accept;
     p.kind = o->schedule_kind;
+    p.threads = o->analysis_threads;
     return p;
 }
 
@@ -677,6 +680,7 @@ void gltrsv_default_opts(gltrsv_plan_opts *o)
     o->block_size = 0;
     o->grid_blocks = 0;
     o->cooperative = 0;
+    o->analysis_threads = 0;
 }
 
 int gltrsv_check_csr(const gltrsv_csr *A)

@@ -56,7 +56,8 @@ def test_check_csr_codes(case, code):
 
 def test_bad_options_rejected():
     m = gen.fig_1_1()
-    for bad in (dict(k=0), dict(alpha0=0.5), dict(growth=1.0), dict(L=-1.0), dict(schedule_kind=7)):
+    for bad in (dict(k=0), dict(alpha0=0.5), dict(growth=1.0), dict(L=-1.0), dict(schedule_kind=7),
+                dict(analysis_threads=-1)):
         with pytest.raises(B.GltrsvError):
             B.schedule(m, B.default_opts(**bad))
 
@@ -82,6 +83,18 @@ def test_growlocal_equals_oracle(pidx):
         core, sup, S = B.schedule(m, o)
         pi, sg, S2 = oracle.growlocal(m, o.k, L=o.L, alpha0=o.alpha0, growth=o.growth, theta=o.accept)
         assert S == S2 and np.array_equal(core, pi) and np.array_equal(sup, sg), m.name
+
+
+@pytest.mark.parametrize("threads", [2, 3, 8])
+def test_growlocal_workers_do_not_change_the_schedule(threads):
+    # the iterations of a superstep run on several host threads; the
+    # acceptance rule reads them in order, so the schedule is the oracle's
+    for p in (PARAMS[0], PARAMS[3], PARAMS[4], PARAMS[5]):
+        for m in cases()[:8] + [gen.random_lower(3000, 0.003, 77)]:
+            o = B.default_opts(analysis_threads=threads, **p)
+            core, sup, S = B.schedule(m, o)
+            pi, sg, S2 = oracle.growlocal(m, o.k, L=o.L, alpha0=o.alpha0, growth=o.growth, theta=o.accept)
+            assert S == S2 and np.array_equal(core, pi) and np.array_equal(sup, sg), (m.name, threads)
 
 
 def test_levels_wavefront_and_order_equal_oracle():
