@@ -82,6 +82,20 @@ Schedule schedule_wavefront(const CsrView &A)
 // ---------------------------------------------------------------------------
 namespace {
 
+// Runs f(lo, hi) over `threads` contiguous slices of [0, n).
+template <class F>
+void parallel_rows(int threads, int64_t n, F f)
+{
+    if (threads <= 1 || n < 4096) {
+        f(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> t;
+    for (int i = 1; i < threads; i++) t.emplace_back([=] { f(n * i / threads, n * (i + 1) / threads); });
+    f(int64_t(0), n / threads);
+    for (std::thread &x : t) x.join();
+}
+
 // The iterations of one superstep (alpha, growth * alpha, ...) all start from
 // the same barrier state, so they are independent: a pool of workers runs
 // several of them at once, each with private trial state, and the acceptance
@@ -92,26 +106,41 @@ public:
     GrowLocalScheduler(const CsrView &A, const SchedParams &p, int workers) : A_(A), p_(p)
     {
         const int64_t n = A.n;
+        const int nw = std::max(1, workers);
         weight_.resize(n);
+        waiting_.resize(n);
+        parallel_rows(nw, n, [&](int64_t lo, int64_t hi) {
+            for (int64_t v = lo; v < hi; v++) {
+                const int64_t d = A.row_ptr[v + 1] - A.row_ptr[v];
+                weight_[v] = d;                  // stored entries, diagonal included
+                waiting_[v] = int32_t(d - 1);    // parents = stored off-diagonals
+            }
+        });
+        // children lists (the transpose of the strict lower part), children
+        // in rising order; worker i owns the parents in its slice of [0, n)
+        // and scans every row, so no two workers write the same counter
         kids_begin_.assign(n + 1, 0);
-        for (int64_t v = 0; v < n; v++) {
-            const int64_t lo = A.row_ptr[v], hi = A.row_ptr[v + 1];
-            weight_[v] = hi - lo;                 // stored entries, diagonal included
-            for (int64_t e = lo; e < hi - 1; e++) kids_begin_[A.col[e] + 1]++;
-        }
+        parallel_rows(nw, n, [&](int64_t lo, int64_t hi) {
+            for (int64_t v = lo + 1; v < n; v++)
+                for (int64_t e = A.row_ptr[v]; e < A.row_ptr[v + 1] - 1; e++) {
+                    const int32_t c = A.col[e];
+                    if (c >= lo && c < hi) kids_begin_[c + 1]++;
+                }
+        });
         std::partial_sum(kids_begin_.begin(), kids_begin_.end(), kids_begin_.begin());
         kids_.resize(kids_begin_[n]);
-        std::vector<int64_t> pos(kids_begin_.begin(), kids_begin_.end() - 1);
+        parallel_rows(nw, n, [&](int64_t lo, int64_t hi) {
+            std::vector<int64_t> pos(kids_begin_.begin() + lo, kids_begin_.begin() + hi);
+            for (int64_t v = lo + 1; v < n; v++)
+                for (int64_t e = A.row_ptr[v]; e < A.row_ptr[v + 1] - 1; e++) {
+                    const int32_t c = A.col[e];
+                    if (c >= lo && c < hi) kids_[pos[c - lo]++] = int32_t(v);
+                }
+        });
+        work_.resize(size_t(nw));
+        for (Worker &w : work_) w.tmp.assign(n, Tmp{0u, 0, 0});
         for (int64_t v = 0; v < n; v++)
-            for (int64_t e = A.row_ptr[v]; e < A.row_ptr[v + 1] - 1; e++) kids_[pos[A.col[e]]++] = int32_t(v);
-        work_.resize(size_t(std::max(1, workers)));
-        for (Worker &w : work_) {
-            w.tmp.resize(n);
-            for (int64_t v = 0; v < n; v++)   // parents = stored off-diagonals
-                w.tmp[v] = Tmp{0u, 0, 0, int32_t(A.row_ptr[v + 1] - A.row_ptr[v] - 1)};
-        }
-        for (int64_t v = 0; v < n; v++)
-            if (work_[0].tmp[v].waiting == 0) free_.push_back(int32_t(v));
+            if (waiting_[v] == 0) free_.push_back(int32_t(v));
         for (size_t i = 1; i < work_.size(); i++) threads_.emplace_back([this, i] { serve(i); });
     }
 
@@ -183,13 +212,13 @@ private:
     struct Tmp {
         uint32_t epoch;
         int32_t wait, owner;  // unassigned parents left; core of the parents placed (-2: several)
-        int32_t waiting;      // unassigned parents at the barrier
     };
     struct Worker {
         std::vector<Tmp> tmp;         // trial fields valid where epoch matches
         uint32_t epoch = 0;
         std::vector<int32_t> excl;    // min-heap of vertices exclusive to the core
         std::vector<int32_t> pv, pp;  // picks (vertex, core) of its iteration
+        std::vector<int32_t> fresh;   // children freed by its part of a commit
         double alpha = 0.0, beta = 0.0;
         int64_t first_count = 0;
     };
@@ -230,7 +259,7 @@ private:
                     Tmp &m = w.tmp[u];
                     if (m.epoch != w.epoch) {
                         m.epoch = w.epoch;
-                        m.wait = m.waiting;
+                        m.wait = waiting_[u];
                         m.owner = core;         // first parent placed in this superstep
                     } else if (m.owner != core) {
                         m.owner = -2;           // parents on two or more cores
@@ -253,22 +282,28 @@ private:
         w.first_count = first_count;
     }
 
-    // The committed superstep's vertices release their children: every
-    // worker updates its own barrier counts; worker 0 collects the children
-    // that became free.
+    // The committed superstep's vertices release their children; worker i
+    // takes every nw-th slice of them and collects the children that became
+    // free.
     void commit(size_t i)
     {
-        Worker &w = work_[i];
-        if (i == 0) fresh_.clear();
-        for (int32_t v : win_v_)
+        const size_t nw = work_.size(), m = win_v_.size();
+        std::vector<int32_t> &fresh = work_[i].fresh;
+        fresh.clear();
+        for (size_t q = i * m / nw; q < (i + 1) * m / nw; q++) {
+            const int32_t v = win_v_[q];
             for (int64_t e = kids_begin_[v]; e < kids_begin_[v + 1]; e++) {
                 const int32_t u = kids_[e];
-                if (--w.tmp[u].waiting == 0 && i == 0 && out_->superstep[u] < 0) fresh_.push_back(u);
+                const int32_t left = nw > 1 ? __atomic_sub_fetch(&waiting_[u], 1, __ATOMIC_RELAXED) : --waiting_[u];
+                if (left == 0 && out_->superstep[u] < 0) fresh.push_back(u);
             }
+        }
     }
 
     void merge_free(const Schedule &out)
     {
+        fresh_.clear();
+        for (const Worker &w : work_) fresh_.insert(fresh_.end(), w.fresh.begin(), w.fresh.end());
         std::sort(fresh_.begin(), fresh_.end());
         merged_.clear();
         merged_.reserve(free_.size() + fresh_.size());
@@ -327,6 +362,7 @@ private:
     const CsrView &A_;
     SchedParams p_;
     std::vector<int64_t> weight_;
+    std::vector<int32_t> waiting_;     // unassigned parents at the barrier
     std::vector<int64_t> kids_begin_;
     std::vector<int32_t> kids_;
     std::vector<int32_t> free_;        // free at the barrier, rising IDs
