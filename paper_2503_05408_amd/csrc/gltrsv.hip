@@ -402,14 +402,40 @@ __global__ __launch_bounds__(kBlock) void trsv_persistent(
 // ---------------------------------------------------------------------------
 
 
+__device__ __forceinline__ unsigned long long *state_word(unsigned long long *state, int32_t i)
+{
+    return state + int64_t(i) * kStateStride;
+}
+
+// One claim of up to per_claim chunks of system i: valid iff the claimed
+// index lies inside the superstep the word held at that moment (it may have
+// advanced since it was read).
+__device__ __forceinline__ int32_t try_claim(const SysDesc *__restrict__ sys, unsigned long long *state, int32_t i,
+                                             int32_t per_claim, int32_t *gs_out, int32_t *c0, int32_t *c1)
+{
+    const unsigned long long got = __hip_atomic_fetch_add(state_word(state, i), (unsigned long long)per_claim,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t gs = int32_t(got >> 32);
+    const int64_t gc = int64_t(got & 0xffffffffull);
+    if (gs >= sys[i].S) return 0;
+    const int32_t *sc = sys[i].super_chunk;
+    const int32_t n2 = sc[gs + 1] - sc[gs];
+    if (gc >= n2) return 0;
+    *gs_out = gs;
+    *c0 = sc[gs] + int32_t(gc);
+    *c1 = sc[gs] + int32_t(min<int64_t>(gc + per_claim, n2));
+    return 1;
+}
+
 __global__ __launch_bounds__(kBlock) void batch_reset(unsigned long long *state, uint32_t *done, int32_t count,
                                                       int32_t ndone, uint32_t *finished, int32_t *err)
 {
     const int32_t i = int32_t(blockIdx.x) * kBlock + int32_t(threadIdx.x);
-    if (i < count) state[i] = 0ull;
+    if (i < count) *state_word(state, i) = 0ull;
     for (int32_t j = i; j < ndone; j += int32_t(gridDim.x) * kBlock) done[j] = 0u;
     if (i == 0) {
-        *finished = 0u;
+        finished[0] = 0u;
+        finished[1] = 0u;
         *err = 0;
     }
 }
@@ -422,72 +448,87 @@ __global__ __launch_bounds__(kBlock) void batch_reset(unsigned long long *state,
 __global__ __launch_bounds__(kBlock) void trsv_batched(const SysDesc *__restrict__ sys, int32_t count,
                                                        unsigned long long *state, uint32_t *done,
                                                        uint32_t *finished, int32_t *err, int64_t spin_limit,
-                                                       int32_t per_claim, int32_t target, int64_t quantum)
+                                                       int32_t per_claim, int32_t target, int64_t quantum,
+                                                       int32_t keep_waves)
 {
     __shared__ double ring[kRing + 1][kBlock];
+    __shared__ uint32_t done_mask[kMaskSystems / 32];   // systems seen finished
+    for (int q = threadIdx.x; q < kMaskSystems / 32; q += kBlock) done_mask[q] = 0u;
+    __syncthreads();
+    const int32_t total_waves = int32_t(gridDim.x) * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
     const int32_t wave = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
     int32_t home = count > 0 ? wave % count : 0;
     int64_t idle_since = -1;   // wall-clock tick when this wave last found no work
     const int64_t deadline = quantum > 0 ? int64_t(wall_clock64()) + quantum : -1;
+    int32_t nap = 1;           // idle back-off, in units of s_sleep(2)
+    int32_t idle = 0;          // consecutive scans without work
+    bool may_retire = true;
     for (;;) {
-        int32_t found = -1, fs = 0, c0 = 0, c1 = 0, quit = 0;
+        // lane 0 walks the systems from `home` on and claims from the first
+        // one with an unclaimed chunk; `live` counts the unfinished ones seen
+        int32_t found = -1, fs = 0, c0 = 0, c1 = 0, live = 0;
+        const bool late = deadline >= 0 && int64_t(wall_clock64()) > deadline;
         if (lane == 0) {
-            const bool late = deadline >= 0 && int64_t(wall_clock64()) > deadline;
             for (int32_t t = 0; t < count && found < 0 && !late; t++) {
                 const int32_t i = home + t < count ? home + t : home + t - count;
-                const int32_t S = sys[i].S;
-                const unsigned long long st =
-                    __hip_atomic_load(state + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (i < kMaskSystems && (done_mask[i >> 5] >> (i & 31)) & 1u) continue;
+                const unsigned long long st = __hip_atomic_load(state_word(state, i), __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
                 const int32_t s = int32_t(st >> 32);
-                if (s >= S) continue;
-                const int32_t *sc = sys[i].super_chunk;
-                const int32_t nch = sc[s + 1] - sc[s];
-                if (int64_t(st & 0xffffffffull) >= nch) continue;
-                const unsigned long long got = __hip_atomic_fetch_add(state + i, (unsigned long long)per_claim,
-                                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int32_t gs = int32_t(got >> 32);
-                const int64_t gc = int64_t(got & 0xffffffffull);
-                if (gs != s) {
-                    // the superstep advanced meanwhile: a valid claim of gs if in range
-                    if (gs >= S) continue;
-                    const int32_t n2 = sc[gs + 1] - sc[gs];
-                    if (gc >= n2) continue;
-                    found = i;
-                    fs = gs;
-                    c0 = sc[gs] + int32_t(gc);
-                    c1 = sc[gs] + int32_t(min<int64_t>(gc + per_claim, n2));
-                } else if (gc < nch) {
-                    found = i;
-                    fs = s;
-                    c0 = sc[s] + int32_t(gc);
-                    c1 = sc[s] + int32_t(min<int64_t>(gc + per_claim, nch));
+                if (s >= sys[i].S) {
+                    if (i < kMaskSystems) atomicOr(&done_mask[i >> 5], 1u << (i & 31));
+                    continue;
                 }
-            }
-            if (found < 0) {
-                if (late ||
-                    __hip_atomic_load(finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= uint32_t(target) ||
-                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-                    quit = 1;
+                live++;
+                const int32_t *sc = sys[i].super_chunk;
+                if (int64_t(st & 0xffffffffull) >= int64_t(sc[s + 1] - sc[s])) continue;
+                if (try_claim(sys, state, i, per_claim, &fs, &c0, &c1)) found = i;
             }
         }
         found = __shfl(found, 0);
-        quit = __shfl(quit, 0);
-        if (quit) return;
         if (found < 0) {
+            int32_t quit = 0;
+            idle++;
             if (lane == 0) {
-                __builtin_amdgcn_s_sleep(2);
-                const int64_t now = int64_t(wall_clock64());
-                if (idle_since < 0) idle_since = now;
-                else if (now - idle_since > spin_limit)
-                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // every system finished (a full scan saw none open), the
+                // quantum is over, or (checked now and then) the target is
+                // met or another wave failed
+                quit = late || live == 0;
+                if (!quit && (idle & 15) == 0)
+                    quit = __hip_atomic_load(finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= uint32_t(target) ||
+                           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
             }
+            if (lane == 0 && !quit) {
+                for (int32_t k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(2);
+                nap = min(2 * nap, int32_t(kIdleNapMax));
+                const int64_t now = int64_t(wall_clock64());
+                if (idle_since < 0) {
+                    idle_since = now;
+                } else if (now - idle_since > spin_limit) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else if (may_retire && now - idle_since > kRetireTicks) {
+                    // retire unless that would leave keep_waves or fewer; a
+                    // wave refused once stays for the rest of the launch
+                    const uint32_t r = __hip_atomic_fetch_add(finished + 1, 1u, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                    if (int64_t(total_waves) - int64_t(r) - 1 >= int64_t(keep_waves)) {
+                        quit = 1;
+                    } else {
+                        __hip_atomic_fetch_sub(finished + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        may_retire = false;
+                    }
+                }
+            }
+            if (__shfl(quit, 0)) return;
             continue;
         }
-        idle_since = -1;
         fs = __shfl(fs, 0);
         c0 = __shfl(c0, 0);
         c1 = __shfl(c1, 0);
+        idle = 0;
+        nap = 1;
+        idle_since = -1;
         home = found;
         const SysDesc d = sys[found];
         for (int32_t c = c0; c < c1; c++) {
@@ -504,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void trsv_batched(const SysDesc *__restrict
             const uint32_t old = __hip_atomic_fetch_add(done + d.done_off + fs, uint32_t(c1 - c0),
                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (int64_t(old) + (c1 - c0) == nch) {
-                __hip_atomic_exchange(state + found, (unsigned long long)(fs + 1) << 32, __ATOMIC_RELAXED,
+                __hip_atomic_exchange(state_word(state, found), (unsigned long long)(fs + 1) << 32, __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
                 if (fs + 1 == d.S)
                     __hip_atomic_fetch_add(finished, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -658,6 +699,7 @@ struct gltrsv_batch {
     hipStream_t graph_stream = nullptr;
     hipStream_t last_stream = nullptr;
     int64_t idle_ticks = 1000000000;   // 10 s of the 100 MHz wall clock
+    int32_t keep_waves = 0;            // waves that never retire (see dev::kRetireTicks)
 };
 
 extern "C" {
@@ -815,6 +857,7 @@ int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv
     int64_t widest = 0;
     for (int32_t q = 0; q < p->S; q++)
         widest = std::max<int64_t>(widest, p->super_chunk_host[q + 1] - p->super_chunk_host[q]);
+    p->widest = widest;
     const int64_t useful = (widest + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
     grid = int(std::max<int64_t>(1, std::min<int64_t>(grid, useful)));
     p->grid = grid;
@@ -1016,9 +1059,10 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
     bt->count = int32_t(bt->plans.size());
     const size_t ndesc = std::max<size_t>(1, bt->plans.size());
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&bt->d_desc), ndesc * sizeof(dev::SysDesc));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_state), ndesc * sizeof(unsigned long long));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&bt->d_state), ndesc * dev::kStateStride * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_done), std::max(1, bt->ndone) * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_finished), sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_finished), 2 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_err), sizeof(int32_t));
     for (int k = 0; k < 2 && e == hipSuccess; k++) {
         e = hipHostMalloc(reinterpret_cast<void **>(&bt->h_desc[k]), ndesc * sizeof(dev::SysDesc), hipHostMallocDefault);
@@ -1060,6 +1104,7 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
     if (opts->grid_blocks > 0) grid = std::min(grid, opts->grid_blocks);
     grid = int(std::max<int64_t>(1, std::min<int64_t>(grid, (chunks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
     bt->grid = grid;
+    bt->keep_waves = dev::keep_waves_for(widest_of(bt->plans), bt->per_claim, grid);
     *out = bt;
     return GLTRSV_OK;
 }
@@ -1071,7 +1116,7 @@ static int batch_enqueue(gltrsv_batch *bt, hipStream_t st)
                        bt->d_err);
     hipLaunchKernelGGL(dev::trsv_batched, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st, bt->d_desc, bt->count,
                        bt->d_state, bt->d_done, bt->d_finished, bt->d_err, bt->idle_ticks, bt->per_claim, bt->count,
-                       int64_t(0));
+                       int64_t(0), bt->keep_waves);
     HIP_TRY(hipGetLastError());
     return GLTRSV_OK;
 }

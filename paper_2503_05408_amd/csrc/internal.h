@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/gltrsv.h"
@@ -18,6 +19,37 @@ namespace dev {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
+
+// Batched launches: the state word of system i sits at state[i * kStateStride]
+// (one per 256 bytes, so waves polling different systems do not queue on
+// one line); an idle wave sleeps 1, 2, 4, ... up to kIdleNapMax short naps
+// between scans.
+#ifndef GLTRSV_STATE_STRIDE
+#define GLTRSV_STATE_STRIDE 32
+#endif
+#ifndef GLTRSV_IDLE_NAP_MAX
+#define GLTRSV_IDLE_NAP_MAX 64
+#endif
+constexpr int kStateStride = GLTRSV_STATE_STRIDE;
+constexpr int kIdleNapMax = GLTRSV_IDLE_NAP_MAX;
+// A wave idle for kRetireTicks of the 100 MHz wall clock leaves the launch
+// while more than keep_waves waves remain, so a long tail of narrow
+// supersteps is not slowed by thousands of pollers.  The first kMaskSystems
+// systems have a bit in a per-workgroup mask once seen finished, so scans
+// skip them.
+#ifndef GLTRSV_RETIRE_TICKS
+#define GLTRSV_RETIRE_TICKS 2000
+#endif
+constexpr int64_t kRetireTicks = GLTRSV_RETIRE_TICKS;
+constexpr int kMaskSystems = 1024;
+
+// Waves kept by a batched launch: enough for the widest superstep of any of
+// its systems, at least 256, at most the whole grid.
+inline int32_t keep_waves_for(int64_t widest_chunks, int32_t per_claim, int grid)
+{
+    const int64_t w = std::max<int64_t>(256, (widest_chunks + per_claim - 1) / std::max(1, per_claim));
+    return int32_t(std::min<int64_t>(w, int64_t(grid) * kWavesPerBlock));
+}
 
 // One system of a batched launch: its plan's device arrays, its vectors, its
 // superstep count and the index of its first per-superstep done counter.
@@ -35,9 +67,10 @@ struct SysDesc {
 
 __global__ void batch_reset(unsigned long long *state, uint32_t *done, int32_t count, int32_t ndone,
                             uint32_t *finished, int32_t *err);
+// finished[0] = systems completed in the launch, finished[1] = waves retired
 __global__ void trsv_batched(const SysDesc *__restrict__ sys, int32_t count, unsigned long long *state,
                              uint32_t *done, uint32_t *finished, int32_t *err, int64_t spin_limit, int32_t per_claim,
-                             int32_t target, int64_t quantum);
+                             int32_t target, int64_t quantum, int32_t keep_waves);
 
 }  // namespace dev
 }  // namespace gltrsv
@@ -58,6 +91,7 @@ struct gltrsv_plan {
     uint64_t key = 0;
     int device = 0;
     int grid = 0;
+    int64_t widest = 0;             // chunks of the widest superstep
     std::vector<int32_t> core, superstep, perm, super_chunk_host;
     uint32_t *d_word = nullptr;
     double *d_value = nullptr;
@@ -68,8 +102,15 @@ struct gltrsv_plan {
     int32_t *d_err = nullptr;
     int64_t *d_trace = nullptr;  // per-superstep timestamps (trace builds only)
     hipStream_t last_stream = nullptr;
-    int64_t spin_limit = 5000000;
+    int64_t spin_limit = 5000000;   // barrier polls before ETIMEDOUT, about 5 s
     int32_t schedule_kind = 0;      // the schedule actually built
-    double predicted_us = 0.0;      // cost-model prediction of one solve   // about 5 s of polling
+    double predicted_us = 0.0;      // cost-model prediction of one solve
     int cooperative = 0;
 };
+
+inline int64_t widest_of(const std::vector<gltrsv_plan *> &plans)
+{
+    int64_t w = 0;
+    for (const gltrsv_plan *p : plans) w = std::max(w, p->widest);
+    return w;
+}

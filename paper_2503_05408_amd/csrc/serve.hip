@@ -139,17 +139,22 @@ int run_quantum(gltrsv_server *sv, int32_t used, int32_t busy)
         sl.fresh = false;
         HIP_TRY(hipMemcpyAsync(sv->d_desc + i, sv->h_desc + i, sizeof(dev::SysDesc), hipMemcpyHostToDevice,
                                sv->stream));
-        HIP_TRY(hipMemsetAsync(sv->d_state + i, 0, sizeof(unsigned long long), sv->stream));
+        HIP_TRY(hipMemsetAsync(sv->d_state + size_t(i) * dev::kStateStride, 0, sizeof(unsigned long long),
+                               sv->stream));
         HIP_TRY(hipMemsetAsync(sv->d_done + sl.done_off, 0, sizeof(uint32_t) * size_t(sl.req.plan->S), sv->stream));
     }
-    HIP_TRY(hipMemsetAsync(sv->d_finished, 0, sizeof(uint32_t), sv->stream));
+    HIP_TRY(hipMemsetAsync(sv->d_finished, 0, 2 * sizeof(uint32_t), sv->stream));
+    int64_t widest = 0;
+    for (int32_t i = 0; i < used; i++)
+        if (sv->slots[i].busy) widest = std::max(widest, sv->slots[i].req.plan->widest);
     const int64_t quantum = int64_t(sv->opts.quantum_us * 100.0);   // 100 MHz wall clock
     hipLaunchKernelGGL(dev::trsv_batched, dim3(unsigned(sv->grid)), dim3(dev::kBlock), 0, sv->stream, sv->d_desc, used,
                        sv->d_state, sv->d_done, sv->d_finished, sv->d_err, int64_t(1000000000), sv->opts.per_claim,
-                       busy, std::max<int64_t>(quantum, 1));
+                       busy, std::max<int64_t>(quantum, 1), dev::keep_waves_for(widest, sv->opts.per_claim, sv->grid));
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(sv->h_state, sv->d_state, sizeof(unsigned long long) * size_t(used), hipMemcpyDeviceToHost,
-                           sv->stream));
+    HIP_TRY(hipMemcpy2DAsync(sv->h_state, sizeof(unsigned long long), sv->d_state,
+                             sizeof(unsigned long long) * dev::kStateStride, sizeof(unsigned long long), size_t(used),
+                             hipMemcpyDeviceToHost, sv->stream));
     int32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, sv->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, sv->stream));
     HIP_TRY(hipStreamSynchronize(sv->stream));
@@ -277,14 +282,17 @@ int gltrsv_server_create(const gltrsv_server_opts *opts, gltrsv_server **out)
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
     const size_t ns = size_t(opts->max_slots);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_desc), ns * sizeof(dev::SysDesc));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_state), ns * sizeof(unsigned long long));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&sv->d_state), ns * dev::kStateStride * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_done), size_t(opts->counter_words) * 4);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_finished), sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_finished), 2 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sv->d_err), sizeof(int32_t));
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_desc), ns * sizeof(dev::SysDesc), 0);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_state), ns * sizeof(unsigned long long), 0);
     if (e == hipSuccess) e = hipMemset(sv->d_err, 0, sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(sv->d_desc, 0, ns * sizeof(dev::SysDesc));
+    // unused slots read as finished: S = 0 and superstep 0
+    if (e == hipSuccess) e = hipMemset(sv->d_state, 0, ns * dev::kStateStride * sizeof(unsigned long long));
     int per_cu = 0, cus = 0;
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dev::trsv_batched, dev::kBlock, 0);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, sv->device);
