@@ -195,6 +195,21 @@ def main():
     torch.cuda.synchronize()
     ms_plain = p0.elapsed_time(p1) / args.plain_steps
 
+    # the same bytes without the dependencies: one gather-probe pass over the plan
+    ones = torch.ones_like(x)
+    ysink = torch.zeros_like(x)
+    plan.gather_probe(ones, ysink)
+    torch.cuda.synchronize()
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for _ in range(5):
+        plan.gather_probe(ones, ysink)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    gather_ms = g0.elapsed_time(g1) / 5
+    del ones, ysink
+
     # achievable copy bandwidth (read + write of 1 GiB) with the library's copy kernel
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
@@ -246,6 +261,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "trsv_persistent", "alg_bytes_per_launch": alg, "kernel_ms": kern_ms,
             "copy_probe_GBs": copy_gbs,
+            "gather_floor_ms": gather_ms,
+            "frac_of_gather_floor": gather_ms / kern_ms if kern_ms > 0 else None,
             "traffic_GBs": (traffic / (kern_ms * 1e-3) / 1e9) if traffic else None,
         },
     }

@@ -287,6 +287,18 @@ int gltrsv_server_destroy(gltrsv_server *server);
  * calibration kernel for memory-traffic counters. */
 int gltrsv_copy_probe(const void *src, void *dst, int64_t bytes, void *stream);
 
+/* The solve's memory traffic with its dependencies taken out: streams the
+ * plan's packed entries once and gathers x (device, n values, original
+ * numbering) at every column one solve reads from memory, with no barrier
+ * and no row waiting for another; a measured floor for gltrsv_solve on the
+ * same plan.  Writes y[i] (device, n values) = the running sum in stored
+ * order of A_ij * x_j over the off-diagonals of row i, where 1.0 stands in
+ * for x_j at the entries the solve keeps on chip (columns among the last
+ * 16 rows of the same (superstep, core) task); with x = ones, y[i] is
+ * exactly the left-to-right sum of row i's off-diagonals.  Rows without
+ * off-diagonals get 0.  Asynchronous on `stream`. */
+int gltrsv_plan_gather_probe(gltrsv_plan *plan, const double *x, double *y, void *stream);
+
 /* Diagnostics of builds compiled with GLTRSV_TRACE (otherwise returns
  * GLTRSV_ENOTSUP): copies up to `count` int64 wall-clock stamps of the last
  * persistent solve, laid out [superstep][workgroup][3] = start of work, end

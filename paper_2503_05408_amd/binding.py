@@ -92,6 +92,7 @@ SIGNATURES = {
     "gltrsv_plan_device_status": ([P, P], i32),
     "gltrsv_debug_trace": ([P, P, i64], i32),
     "gltrsv_copy_probe": ([P, P, i64, P], i32),
+    "gltrsv_plan_gather_probe": ([P, P, P, P], i32),
     "gltrsv_default_batch_opts": ([P], None),
     "gltrsv_batch_create": ([P, i32, P, P], i32),
     "gltrsv_batch_solve": ([P, P, P, P], i32),
@@ -294,6 +295,17 @@ class Plan:
         _check(load().gltrsv_solve_plain(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
                "gltrsv_solve_plain")
         return x
+
+    def gather_probe(self, x, y=None, stream=None):
+        """The solve's traffic without its dependencies (diagnostic):
+        y[i] = running sum of A_ij * x_j over row i's off-diagonals, 1.0 in
+        place of x_j for the entries the solve keeps on chip."""
+        import torch
+        if y is None:
+            y = torch.zeros_like(x)
+        _check(load().gltrsv_plan_gather_probe(self._p, _dev_ptr(x, self.n), _dev_ptr(y, self.n), _stream_ptr(stream)),
+               "gltrsv_plan_gather_probe")
+        return y
 
     def debug_trace(self):
         """[S, grid, 3] wall-clock stamps of the last persistent solve (trace

@@ -554,6 +554,52 @@ __global__ __launch_bounds__(kBlock) void trsv_batched(const SysDesc *__restrict
     }
 }
 
+// The solve's memory traffic without its dependencies: one wave per chunk
+// streams the chunk's words and values and gathers x at every column the
+// solve reads from memory; a header closes the previous row with y[row] =
+// the running sum, in stored order, of value * x (1.0 stands in for x at
+// entries the solve takes from its on-chip ring).  No barrier, no division,
+// no row waits for another: the floor one solve's bytes can reach.
+__global__ __launch_bounds__(kBlock) void gather_probe(const uint32_t *__restrict__ word,
+                                                       const double *__restrict__ value,
+                                                       const int64_t *__restrict__ chunk_base,
+                                                       const int32_t *__restrict__ chunk_len, int64_t chunks,
+                                                       const double *__restrict__ x, double *__restrict__ y)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t c = int64_t(blockIdx.x) * kWavesPerBlock + int64_t(threadIdx.x >> 6);
+    if (c >= chunks) return;
+    const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
+    double acc = 0.0;
+    int32_t row = -1;
+    Batch now, nxt;
+    load_batch(cur, 0, now);
+    for (int32_t t0 = 0; t0 < cur.len; t0 += kUnroll) {
+        load_batch(cur, t0 + kUnroll, nxt);
+        double g[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) {
+            const uint32_t w = now.w[j];
+            const bool ext = (w & (HDR | INTL)) == 0;
+            const double gx = load_x(ext ? x + w : x);
+            g[j] = ext ? gx : 1.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) {
+            const uint32_t w = now.w[j];
+            if (w & HDR) {
+                if (row >= 0) y[row] = acc;
+                acc = 0.0;
+                row = w == PAD ? -1 : int32_t(w & MASK);
+            } else {
+                acc = acc + now.v[j] * g[j];
+            }
+        }
+        now = nxt;
+    }
+    if (row >= 0) y[row] = acc;
+}
+
 // Plain copy of 16-byte elements, grid-stride: the achievable-bandwidth
 // reference and the calibration kernel of the memory-traffic counters.
 __global__ __launch_bounds__(kBlock) void copy_probe(const double2 *__restrict__ src, double2 *__restrict__ dst,
@@ -967,6 +1013,19 @@ int gltrsv_copy_probe(const void *src, void *dst, int64_t bytes, void *stream)
     const int64_t blocks = std::min<int64_t>(int64_t(cus) * 8, (n16 + dev::kBlock - 1) / dev::kBlock);
     hipLaunchKernelGGL(dev::copy_probe, dim3(unsigned(blocks)), dim3(dev::kBlock), 0, static_cast<hipStream_t>(stream),
                        static_cast<const double2 *>(src), static_cast<double2 *>(dst), n16);
+    HIP_TRY(hipGetLastError());
+    return GLTRSV_OK;
+}
+
+int gltrsv_plan_gather_probe(gltrsv_plan *p, const double *x, double *y, void *stream)
+{
+    if (!p || (p->n && (!x || !y))) return set_error(GLTRSV_EINVAL, "null argument");
+    if (p->chunks == 0) return GLTRSV_OK;
+    HIP_TRY(hipSetDevice(p->device));
+    const int64_t blocks = (p->chunks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
+    hipLaunchKernelGGL(dev::gather_probe, dim3(unsigned(blocks)), dim3(dev::kBlock), 0,
+                       static_cast<hipStream_t>(stream), p->d_word, p->d_value, p->d_chunk_base, p->d_chunk_len,
+                       p->chunks, x, y);
     HIP_TRY(hipGetLastError());
     return GLTRSV_OK;
 }
