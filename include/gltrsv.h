@@ -78,6 +78,15 @@ int gltrsv_check_csr(const gltrsv_csr *A);
 #define GLTRSV_SCHED_WAVEFRONT 1   /* level sets: one superstep per wavefront */
 #define GLTRSV_SCHED_AUTO      2   /* both; keep the lower predicted time     */
 
+/* Stream filling (gltrsv_plan_opts.pack), Sec. 5 reorder plus packing:
+ *  AUTO   -- device for systems with at least 2^20 stored entries, else host;
+ *  HOST   -- one host pass over the entries;
+ *  DEVICE -- device kernels: row lengths, a wavefront prefix scan of them
+ *            staged through LDS, and the scatter of the entries. */
+#define GLTRSV_PACK_AUTO   0
+#define GLTRSV_PACK_HOST   1
+#define GLTRSV_PACK_DEVICE 2
+
 typedef struct gltrsv_plan_opts {
     int32_t k;              /* cores of the BSP schedule (Def. 2.1), >= 1     */
     double L;               /* barrier cost in weight units (Sec. 3, Eq. 3.1) */
@@ -104,6 +113,10 @@ typedef struct gltrsv_plan_opts {
                                concurrently; 0 = automatic (1 below 2e5 rows,
                                else up to 8).  The schedule does not depend
                                on it.                                        */
+    int32_t pack;             /* GLTRSV_PACK_*: where the packed stream is
+                               filled (the layout of tasks, chunks and lanes
+                               is always computed on the host); the stream is
+                               the same either way                           */
 } gltrsv_plan_opts;
 
 /* Fills the paper's parameters: k = 22 (the core count of the main
@@ -162,6 +175,7 @@ typedef struct gltrsv_plan_info {
                                superstep 3 us plus the larger of 0.18 us per
                                entry of its longest task and its entries at
                                4e4 entries/us                                */
+    int32_t device_packed;  /* 1 if the stream was filled on the device       */
 } gltrsv_plan_info;
 
 /* Analyses A (checks, schedule, Sec. 5 order) and uploads the packed matrix
@@ -298,6 +312,15 @@ int gltrsv_copy_probe(const void *src, void *dst, int64_t bytes, void *stream);
  * exactly the left-to-right sum of row i's off-diagonals.  Rows without
  * off-diagonals get 0.  Asynchronous on `stream`. */
 int gltrsv_plan_gather_probe(gltrsv_plan *plan, const double *x, double *y, void *stream);
+
+/* Copies the plan's packed stream to host memory: word[slots] (uint32)
+ * and value[slots] (double), slots = gltrsv_plan_info.stream_slots (any
+ * other count is EINVAL).  Entry t of lane l of chunk c is at
+ * chunk_base[c] + 64 t + l.  Word encoding: bit 31 set = row header (bits
+ * 0..29 = original row, value = the diagonal), 0xFFFFFFFF = padding, bit 30
+ * set = a column of the same task that many rows back (< 16), otherwise the
+ * column itself.  Synchronous. */
+int gltrsv_plan_stream(const gltrsv_plan *plan, uint32_t *word, double *value, int64_t slots);
 
 /* Diagnostics of builds compiled with GLTRSV_TRACE (otherwise returns
  * GLTRSV_ENOTSUP): copies up to `count` int64 wall-clock stamps of the last

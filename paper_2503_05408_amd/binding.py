@@ -29,6 +29,9 @@ ERRORS = {
 SCHED_GROWLOCAL = 0
 SCHED_WAVEFRONT = 1
 SCHED_AUTO = 2
+PACK_AUTO = 0
+PACK_HOST = 1
+PACK_DEVICE = 2
 
 
 class GltrsvError(RuntimeError):
@@ -44,7 +47,7 @@ class Csr(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("k", i32), ("L", dbl), ("alpha0", dbl), ("growth", dbl), ("accept", dbl),
                 ("schedule_kind", i32), ("reorder", i32), ("block_size", i32), ("grid_blocks", i32),
-                ("cooperative", i32), ("analysis_threads", i32)]
+                ("cooperative", i32), ("analysis_threads", i32), ("pack", i32)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -68,7 +71,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n", i64), ("nnz", i64), ("supersteps", i32), ("wavefronts", i32), ("tasks", i64),
                 ("chunks", i64), ("stream_slots", i64), ("device_bytes", i64), ("analysis_ns", i64),
                 ("pattern_key", u64), ("grid_blocks", i32), ("block_size", i32), ("max_task_rows", i64),
-                ("schedule_kind", i32), ("predicted_us", dbl)]
+                ("schedule_kind", i32), ("predicted_us", dbl), ("device_packed", i32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -93,6 +96,7 @@ SIGNATURES = {
     "gltrsv_debug_trace": ([P, P, i64], i32),
     "gltrsv_copy_probe": ([P, P, i64, P], i32),
     "gltrsv_plan_gather_probe": ([P, P, P, P], i32),
+    "gltrsv_plan_stream": ([P, P, P, i64], i32),
     "gltrsv_default_batch_opts": ([P], None),
     "gltrsv_batch_create": ([P, i32, P, P], i32),
     "gltrsv_batch_solve": ([P, P, P, P], i32),
@@ -295,6 +299,14 @@ class Plan:
         _check(load().gltrsv_solve_plain(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
                "gltrsv_solve_plain")
         return x
+
+    def stream(self):
+        """The packed stream as (word uint32[slots], value float64[slots])."""
+        slots = self.info()["stream_slots"]
+        w = np.empty(slots, dtype=np.uint32)
+        v = np.empty(slots, dtype=np.float64)
+        _check(load().gltrsv_plan_stream(self._p, _np_ptr(w), _np_ptr(v), slots), "gltrsv_plan_stream")
+        return w, v
 
     def gather_probe(self, x, y=None, stream=None):
         """The solve's traffic without its dependencies (diagnostic):

@@ -660,6 +660,8 @@ int check_opts(const gltrsv_plan_opts *o)
     if (o->grid_blocks < 0) return set_error(GLTRSV_EINVAL, "grid_blocks must be >= 0");
     if (o->analysis_threads < 0 || o->analysis_threads > 64)
         return set_error(GLTRSV_EINVAL, "analysis_threads must be in 0..64");
+    if (o->pack != GLTRSV_PACK_AUTO && o->pack != GLTRSV_PACK_HOST && o->pack != GLTRSV_PACK_DEVICE)
+        return set_error(GLTRSV_EINVAL, "unknown pack mode");
     return GLTRSV_OK;
 }
 
@@ -769,6 +771,7 @@ void gltrsv_default_opts(gltrsv_plan_opts *o)
     o->grid_blocks = 0;
     o->cooperative = 0;
     o->analysis_threads = 0;
+    o->pack = GLTRSV_PACK_AUTO;
 }
 
 int gltrsv_check_csr(const gltrsv_csr *A)
@@ -859,21 +862,42 @@ int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv
     Schedule s = build_schedule(V, opts, &p->perm, &p->predicted_us, &p->schedule_kind);
     std::vector<int32_t> lv;
     p->wavefronts = wavefront_levels(V, lv);
-    Packed pk = pack_stream(V, s, p->perm);
+    const bool on_device =
+        opts->pack == GLTRSV_PACK_DEVICE || (opts->pack == GLTRSV_PACK_AUTO && V.nnz >= (int64_t(1) << 20));
+    PackLayout lay = pack_layout(V, s, p->perm);
+    if (!on_device) pack_fill(V, s, p->perm, lay);
+    Packed &pk = lay.pk;
     p->S = s.S;
     p->core = std::move(s.core);
     p->superstep = std::move(s.superstep);
     p->tasks = pk.tasks;
     p->chunks = int64_t(pk.chunk_len.size());
-    p->slots = int64_t(pk.word.size());
+    p->slots = pk.slots;
     p->max_task_rows = pk.max_task_rows;
     p->super_chunk_host = pk.super_chunk;
     p->key = pattern_key(V);
 
     HIP_TRY(hipGetDevice(&p->device));
     int64_t bytes = 0;
-    if ((rc = upload(&p->d_word, pk.word, &bytes)) || (rc = upload(&p->d_value, pk.value, &bytes)) ||
-        (rc = upload(&p->d_chunk_base, pk.chunk_base, &bytes)) || (rc = upload(&p->d_chunk_len, pk.chunk_len, &bytes)) ||
+    if (on_device) {
+        const size_t ns = size_t(std::max<int64_t>(1, pk.slots));
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->d_word), ns * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&p->d_value), ns * sizeof(double));
+        if (e != hipSuccess) {
+            gltrsv_plan_destroy(p);
+            return set_error(e == hipErrorOutOfMemory ? GLTRSV_ENOMEM : GLTRSV_EHIP, "stream allocation");
+        }
+        bytes += int64_t(ns) * 12;
+        if ((rc = dev::device_pack(V, p->perm, lay, p->d_word, p->d_value))) {
+            gltrsv_plan_destroy(p);
+            return rc;
+        }
+    } else if ((rc = upload(&p->d_word, pk.word, &bytes)) || (rc = upload(&p->d_value, pk.value, &bytes))) {
+        gltrsv_plan_destroy(p);
+        return rc;
+    }
+    p->device_packed = on_device;
+    if ((rc = upload(&p->d_chunk_base, pk.chunk_base, &bytes)) || (rc = upload(&p->d_chunk_len, pk.chunk_len, &bytes)) ||
         (rc = upload(&p->d_super_chunk, pk.super_chunk, &bytes))) {
         gltrsv_plan_destroy(p);
         return rc;
@@ -941,6 +965,7 @@ int gltrsv_plan_info_get(const gltrsv_plan *p, gltrsv_plan_info *o)
     o->max_task_rows = p->max_task_rows;
     o->schedule_kind = p->schedule_kind;
     o->predicted_us = p->predicted_us;
+    o->device_packed = p->device_packed ? 1 : 0;
     return GLTRSV_OK;
 }
 
@@ -1014,6 +1039,17 @@ int gltrsv_copy_probe(const void *src, void *dst, int64_t bytes, void *stream)
     hipLaunchKernelGGL(dev::copy_probe, dim3(unsigned(blocks)), dim3(dev::kBlock), 0, static_cast<hipStream_t>(stream),
                        static_cast<const double2 *>(src), static_cast<double2 *>(dst), n16);
     HIP_TRY(hipGetLastError());
+    return GLTRSV_OK;
+}
+
+int gltrsv_plan_stream(const gltrsv_plan *p, uint32_t *word, double *value, int64_t slots)
+{
+    if (!p || (p->slots && (!word || !value))) return set_error(GLTRSV_EINVAL, "null argument");
+    if (slots != p->slots) return set_error(GLTRSV_EINVAL, "slots must equal the plan's stream_slots");
+    if (slots == 0) return GLTRSV_OK;
+    HIP_TRY(hipSetDevice(p->device));
+    HIP_TRY(hipMemcpy(word, p->d_word, sizeof(uint32_t) * size_t(slots), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(value, p->d_value, sizeof(double) * size_t(slots), hipMemcpyDeviceToHost));
     return GLTRSV_OK;
 }
 

@@ -67,6 +67,11 @@ struct SysDesc {
 
 __global__ void batch_reset(unsigned long long *state, uint32_t *done, int32_t count, int32_t ndone,
                             uint32_t *finished, int32_t *err);
+// Fills the plan's stream (d_word, d_value: lay.pk.slots entries) on the
+// device from A, the schedule order and the host layout; synchronous.
+int device_pack(const CsrView &A, const std::vector<int32_t> &perm, const PackLayout &lay, uint32_t *d_word,
+                double *d_value);
+
 // finished[0] = systems completed in the launch, finished[1] = waves retired
 __global__ void trsv_batched(const SysDesc *__restrict__ sys, int32_t count, unsigned long long *state,
                              uint32_t *done, uint32_t *finished, int32_t *err, int64_t spin_limit, int32_t per_claim,
@@ -105,6 +110,7 @@ struct gltrsv_plan {
     int64_t spin_limit = 5000000;   // barrier polls before ETIMEDOUT, about 5 s
     int32_t schedule_kind = 0;      // the schedule actually built
     double predicted_us = 0.0;      // cost-model prediction of one solve
+    bool device_packed = false;     // stream filled by the packing kernels
     int cooperative = 0;
 };
 
