@@ -14,6 +14,7 @@ Each function cites the passage of the paper (arxiv 2503.05408) it follows:
 * :func:`validate`   -- Definition 2.1.
 * :func:`growlocal`  -- Algorithm 3.1 (Sec. 3, Eq. (3.1); acceptance factor
   0.97 from the proof of Theorem 3.1 in Appendix B).
+* :func:`growlocal_blocks` -- block-parallel scheduling (Sec. 3.1).
 * :func:`reorder`    -- Sec. 5.
 * :func:`bsp_solve`  -- the schedule executed superstep by superstep with
   strict visibility (Sec. 2.3).
@@ -73,6 +74,8 @@ def _load():
             lib.oracle_validate.argtypes = [i64, P, P, i32, P, P, i32]
             lib.oracle_growlocal.argtypes = [i64, P, P, i32, dbl, dbl, dbl, dbl, P, P, P,
                                              i64, P, P, P, P, P]
+            lib.oracle_growlocal_weighted.argtypes = [i64, P, P, P, i32, dbl, dbl, dbl, dbl, P, P, P,
+                                                      i64, P, P, P, P, P]
             lib.oracle_reorder.argtypes = [i64, P, P, P, P, P, P, P, P, P]
             lib.oracle_bsp_solve.argtypes = [i64, P, P, P, P, P, P, P, P]
             _lib = lib
@@ -162,6 +165,54 @@ def growlocal(m, k, L=PAPER_L, alpha0=PAPER_ALPHA0, growth=PAPER_GROWTH, theta=P
         tr = [(int(ts[i]), float(ta[i]), float(tb[i]), bool(tw[i])) for i in range(cnt)]
         return pi, sigma, S.value, tr
     return pi, sigma, S.value
+
+
+def block_bounds(n: int, nblocks: int) -> list[int]:
+    """Row bounds of the diagonal blocks: block b holds rows
+    [floor(b n / B), floor((b+1) n / B)) (equal row counts; the paper does not
+    say how the blocks are sized)."""
+    return [(b * n) // nblocks for b in range(nblocks + 1)]
+
+
+def growlocal_blocks(m, k, nblocks, L=PAPER_L, alpha0=PAPER_ALPHA0, growth=PAPER_GROWTH,
+                     theta=PAPER_THETA):
+    """Block-parallel GrowLocal (Sec. 3.1): the matrix is cut along the
+    diagonal into ``nblocks`` lower-triangular blocks; each block is scheduled
+    by Algorithm 3.1 as a DAG of its own (the edges from earlier blocks are
+    dropped: those parents all finish in earlier supersteps) with the vertex
+    weights of the full rows; the schedules are placed one after the other by
+    adding to each block's superstep numbers the supersteps of all earlier
+    blocks.  Returns (pi, sigma, S)."""
+    rp, c, _ = _csr(m)
+    pi = np.empty(m.n, dtype=np.int32)
+    sigma = np.empty(m.n, dtype=np.int32)
+    offset = 0
+    bounds = block_bounds(m.n, nblocks)
+    for lo, hi in zip(bounds[:-1], bounds[1:]):
+        if hi == lo:
+            continue
+        nb = hi - lo
+        lens = rp[lo + 1:hi + 1] - rp[lo:hi]
+        seg = np.repeat(np.arange(nb), lens)
+        cols = c[rp[lo]:rp[hi]]
+        keep = cols >= lo
+        sub_rp = np.zeros(nb + 1, dtype=np.int64)
+        np.cumsum(np.bincount(seg[keep], minlength=nb), out=sub_rp[1:])
+        sub_col = np.ascontiguousarray(cols[keep] - lo, dtype=np.int32)
+        weight = np.ascontiguousarray(lens, dtype=np.int64)
+        pb = np.empty(nb, dtype=np.int32)
+        sb = np.empty(nb, dtype=np.int32)
+        S = ctypes.c_int32(0)
+        nt = ctypes.c_int64(0)
+        rc = _load().oracle_growlocal_weighted(nb, _p(sub_rp), _p(sub_col), _p(weight), int(k), float(L),
+                                               float(alpha0), float(growth), float(theta), _p(pb), _p(sb),
+                                               ctypes.byref(S), 0, None, None, None, None, ctypes.byref(nt))
+        if rc:
+            raise OracleError(f"oracle_growlocal_weighted: {rc}")
+        pi[lo:hi] = pb
+        sigma[lo:hi] = sb + offset
+        offset += S.value
+    return pi, sigma, offset
 
 
 def wavefront_schedule(m):

@@ -11,6 +11,8 @@
  *   oracle_levels       wavefronts (level sets) of the DAG, Sec. 1 / Sec. 6.2
  *   oracle_validate     validity of a BSP schedule, Definition 2.1
  *   oracle_growlocal    the GrowLocal scheduler, Algorithm 3.1 and Sec. 3
+ *   oracle_growlocal_weighted  the same with given vertex weights (used by
+ *                       the block-parallel scheduling of Sec. 3.1)
  *   oracle_reorder      schedule-based symmetric permutation, Sec. 5
  *   oracle_bsp_solve    executes a schedule superstep by superstep with strict
  *                       visibility (a value computed on another core is
@@ -272,12 +274,15 @@ static int64_t gl_iteration(gl_state *st, double alpha, double L, int32_t *av, i
 
 /* GrowLocal.  Outputs pi (core, 0..k-1) and sigma (superstep, 0..S-1).
  * Optional trace of every iteration: superstep, alpha, beta, worthy flag,
- * up to max_trace entries; *ntrace receives the total count. */
-int oracle_growlocal(int64_t n, const int64_t *row_ptr, const int32_t *col,
-                     int32_t k, double L, double alpha0, double growth, double theta,
-                     int32_t *pi, int32_t *sigma, int32_t *S_out,
-                     int64_t max_trace, int32_t *tr_s, double *tr_alpha, double *tr_beta,
-                     int8_t *tr_worthy, int64_t *ntrace)
+ * up to max_trace entries; *ntrace receives the total count.
+ * weight: vertex weights, or NULL for the stored entries of each row.  The
+ * block-parallel form of Sec. 3.1 schedules a diagonal block as its own DAG
+ * but keeps the weights of the full matrix's rows. */
+int oracle_growlocal_weighted(int64_t n, const int64_t *row_ptr, const int32_t *col, const int64_t *weight,
+                              int32_t k, double L, double alpha0, double growth, double theta,
+                              int32_t *pi, int32_t *sigma, int32_t *S_out,
+                              int64_t max_trace, int32_t *tr_s, double *tr_alpha, double *tr_beta,
+                              int8_t *tr_worthy, int64_t *ntrace)
 {
     int rc = oracle_check_csr(n, row_ptr, col, NULL);
     if (rc) return rc;
@@ -304,7 +309,7 @@ int oracle_growlocal(int64_t n, const int64_t *row_ptr, const int32_t *col,
         !core_it || !heap || !av || !ap || !bv || !bp) { rc = OR_ENOMEM; goto done; }
 
     for (int64_t v = 0; v < n; v++) {
-        w[v] = row_ptr[v + 1] - row_ptr[v];
+        w[v] = weight ? weight[v] : row_ptr[v + 1] - row_ptr[v];
         rem[v] = (int32_t)(row_ptr[v + 1] - row_ptr[v] - 1);
         for (int64_t p = row_ptr[v]; p < row_ptr[v + 1] - 1; p++) cptr[col[p] + 1]++;
     }
@@ -372,6 +377,16 @@ done:
     free(w); free(cptr); free(rem); free(child); free(fill); free(F); free(F2); free(assigned);
     free(stamp); free(rem_it); free(core_it); free(heap); free(av); free(ap); free(bv); free(bp);
     return rc;
+}
+
+int oracle_growlocal(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                     int32_t k, double L, double alpha0, double growth, double theta,
+                     int32_t *pi, int32_t *sigma, int32_t *S_out,
+                     int64_t max_trace, int32_t *tr_s, double *tr_alpha, double *tr_beta,
+                     int8_t *tr_worthy, int64_t *ntrace)
+{
+    return oracle_growlocal_weighted(n, row_ptr, col, NULL, k, L, alpha0, growth, theta, pi, sigma, S_out,
+                                     max_trace, tr_s, tr_alpha, tr_beta, tr_worthy, ntrace);
 }
 
 /* ------------------------------------------------------------------------ */

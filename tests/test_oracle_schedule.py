@@ -311,3 +311,79 @@ def test_reorder_properties():
         x = oracle.solve(m, b)
         # the permuted system gives the same values, row by row
         assert oracle.same_bits(oracle.solve(pm, b[perm]), x[perm])
+
+
+# ---------------------------------------------------------------------------
+# block-parallel scheduling, Sec. 3.1
+# ---------------------------------------------------------------------------
+
+def test_blocks_one_block_is_plain_growlocal():
+    for m in (gen.random_lower(400, 0.02, 5), gen.fig_3_1(), gen.chain(50)):
+        for k in (1, 3, 22):
+            a = oracle.growlocal(m, k)
+            b = oracle.growlocal_blocks(m, k, 1)
+            assert a[2] == b[2] and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def _direct_sum(parts):
+    """Block-diagonal matrix of the given lower-triangular pieces."""
+    rp, cols, vals, off = [0], [], [], 0
+    for m in parts:
+        for i in range(m.n):
+            for e in range(m.row_ptr[i], m.row_ptr[i + 1]):
+                cols.append(int(m.col[e]) + off)
+                vals.append(float(m.val[e]))
+            rp.append(len(cols))
+        off += m.n
+    return gen.CSR(off, np.array(rp, np.int64), np.array(cols, np.int32), np.array(vals))
+
+
+def test_blocks_of_a_direct_sum_are_the_pieces_scheduled_alone():
+    # with no edge between blocks, each block is the piece itself (same DAG,
+    # same weights), and the pieces' schedules follow one another
+    pieces = [gen.random_lower(120, 0.05, 31), gen.random_lower(120, 0.02, 32), gen.chain(120)]
+    m = _direct_sum(pieces)
+    for k, L in ((2, 0.0), (4, 10.0), (22, 500.0)):
+        pi, sg, S = oracle.growlocal_blocks(m, k, 3, L=L, alpha0=1.0)
+        off = 0
+        for b, piece in enumerate(pieces):
+            p2, s2, S2 = oracle.growlocal(piece, k, L=L, alpha0=1.0)
+            assert np.array_equal(pi[120 * b:120 * (b + 1)], p2)
+            assert np.array_equal(sg[120 * b:120 * (b + 1)], s2 + off)
+            off += S2
+        assert S == off
+
+
+def test_blocks_keep_the_weights_of_the_full_rows():
+    # n = 6 in two blocks; row 3 stores entries in columns 0, 1, 2 (outside
+    # its block) and 3, so its weight is 4 although its block DAG has no edge.
+    # k = 2, L = 0, alpha0 = 1, growth 1.5, theta 0.97, derived by hand:
+    # block 0 (rows 0-2, edgeless, weight 1): alpha 1 and 1.5 give
+    #   {0 -> core 0, 1 -> core 1}, beta 2; alpha 2.25 gives beta 3/2 < 0.97*2,
+    #   so superstep 0 = {0, 1}; superstep 1 = {2 -> core 0} (saturated).
+    # block 1 (rows 3-5): alpha 1 and 1.5: core 0 takes 3 (weight 4), core 1
+    #   takes 4 and 5 (weights 1, total 2 < 4), beta 6/4; alpha 2.25: core 0
+    #   takes 3 and 4 (weight 5), core 1 takes 5, beta 6/5 < 0.97 * 1.5, so the
+    #   whole block is superstep 2.  With the block's own row lengths (weight
+    #   1 for row 3) row 5 would wait for a second superstep.
+    m = gen.from_entries(6, [(4, 1), (4, 2), (4, 3)])   # 1-based (row, col)
+    pi, sg, S = oracle.growlocal_blocks(m, 2, 2, L=0.0, alpha0=1.0)
+    assert S == 3
+    assert list(sg) == [0, 0, 1, 2, 2, 2]
+    assert list(pi) == [0, 1, 0, 0, 1, 1]
+
+
+@pytest.mark.parametrize("nblocks", [2, 3, 7, 50])
+def test_block_schedules_are_valid_and_solve_exactly(nblocks):
+    for s in range(4):
+        m = gen.random_lower(300, 0.03, 60 + s, band=None if s % 2 else 12)
+        for k, L, a0 in ((3, 0.0, 1.0), (22, 500.0, 20.0), (1 << 16, 50.0, 1.0)):
+            pi, sg, S = oracle.growlocal_blocks(m, k, nblocks, L=L, alpha0=a0)
+            assert oracle.validate(m, k, pi, sg, S) == oracle.VALID
+            # every block's supersteps lie after those of the earlier blocks
+            bounds = oracle.block_bounds(m.n, nblocks)
+            for lo, mid, hi in zip(bounds[:-2], bounds[1:-1], bounds[2:]):
+                if lo < mid < hi:
+                    assert sg[lo:mid].max() < sg[mid:hi].min()
+            b = gen.rhs_uniform(m.n, s)
+            assert oracle.same_bits(oracle.bsp_solve(m, b, pi, sg), oracle.solve(m, b))
