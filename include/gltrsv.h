@@ -117,6 +117,15 @@ typedef struct gltrsv_plan_opts {
                                filled (the layout of tasks, chunks and lanes
                                is always computed on the host); the stream is
                                the same either way                           */
+    int32_t blocks;           /* block-parallel scheduling (Sec. 3.1) when > 1:
+                               the rows are cut into that many diagonal
+                               blocks of equal row count (block b = rows
+                               [floor(b n/B), floor((b+1) n/B))), each block
+                               is scheduled by GrowLocal as a DAG of its own
+                               (edges from earlier blocks dropped) with the
+                               weights of the full rows, on separate host
+                               threads, and block b's supersteps follow those
+                               of blocks 0..b-1; 0 or 1 = the whole matrix   */
 } gltrsv_plan_opts;
 
 /* Fills the paper's parameters: k = 22 (the core count of the main

@@ -3,6 +3,7 @@
 #include "analysis.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <condition_variable>
 #include <mutex>
@@ -103,7 +104,9 @@ void parallel_rows(int threads, int64_t n, F f)
 // number of workers.
 class GrowLocalScheduler {
 public:
-    GrowLocalScheduler(const CsrView &A, const SchedParams &p, int workers) : A_(A), p_(p)
+    // weight: vertex weights, or nullptr for the stored entries of each row
+    GrowLocalScheduler(const CsrView &A, const SchedParams &p, int workers, const int64_t *weight = nullptr)
+        : A_(A), p_(p)
     {
         const int64_t n = A.n;
         const int nw = std::max(1, workers);
@@ -112,8 +115,8 @@ public:
         parallel_rows(nw, n, [&](int64_t lo, int64_t hi) {
             for (int64_t v = lo; v < hi; v++) {
                 const int64_t d = A.row_ptr[v + 1] - A.row_ptr[v];
-                weight_[v] = d;                  // stored entries, diagonal included
-                waiting_[v] = int32_t(d - 1);    // parents = stored off-diagonals
+                weight_[v] = weight ? weight[v] : d;   // stored entries, diagonal included
+                waiting_[v] = int32_t(d - 1);         // parents = stored off-diagonals
             }
         });
         // children lists (the transpose of the strict lower part), children
@@ -390,9 +393,75 @@ int growlocal_workers(int64_t n, int32_t requested)
     return int(std::min<int64_t>({8, hw, by_mem}));
 }
 
+std::vector<int64_t> block_bounds(int64_t n, int32_t nblocks)
+{
+    std::vector<int64_t> b(size_t(nblocks) + 1);
+    for (int32_t i = 0; i <= nblocks; i++) b[size_t(i)] = (int64_t(i) * n) / nblocks;
+    return b;
+}
+
+namespace {
+
+// Block-parallel GrowLocal (Sec. 3.1): every diagonal block is its own DAG
+// (edges from earlier blocks dropped; those parents finish in earlier
+// supersteps) scheduled with the weights of the full rows, the blocks on
+// separate threads; superstep numbers are then offset block after block.
+Schedule schedule_growlocal_blocks(const CsrView &A, const SchedParams &p)
+{
+    const int64_t n = A.n;
+    const int32_t nb = p.blocks;
+    const std::vector<int64_t> bounds = block_bounds(n, nb);
+    std::vector<Schedule> part(static_cast<size_t>(nb));
+    std::atomic<int32_t> next{0};
+    auto worker = [&]() {
+        for (int32_t b; (b = next.fetch_add(1)) < nb;) {
+            const int64_t lo = bounds[size_t(b)], hi = bounds[size_t(b) + 1];
+            if (hi == lo) continue;
+            std::vector<int64_t> rp(size_t(hi - lo) + 1, 0), w(size_t(hi - lo));
+            std::vector<int32_t> col;
+            col.reserve(size_t(A.row_ptr[hi] - A.row_ptr[lo]));
+            for (int64_t i = lo; i < hi; i++) {
+                for (int64_t e = A.row_ptr[i]; e < A.row_ptr[i + 1]; e++)
+                    if (A.col[e] >= lo) col.push_back(int32_t(A.col[e] - lo));
+                rp[size_t(i - lo) + 1] = int64_t(col.size());
+                w[size_t(i - lo)] = A.row_ptr[i + 1] - A.row_ptr[i];
+            }
+            CsrView sub;
+            sub.n = hi - lo;
+            sub.nnz = int64_t(col.size());
+            sub.row_ptr = rp.data();
+            sub.col = col.data();
+            GrowLocalScheduler g(sub, p, 1, w.data());
+            part[size_t(b)] = g.run();
+        }
+    };
+    const int threads = std::max(1, std::min<int>(nb, growlocal_workers(n, p.threads)));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; t++) pool.emplace_back(worker);
+    worker();
+    for (std::thread &t : pool) t.join();
+    Schedule out;
+    out.core.resize(size_t(n));
+    out.superstep.resize(size_t(n));
+    int32_t offset = 0;
+    for (int32_t b = 0; b < nb; b++) {
+        const int64_t lo = bounds[size_t(b)], hi = bounds[size_t(b) + 1];
+        for (int64_t i = lo; i < hi; i++) {
+            out.core[size_t(i)] = part[size_t(b)].core[size_t(i - lo)];
+            out.superstep[size_t(i)] = part[size_t(b)].superstep[size_t(i - lo)] + offset;
+        }
+        offset += part[size_t(b)].S;
+    }
+    out.S = offset;
+    return out;
+}
+
+}  // namespace
+
 Schedule schedule_growlocal(const CsrView &A, const SchedParams &p)
 {
     if (A.n == 0) return Schedule{};
+    if (p.blocks > 1) return schedule_growlocal_blocks(A, p);
     GrowLocalScheduler g(A, p, growlocal_workers(A.n, p.threads));
     return g.run();
 }

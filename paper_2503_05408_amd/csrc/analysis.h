@@ -41,6 +41,7 @@ struct SchedParams {
     double L = 500.0, alpha0 = 20.0, growth = 1.5, accept = 0.97;
     int32_t kind = 0;  // 0 GrowLocal, 1 wavefront
     int32_t threads = 0;  // GrowLocal workers, 0 = automatic
+    int32_t blocks = 0;   // > 1: block-parallel scheduling over that many diagonal blocks
 };
 
 struct Schedule {
@@ -56,6 +57,9 @@ int32_t wavefront_levels(const CsrView &A, std::vector<int32_t> &level);
 
 Schedule schedule_wavefront(const CsrView &A);
 Schedule schedule_growlocal(const CsrView &A, const SchedParams &p);
+// Row bounds of the diagonal blocks of block-parallel scheduling (Sec. 3.1):
+// block b = rows [floor(b n / B), floor((b+1) n / B)).
+std::vector<int64_t> block_bounds(int64_t n, int32_t nblocks);
 // Workers GrowLocal uses for n rows when `requested` (0 = automatic) is given.
 int growlocal_workers(int64_t n, int32_t requested);
 

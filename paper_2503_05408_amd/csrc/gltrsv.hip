@@ -662,6 +662,7 @@ int check_opts(const gltrsv_plan_opts *o)
         return set_error(GLTRSV_EINVAL, "analysis_threads must be in 0..64");
     if (o->pack != GLTRSV_PACK_AUTO && o->pack != GLTRSV_PACK_HOST && o->pack != GLTRSV_PACK_DEVICE)
         return set_error(GLTRSV_EINVAL, "unknown pack mode");
+    if (o->blocks < 0) return set_error(GLTRSV_EINVAL, "blocks must be >= 0");
     return GLTRSV_OK;
 }
 
@@ -675,6 +676,7 @@ SchedParams params_of(const gltrsv_plan_opts *o)
     p.accept = o->accept;
     p.kind = o->schedule_kind;
     p.threads = o->analysis_threads;
+    p.blocks = o->blocks;
     return p;
 }
 
@@ -772,6 +774,7 @@ void gltrsv_default_opts(gltrsv_plan_opts *o)
     o->cooperative = 0;
     o->analysis_threads = 0;
     o->pack = GLTRSV_PACK_AUTO;
+    o->blocks = 0;
 }
 
 int gltrsv_check_csr(const gltrsv_csr *A)

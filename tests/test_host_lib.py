@@ -57,7 +57,7 @@ def test_check_csr_codes(case, code):
 def test_bad_options_rejected():
     m = gen.fig_1_1()
     for bad in (dict(k=0), dict(alpha0=0.5), dict(growth=1.0), dict(L=-1.0), dict(schedule_kind=7),
-                dict(analysis_threads=-1), dict(pack=9)):
+                dict(analysis_threads=-1), dict(pack=9), dict(blocks=-2)):
         with pytest.raises(B.GltrsvError):
             B.schedule(m, B.default_opts(**bad))
 
@@ -95,6 +95,26 @@ def test_growlocal_workers_do_not_change_the_schedule(threads):
             core, sup, S = B.schedule(m, o)
             pi, sg, S2 = oracle.growlocal(m, o.k, L=o.L, alpha0=o.alpha0, growth=o.growth, theta=o.accept)
             assert S == S2 and np.array_equal(core, pi) and np.array_equal(sup, sg), (m.name, threads)
+
+
+@pytest.mark.parametrize("nblocks", [2, 5, 16])
+def test_block_parallel_growlocal_equals_oracle(nblocks):
+    for p in (PARAMS[0], PARAMS[2], PARAMS[3]):
+        for m in cases()[:10]:
+            o = B.default_opts(blocks=nblocks, **p)
+            core, sup, S = B.schedule(m, o)
+            pi, sg, S2 = oracle.growlocal_blocks(m, o.k, nblocks, L=o.L, alpha0=o.alpha0, growth=o.growth,
+                                                 theta=o.accept)
+            assert S == S2 and np.array_equal(core, pi) and np.array_equal(sup, sg), (m.name, nblocks)
+
+
+def test_block_parallel_growlocal_threads_equal_oracle():
+    # 3e5 rows: the blocks are scheduled on several host threads
+    m = gen.erdos_renyi(300_000, 1e-5, gen.SEED_BASE + 9)
+    o = B.gpu_opts(blocks=8)
+    core, sup, S = B.schedule(m, o)
+    pi, sg, S2 = oracle.growlocal_blocks(m, o.k, 8, L=o.L, alpha0=o.alpha0, growth=o.growth, theta=o.accept)
+    assert S == S2 and np.array_equal(core, pi) and np.array_equal(sup, sg)
 
 
 def test_levels_wavefront_and_order_equal_oracle():
