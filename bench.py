@@ -104,15 +104,17 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="er1e7")
-    ap.add_argument("--schedule", default="growlocal", choices=["growlocal", "wavefront"])
+    ap.add_argument("--schedule", default="growlocal", choices=["growlocal", "wavefront", "auto"])
     ap.add_argument("--L", type=float, default=50.0)
     ap.add_argument("--alpha0", type=float, default=1.0)
     ap.add_argument("--k", type=int, default=1 << 16)
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"],
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "analysis"],
                     help="single: one n=1e7 system (the headline line); batch: 64 systems in one launch; "
-                         "serve: Poisson request stream against resident plans")
+                         "serve: Poisson request stream against resident plans; analysis: analysis time, "
+                         "supersteps and solve time against the number of scheduling blocks")
+    ap.add_argument("--blocks", default="1,2,4,8,16")
     ap.add_argument("--systems", type=int, default=64)
     ap.add_argument("--pool", type=int, default=256)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -127,6 +129,8 @@ def main():
         return bench_batch(args)
     if args.mode == "serve":
         return bench_serve(args)
+    if args.mode == "analysis":
+        return bench_analysis(args)
 
     import torch
     import oracle
@@ -135,7 +139,7 @@ def main():
     t = time.time()
     m, desc = workload(args.workload)
     log(f"workload {m.name}: n={m.n} nnz={m.nnz} generated in {time.time() - t:.1f} s")
-    kind = B.SCHED_WAVEFRONT if args.schedule == "wavefront" else B.SCHED_GROWLOCAL
+    kind = {"wavefront": B.SCHED_WAVEFRONT, "auto": B.SCHED_AUTO}.get(args.schedule, B.SCHED_GROWLOCAL)
     opts = B.default_opts(k=args.k, L=args.L, alpha0=args.alpha0, schedule_kind=kind)
     t = time.time()
     plan = B.Plan(m, opts)
@@ -195,6 +199,24 @@ def main():
     torch.cuda.synchronize()
     ms_plain = p0.elapsed_time(p1) / args.plain_steps
 
+    # plain form with its S launches captured once in a hipGraph and replayed
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.solve_plain(b, x)
+    x.fill_(float("nan"))
+    graph.replay()
+    torch.cuda.synchronize()
+    exact_graph = oracle.same_bits(x.cpu().numpy(), want)
+    q0 = torch.cuda.Event(enable_timing=True)
+    q1 = torch.cuda.Event(enable_timing=True)
+    q0.record(stream)
+    for _ in range(args.plain_steps):
+        graph.replay()
+    q1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = q0.elapsed_time(q1) / args.plain_steps
+    del graph
+
     # the same bytes without the dependencies: one gather-probe pass over the plan
     ones = torch.ones_like(x)
     ysink = torch.zeros_like(x)
@@ -230,7 +252,9 @@ def main():
     alg = algorithmic_bytes(m.n, m.nnz)
     kern_ms = float(np.mean(per))
     achieved = alg / (kern_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, "trsv_persistent") if args.schedule == "growlocal" else None
+    default_run = args.workload == "er1e7" and args.schedule == "growlocal"
+    traffic = measured_traffic(args.workload if default_run else f"{args.workload}_{args.schedule}",
+                               "trsv_persistent")
     out = {
         "metric": "reduced elements/sec (exact) at 1 MI355X vs plain launch; p50/p99 latency",
         "value": rows_s,
@@ -252,10 +276,14 @@ def main():
             "chunks": info["chunks"], "grid_blocks": info["grid_blocks"],
             "analysis_s": info["analysis_ns"] / 1e9,
         },
-        "exact": bool(exact and exact_plain),
-        "plain": {"value": rows_s_plain, "ms_per_step": ms_plain, "launches_per_step": info["supersteps"]},
+        "exact": bool(exact and exact_plain and exact_graph),
+        "nnz_per_s": m.nnz / (ms * 1e-3),
+        "gflops": (2 * m.nnz - m.n) / (ms * 1e-3) / 1e9,
+        "plain": {"value": rows_s_plain, "ms_per_step": ms_plain, "launches_per_step": info["supersteps"],
+                  "graph_ms_per_step": ms_graph},
         "speedup_vs_plain": (ms_plain / ms) if ms > 0 else None,
-        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
+        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
+                       "iqr": float(np.percentile(per, 75) - np.percentile(per, 25))},
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -271,6 +299,54 @@ def main():
         out["cpu_baseline"] = cpu_baseline(m)
     plan.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_analysis(args):
+    """Block-parallel scheduling (Sec. 3.1) on one workload: for each block
+    count, the plan's analysis time, supersteps and persistent solve time,
+    and the solves after which the GrowLocal plan repays its extra analysis
+    time over the wavefront plan (Table 7.6/7.7 analogue)."""
+    import torch
+    import oracle
+    from paper_2503_05408_amd import binding as B
+    m, desc = workload(args.workload)
+    b = torch.ones(m.n, dtype=torch.float64, device="cuda")
+    want = oracle.solve(m, np.ones(m.n))
+    stream = torch.cuda.current_stream()
+
+    def measure(opts):
+        t0 = time.perf_counter()
+        plan = B.Plan(m, opts)
+        wall = time.perf_counter() - t0
+        info = plan.info()
+        x = plan.solve(b)
+        torch.cuda.synchronize()
+        exact = oracle.same_bits(x.cpu().numpy(), want)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan.solve(b, x)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plan.close()
+        return {"analysis_s": info["analysis_ns"] / 1e9, "plan_wall_s": wall, "supersteps": info["supersteps"],
+                "solve_ms": e0.elapsed_time(e1) / args.steps, "exact": bool(exact)}
+
+    wf = measure(B.default_opts(schedule_kind=B.SCHED_WAVEFRONT))
+    log(f"wavefront: {wf}")
+    rows = []
+    for nb in [int(v) for v in args.blocks.split(",")]:
+        r = measure(B.default_opts(k=args.k, L=args.L, alpha0=args.alpha0, blocks=nb))
+        gain_ms = wf["solve_ms"] - r["solve_ms"]
+        r["blocks"] = nb
+        r["repay_solves_vs_wavefront"] = ((r["analysis_s"] - wf["analysis_s"]) * 1e3 / gain_ms
+                                          if gain_ms > 0 else None)
+        log(f"blocks={nb}: {r}")
+        rows.append(r)
+    print(json.dumps({"mode": "analysis", "workload": desc, "n": m.n, "nnz": m.nnz,
+                      "schedule": f"growlocal k={args.k} L={args.L:g} alpha0={args.alpha0:g}",
+                      "host_threads": os.cpu_count(), "wavefront": wf, "blocks": rows}), flush=True)
 
 
 def auto_plan(m):

@@ -100,3 +100,12 @@ def test_poisoned_output():
         plan.solve_plain(torch.from_numpy(b).cuda(), x)
         torch.cuda.synchronize()
         assert oracle.same_bits(x.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("nblocks", [2, 7])
+def test_block_parallel_schedule_solves_exactly(nblocks):
+    for m in (gen.random_lower(6000, 0.003, 41), gen.narrow_band(20000, 0.05, 20, 6)):
+        want, x1, x2, info = _solve_both(m, B.gpu_opts(blocks=nblocks), seed=nblocks)
+        pi, sg, S = oracle.growlocal_blocks(m, 1 << 16, nblocks, L=50.0, alpha0=1.0)
+        assert info["supersteps"] == S
+        assert oracle.same_bits(x1, want) and oracle.same_bits(x2, want), m.name
