@@ -185,6 +185,7 @@ typedef struct gltrsv_plan_info {
                                entry of its longest task and its entries at
                                4e4 entries/us                                */
     int32_t device_packed;  /* 1 if the stream was filled on the device       */
+    int32_t async_grid_blocks; /* workgroups of gltrsv_solve_async            */
 } gltrsv_plan_info;
 
 /* Analyses A (checks, schedule, Sec. 5 order) and uploads the packed matrix
@@ -303,6 +304,19 @@ int64_t gltrsv_clock_ns(void);
 
 /* Waits until every accepted request has completed, then frees the server. */
 int gltrsv_server_destroy(gltrsv_server *server);
+
+/* Semi-asynchronous solve (the paper's future-work direction, Sec. 8): the
+ * same schedule, stream and per-row arithmetic as gltrsv_solve (so the same
+ * bits), with the barriers replaced by per-row readiness.  x is first filled
+ * with a signalling-NaN mark that no computed value can equal (every x_i is
+ * the result of a division); a lane that gathers the mark reads again until
+ * the value is there.  Waves run the chunks in schedule order, so the solve
+ * always progresses.  b and x: device, n values each, original numbering;
+ * b == x (in place) is allowed and uses a plan-owned copy of b (allocated on
+ * the first such call); b and x must otherwise not overlap.  Asynchronous on
+ * `stream`; a wait that exceeds the spin limit is reported by
+ * gltrsv_plan_device_status (GLTRSV_ETIMEDOUT). */
+int gltrsv_solve_async(gltrsv_plan *plan, const double *b, double *x, void *stream);
 
 /* Plain device-to-device copy of `bytes` (a multiple of 16) from src to dst
  * (device pointers, caller-owned, non-overlapping), asynchronous on `stream`.

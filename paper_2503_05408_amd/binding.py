@@ -72,7 +72,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n", i64), ("nnz", i64), ("supersteps", i32), ("wavefronts", i32), ("tasks", i64),
                 ("chunks", i64), ("stream_slots", i64), ("device_bytes", i64), ("analysis_ns", i64),
                 ("pattern_key", u64), ("grid_blocks", i32), ("block_size", i32), ("max_task_rows", i64),
-                ("schedule_kind", i32), ("predicted_us", dbl), ("device_packed", i32)]
+                ("schedule_kind", i32), ("predicted_us", dbl), ("device_packed", i32),
+                ("async_grid_blocks", i32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -97,6 +98,7 @@ SIGNATURES = {
     "gltrsv_debug_trace": ([P, P, i64], i32),
     "gltrsv_copy_probe": ([P, P, i64, P], i32),
     "gltrsv_plan_gather_probe": ([P, P, P, P], i32),
+    "gltrsv_solve_async": ([P, P, P, P], i32),
     "gltrsv_plan_stream": ([P, P, P, i64], i32),
     "gltrsv_default_batch_opts": ([P], None),
     "gltrsv_batch_create": ([P, i32, P, P], i32),
@@ -290,6 +292,15 @@ class Plan:
             x = torch.empty_like(b)
         _check(load().gltrsv_solve(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
                "gltrsv_solve")
+        return x
+
+    def solve_async(self, b, x=None, stream=None):
+        """Semi-asynchronous solve: no barriers, per-row readiness."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        _check(load().gltrsv_solve_async(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
+               "gltrsv_solve_async")
         return x
 
     def solve_plain(self, b, x=None, stream=None):

@@ -180,12 +180,58 @@ __device__ __forceinline__ void process_batch(const Batch &B, const double (&g)[
         if (yrow[j] >= 0) store_x(x + yrow[j], ys[j]);
 }
 
+// Semi-asynchronous execution: x starts filled with kUnready, a signalling
+// NaN.  Every value the solve stores is the result of a division, which never
+// yields a signalling NaN, so a gathered kUnready means "not computed yet":
+// the gather is repeated until the value arrives.
+constexpr unsigned long long kUnready = 0x7FF4A5A5A5A5A5A5ull;
+#ifndef GLTRSV_AWAIT_NAP_MAX
+#define GLTRSV_AWAIT_NAP_MAX 1
+#endif
+constexpr int kAwaitNapMax = GLTRSV_AWAIT_NAP_MAX;   // longest pause between re-reads, in s_sleep(1) units
+
+__device__ __forceinline__ bool unready(uint32_t c, double g)
+{
+    return (c & (HDR | INTL)) == 0 && static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
+}
+
+// Waits until every gathered column of the batch holds a computed value.
+// Gives up after spin_limit rounds (setting *err) or once another wave has
+// set *err; the solve's status then reports the failure.
+__device__ __forceinline__ void await_batch(const Batch &B, double (&g)[kUnroll], const double *x, int32_t *err,
+                                            int64_t spin_limit)
+{
+    bool miss = false;
+#pragma unroll
+    for (int j = 0; j < kUnroll; j++) miss |= unready(B.w[j], g[j]);
+    if (__ballot(miss) == 0ull) return;
+    int32_t nap = 1;
+    for (int64_t spins = 1;; spins++) {
+        for (int32_t k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(1);
+        nap = min(2 * nap, int32_t(kAwaitNapMax));
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++)
+            if (unready(B.w[j], g[j])) g[j] = load_x(x + B.w[j]);
+        miss = false;
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++) miss |= unready(B.w[j], g[j]);
+        if (__ballot(miss) == 0ull) return;
+        if (spins > spin_limit) {
+            if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    }
+}
+
 // One pipeline step: gathers of `nxt`, words/values of the batch after it
-// into `fut`, then the work of `now`.
+// into `fut`, then the work of `now` (in the semi-asynchronous form, once
+// every operand of `now` has been computed).
 #define GLTRSV_STEP(NOW, GNOW, NXT, GNXT, FUT, T0)                                                       \
     do {                                                                                                 \
         gather_batch(NXT, b, x, GNXT);                                                                   \
         load_batch(cur, (T0) + 2 * kUnroll, FUT);                                                        \
+        if constexpr (kAsync) await_batch(NOW, GNOW, x, err, spin_limit);                                \
         process_batch(NOW, GNOW, st, x, ring);                                                           \
     } while (0)
 
@@ -193,8 +239,9 @@ __device__ __forceinline__ void process_batch(const Batch &B, const double (&g)[
 // loaded by the caller, possibly before the superstep's barrier).  The loop
 // is unrolled three times so the three batch buffers change roles without
 // register copies.
+template <bool kAsync = false>
 __device__ __forceinline__ void run_lane(const LaneCursor &cur, Batch &b0, Batch &b1, const double *b, double *x,
-                                         Ring ring)
+                                         Ring ring, int32_t *err = nullptr, int64_t spin_limit = 0)
 {
     LaneState st;
     st.acc = 0.0;
@@ -384,6 +431,41 @@ __global__ __launch_bounds__(kBlock) void trsv_persistent(
 #ifdef GLTRSV_TRACE
         if (threadIdx.x == 0) trace[(int64_t(s) * gridDim.x + blockIdx.x) * 3 + 2] = wall_clock64();
 #endif
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Semi-asynchronous solve: no barriers.  Wave w runs chunks w, w + W, w + 2W,
+// ... in order (chunks are numbered superstep by superstep), and a lane waits
+// only for the columns it reads (await_batch).  Progress: the earliest
+// unfinished chunk depends only on chunks of earlier supersteps, which are
+// finished, and its wave has finished its own earlier chunks, so it is
+// running it; hence every chunk completes provided all W waves are resident
+// (the grid is sized to the device's co-resident capacity, as for the
+// persistent kernel, and a wave kept from starting ends the solve with the
+// spin-limit error instead of a hang).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void fill_unready(unsigned long long *x, int64_t n)
+{
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) x[i] = kUnready;
+}
+
+__global__ __launch_bounds__(kBlock) void trsv_async(const uint32_t *__restrict__ word,
+                                                     const double *__restrict__ value,
+                                                     const int64_t *__restrict__ chunk_base,
+                                                     const int32_t *__restrict__ chunk_len, int32_t chunks,
+                                                     const double *b, double *x, int32_t *err, int64_t spin_limit)
+{
+    __shared__ double ring[kRing + 1][kBlock];
+    const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
+    const int lane = threadIdx.x & 63;
+    for (int32_t c = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6); c < chunks; c += waves) {
+        const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
+        Batch b0, b1;
+        load_batch(cur, 0, b0);
+        load_batch(cur, kUnroll, b1);
+        run_lane<true>(cur, b0, b1, b, x, ring, err, spin_limit);
     }
 }
 
@@ -842,6 +924,7 @@ int gltrsv_plan_destroy(gltrsv_plan *p)
     (void)hipFree(p->d_bar);
     (void)hipFree(p->d_err);
     (void)hipFree(p->d_trace);
+    (void)hipFree(p->d_bcopy);
     delete p;
     return GLTRSV_OK;
 }
@@ -932,8 +1015,27 @@ int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv
         widest = std::max<int64_t>(widest, p->super_chunk_host[q + 1] - p->super_chunk_host[q]);
     p->widest = widest;
     const int64_t useful = (widest + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
+    const int cap = grid;
     grid = int(std::max<int64_t>(1, std::min<int64_t>(grid, useful)));
     p->grid = grid;
+    // semi-asynchronous kernel: waves in flight = about four supersteps of
+    // average width, at most one workgroup per CU (more waves only add
+    // polling of not-yet-computed rows), all co-resident
+    {
+        int per_cu_a = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_a, dev::trsv_async, dev::kBlock, 0);
+        if (e != hipSuccess) {
+            gltrsv_plan_destroy(p);
+            return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
+        }
+        int64_t ga = std::min<int64_t>(int64_t(per_cu_a) * cus, cus);
+        const int64_t avg_width = p->S > 0 ? (p->chunks + p->S - 1) / p->S : 1;
+        ga = std::min<int64_t>(ga, avg_width);   // avg_width chunks x 4 waves per block = 4 supersteps
+        if (opts->grid_blocks > 0) ga = opts->grid_blocks < per_cu_a * cus ? opts->grid_blocks : per_cu_a * cus;
+        (void)cap;
+        p->grid_async = int(std::max<int64_t>(
+            1, std::min<int64_t>(ga, (p->chunks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
+    }
 #ifdef GLTRSV_TRACE
     {
         std::vector<int64_t> tr(size_t(p->S) * grid * 3, 0);
@@ -969,6 +1071,7 @@ int gltrsv_plan_info_get(const gltrsv_plan *p, gltrsv_plan_info *o)
     o->schedule_kind = p->schedule_kind;
     o->predicted_us = p->predicted_us;
     o->device_packed = p->device_packed ? 1 : 0;
+    o->async_grid_blocks = p->grid_async;
     return GLTRSV_OK;
 }
 
@@ -1026,6 +1129,41 @@ int gltrsv_solve(gltrsv_plan *p, const double *b, double *x, void *stream)
                            bar, err, lim, tr);
         HIP_TRY(hipGetLastError());
     }
+    p->last_stream = st;
+    return GLTRSV_OK;
+}
+
+int gltrsv_solve_async(gltrsv_plan *p, const double *b, double *x, void *stream)
+{
+    if (!p || (p->n && (!b || !x))) return set_error(GLTRSV_EINVAL, "null argument");
+    if (p->n == 0) return GLTRSV_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double *bb = b;
+    if (b == x) {   // x is about to be overwritten with the not-yet-computed mark
+        if (!p->d_bcopy) HIP_TRY(hipMalloc(reinterpret_cast<void **>(&p->d_bcopy), sizeof(double) * size_t(p->n)));
+        HIP_TRY(hipMemcpyAsync(p->d_bcopy, b, sizeof(double) * size_t(p->n), hipMemcpyDeviceToDevice, st));
+        bb = p->d_bcopy;
+    }
+    const int64_t fill_blocks = std::min<int64_t>(4096, (p->n + dev::kBlock - 1) / dev::kBlock);
+    hipLaunchKernelGGL(dev::fill_unready, dim3(unsigned(fill_blocks)), dim3(dev::kBlock), 0, st,
+                       reinterpret_cast<unsigned long long *>(x), p->n);
+    const int32_t chunks = int32_t(p->chunks);
+    int64_t lim = p->spin_limit;
+    if (p->cooperative) {
+        const uint32_t *w = p->d_word;
+        const double *v = p->d_value;
+        const int64_t *cb = p->d_chunk_base;
+        const int32_t *cl = p->d_chunk_len;
+        int32_t *err = p->d_err;
+        int32_t nch = chunks;
+        void *args[] = {&w, &v, &cb, &cl, &nch, &bb, &x, &err, &lim};
+        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(dev::trsv_async), dim3(p->grid_async),
+                                           dim3(dev::kBlock), args, 0, st));
+    } else {
+        hipLaunchKernelGGL(dev::trsv_async, dim3(p->grid_async), dim3(dev::kBlock), 0, st, p->d_word, p->d_value,
+                           p->d_chunk_base, p->d_chunk_len, chunks, bb, x, p->d_err, lim);
+    }
+    HIP_TRY(hipGetLastError());
     p->last_stream = st;
     return GLTRSV_OK;
 }

@@ -111,6 +111,8 @@ struct gltrsv_plan {
     int32_t schedule_kind = 0;      // the schedule actually built
     double predicted_us = 0.0;      // cost-model prediction of one solve
     bool device_packed = false;     // stream filled by the packing kernels
+    int grid_async = 0;             // workgroups of the semi-asynchronous kernel
+    double *d_bcopy = nullptr;      // b when a semi-asynchronous solve runs in place
     int cooperative = 0;
 };
 

@@ -28,9 +28,12 @@ def _solve_both(m, opts, b=None, seed=0):
     with B.Plan(m, opts) as plan:
         x1 = plan.solve(bd)
         x2 = plan.solve_plain(bd)
+        x3 = plan.solve_async(bd)
         torch.cuda.synchronize()
         assert plan.device_status() == 0
         info = plan.info()
+    # the semi-asynchronous form (no barriers) computes the same bits
+    assert oracle.same_bits(x3.cpu().numpy(), want), (m.name, "async")
     return want, x1.cpu().numpy(), x2.cpu().numpy(), info
 
 
@@ -109,3 +112,23 @@ def test_block_parallel_schedule_solves_exactly(nblocks):
         pi, sg, S = oracle.growlocal_blocks(m, 1 << 16, nblocks, L=50.0, alpha0=1.0)
         assert info["supersteps"] == S
         assert oracle.same_bits(x1, want) and oracle.same_bits(x2, want), m.name
+
+
+def test_async_in_place_and_repeated():
+    import torch
+    m = gen.narrow_band(30000, 0.05, 20, 8)
+    b = gen.rhs_uniform(m.n, 4)
+    want = oracle.solve(m, b)
+    with B.Plan(m, B.gpu_opts(schedule_kind=B.SCHED_WAVEFRONT)) as plan:
+        for rep in range(3):
+            x = torch.from_numpy(b).cuda()
+            plan.solve_async(x, x)          # in place: b == x
+            torch.cuda.synchronize()
+            assert plan.device_status() == 0
+            assert oracle.same_bits(x.cpu().numpy(), want), rep
+        bd = torch.from_numpy(b).cuda()
+        x = torch.empty_like(bd)
+        for rep in range(3):
+            plan.solve_async(bd, x)
+        torch.cuda.synchronize()
+        assert oracle.same_bits(x.cpu().numpy(), want)
