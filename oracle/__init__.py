@@ -9,6 +9,8 @@ its own); this module only marshals numpy arrays.
 Each function cites the passage of the paper (arxiv 2503.05408) it follows:
 
 * :func:`solve`      -- forward substitution, Eq. (2.1).
+* :func:`solve_upper` -- backward substitution, its mirror (Sec. 2.2);
+  :func:`mirror_upper` and :func:`growlocal_upper` schedule it.
 * :func:`levels`     -- wavefronts; average wavefront size = floor(n / #levels)
   (Sec. 6.2; the appendix tables round down).
 * :func:`validate`   -- Definition 2.1.
@@ -69,6 +71,7 @@ def _load():
             i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
             lib.oracle_check_csr.argtypes = [i64, P, P, P]
             lib.oracle_solve.argtypes = [i64, P, P, P, P, P]
+            lib.oracle_solve_upper.argtypes = [i64, P, P, P, P, P]
             lib.oracle_levels.argtypes = [i64, P, P, P]
             lib.oracle_levels.restype = i64
             lib.oracle_validate.argtypes = [i64, P, P, i32, P, P, i32]
@@ -112,6 +115,63 @@ def solve(m, b) -> np.ndarray:
     if rc:
         raise OracleError(f"oracle_solve: {rc}")
     return x
+
+
+def solve_upper(m, b) -> np.ndarray:
+    """Serial backward substitution of an upper-triangular CSR (diagonal
+    first in each row): rows from the last to the first, running subtraction
+    in stored column order, one division (the mirror of Eq. (2.1), Sec. 2.2)."""
+    rp, c, v = _csr(m)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.empty(m.n, dtype=np.float64)
+    rc = _load().oracle_solve_upper(m.n, _p(rp), _p(c), _p(v), _p(b), _p(x))
+    if rc:
+        raise OracleError(f"oracle_solve_upper: {rc}")
+    return x
+
+
+def mirror_upper(m, keep_order: bool = False):
+    """The lower-triangular matrix J A J of an upper-triangular A, with J the
+    reversal (row/column i -> n-1-i).  Row n-1-i holds row i's entries.  With
+    keep_order the entries stay in A's stored order (columns then fall and
+    the diagonal moves to the end); otherwise columns rise (a sorted CSR).
+    Its DAG is A's DAG with every vertex renamed i -> n-1-i."""
+    from paper_2503_05408_amd.gen import CSR
+    rp, c, v = _csr(m)
+    n = m.n
+    rows_rp = np.zeros(n + 1, dtype=np.int64)
+    lens = (rp[1:] - rp[:-1])[::-1]
+    np.cumsum(lens, out=rows_rp[1:])
+    col2 = np.empty_like(c)
+    val2 = np.empty_like(v)
+    for t in range(n):
+        i = n - 1 - t
+        a, e = rp[i], rp[i + 1]
+        offc = (n - 1 - c[a + 1:e]).astype(np.int32)
+        offv = v[a + 1:e]
+        if not keep_order:
+            offc, offv = offc[::-1], offv[::-1]
+        o = rows_rp[t]
+        col2[o:o + e - a - 1] = offc
+        val2[o:o + e - a - 1] = offv
+        col2[o + e - a - 1] = t
+        val2[o + e - a - 1] = v[a]
+    return CSR(n, rows_rp, col2, val2, name=(m.name or "") + "_mirror")
+
+
+def growlocal_upper(m, k, L=PAPER_L, alpha0=PAPER_ALPHA0, growth=PAPER_GROWTH, theta=PAPER_THETA,
+                    nblocks: int = 1):
+    """GrowLocal for backward substitution: the DAG of an upper-triangular A
+    with its vertices numbered in the direction of the solve (row i is
+    vertex n-1-i), so Algorithm 3.1's smallest-ID rules and the diagonal
+    blocks of Sec. 3.1 run in the reverse direction as the text prescribes.
+    Returns (pi, sigma, S) indexed by the rows of A."""
+    low = mirror_upper(m)
+    if nblocks > 1:
+        pi, sg, S = growlocal_blocks(low, k, nblocks, L=L, alpha0=alpha0, growth=growth, theta=theta)
+    else:
+        pi, sg, S = growlocal(low, k, L=L, alpha0=alpha0, growth=growth, theta=theta)
+    return pi[::-1].copy(), sg[::-1].copy(), S
 
 
 def levels(m):

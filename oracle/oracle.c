@@ -8,6 +8,7 @@
  *
  * Contents, each written from the paper (arxiv 2503.05408):
  *   oracle_solve        forward substitution, Eq. (2.1), Sec. 2.2
+ *   oracle_solve_upper  backward substitution, its mirror (Sec. 2.2)
  *   oracle_levels       wavefronts (level sets) of the DAG, Sec. 1 / Sec. 6.2
  *   oracle_validate     validity of a BSP schedule, Definition 2.1
  *   oracle_growlocal    the GrowLocal scheduler, Algorithm 3.1 and Sec. 3
@@ -105,6 +106,46 @@ int oracle_solve(int64_t n, const int64_t *row_ptr, const int32_t *col, const do
             acc = acc - prod;
         }
         x[i] = acc / val[e];
+    }
+    return OR_OK;
+}
+
+/* Upper-triangular CSR: in every row the diagonal is the first stored entry
+ * and the off-diagonal columns ascend above it. */
+static int check_rows_upper(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val)
+{
+    if (n < 0 || (n > 0 && (!row_ptr || !col))) return OR_EARG;
+    if (n == 0) return OR_OK;
+    if (row_ptr[0] != 0) return OR_EBADCSR;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t a = row_ptr[i], e = row_ptr[i + 1];
+        if (e <= a) return OR_EBADCSR;                 /* no diagonal */
+        if (col[a] != i) return OR_EBADCSR;             /* diagonal first */
+        if (val && val[a] == 0.0) return OR_EBADCSR;
+        for (int64_t p = a + 1; p < e; p++)
+            if (col[p] <= col[p - 1] || col[p] >= n) return OR_EBADCSR;
+    }
+    return OR_OK;
+}
+
+/* Backward substitution, the mirror of Eq. (2.1) (Sec. 2.2: an upper
+ * triangular system is solved the same way in the reverse direction):
+ * x_i = (b_i - sum_{j>i} A_ij x_j) / A_ii for i = n-1 down to 0, the sum as a
+ * running subtraction in stored (rising column) order, one division.  b and
+ * x may be the same array. */
+int oracle_solve_upper(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                       const double *b, double *x)
+{
+    int rc = check_rows_upper(n, row_ptr, col, val);
+    if (rc) return rc;
+    for (int64_t i = n - 1; i >= 0; i--) {
+        int64_t d = row_ptr[i], e = row_ptr[i + 1];   /* d = diagonal position */
+        double acc = b[i];
+        for (int64_t p = d + 1; p < e; p++) {
+            double prod = val[p] * x[col[p]];
+            acc = acc - prod;
+        }
+        x[i] = acc / val[d];
     }
     return OR_OK;
 }

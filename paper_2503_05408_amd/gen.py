@@ -37,10 +37,12 @@ SEED_BASE = 2503054080
 
 @dataclass
 class CSR:
-    """Square lower-triangular matrix in CSR form.
+    """Square triangular matrix in CSR form.
 
     ``row_ptr`` int64[n+1], ``col`` int32[nnz], ``val`` float64[nnz].  Within a
-    row the columns ascend and the diagonal entry is the last one.
+    row the columns ascend; the diagonal entry is the last one of a lower
+    triangle (the default) and the first one of an upper triangle
+    (``meta["upper"]`` true, see :func:`upper_of`).
     """
 
     n: int
@@ -423,4 +425,21 @@ def batch_mix(count: int = 64, seed: int = SEED_BASE + 100, lo_exp: float = 3.0,
             m = _stencil((side, side, max(1, n // (side * side))),
                          [(-1, 0, 0), (0, -1, 0), (0, 0, -1)], 6.0, f"mix{i}_st3d7_{side}")
             out.append(m)
+    return out
+
+
+def upper_of(m: CSR, name: str | None = None) -> CSR:
+    """The transpose of a lower-triangular CSR: an upper-triangular CSR whose
+    row j holds the entries of column j (rising columns, diagonal first), with
+    the same values."""
+    n = m.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(m.row_ptr))
+    cols = m.col.astype(np.int64)
+    order = np.lexsort((rows, cols))          # by column of m, then row of m
+    t_rows, t_cols, t_vals = cols[order], rows[order], m.val[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(t_rows, minlength=n), out=row_ptr[1:])
+    out = CSR(n, row_ptr, t_cols.astype(np.int32), np.ascontiguousarray(t_vals), name or (m.name + "_T"),
+              dict(m.meta))
+    out.meta["upper"] = True
     return out
