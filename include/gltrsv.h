@@ -43,7 +43,8 @@ extern "C" {
 /* ---------------------------------------------------------------- errors */
 #define GLTRSV_OK          0
 #define GLTRSV_EINVAL     -1   /* null pointer, negative size, bad option    */
-#define GLTRSV_ENOTLOWER  -2   /* an entry above the diagonal                */
+#define GLTRSV_ENOTLOWER  -2   /* an entry on the wrong side of the diagonal
+                                  (above it; below it for GLTRSV_UPPER)    */
 #define GLTRSV_ESINGULAR  -3   /* diagonal missing, not last, or zero        */
 #define GLTRSV_EUNSORTED  -4   /* off-diagonal columns not strictly rising   */
 #define GLTRSV_ERANGE     -5   /* index out of range, or n too large         */
@@ -77,6 +78,10 @@ int gltrsv_check_csr(const gltrsv_csr *A);
 #define GLTRSV_SCHED_GROWLOCAL 0   /* Algorithm 3.1                           */
 #define GLTRSV_SCHED_WAVEFRONT 1   /* level sets: one superstep per wavefront */
 #define GLTRSV_SCHED_AUTO      2   /* both; keep the lower predicted time     */
+
+/* gltrsv_plan_opts.triangle */
+#define GLTRSV_LOWER 0
+#define GLTRSV_UPPER 1
 
 /* Stream filling (gltrsv_plan_opts.pack), Sec. 5 reorder plus packing:
  *  AUTO   -- device for systems with at least 2^20 stored entries, else host;
@@ -126,6 +131,17 @@ typedef struct gltrsv_plan_opts {
                                weights of the full rows, on separate host
                                threads, and block b's supersteps follow those
                                of blocks 0..b-1; 0 or 1 = the whole matrix   */
+    int32_t triangle;         /* GLTRSV_LOWER (forward substitution, Eq. (2.1))
+                               or GLTRSV_UPPER (backward substitution, its
+                               mirror, Sec. 2.2): A is upper-triangular with
+                               the diagonal FIRST in every row and rising
+                               columns; x_i = (b_i - sum_{j>i} A_ij x_j) /
+                               A_ii for i = n-1 .. 0, the sum as a running
+                               subtraction in stored order.  The schedule is
+                               built on the reversed numbering (row i is
+                               vertex n-1-i) so GrowLocal runs in the solve's
+                               direction; gltrsv_schedule and
+                               gltrsv_plan_schedule report it per row.       */
 } gltrsv_plan_opts;
 
 /* Fills the paper's parameters: k = 22 (the core count of the main

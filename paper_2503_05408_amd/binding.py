@@ -29,6 +29,8 @@ ERRORS = {
 SCHED_GROWLOCAL = 0
 SCHED_WAVEFRONT = 1
 SCHED_AUTO = 2
+LOWER = 0
+UPPER = 1
 PACK_AUTO = 0
 PACK_HOST = 1
 PACK_DEVICE = 2
@@ -48,7 +50,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("k", i32), ("L", dbl), ("alpha0", dbl), ("growth", dbl), ("accept", dbl),
                 ("schedule_kind", i32), ("reorder", i32), ("block_size", i32), ("grid_blocks", i32),
                 ("cooperative", i32), ("analysis_threads", i32), ("pack", i32),
-                ("blocks", i32)]
+                ("blocks", i32), ("triangle", i32)]
 
 
 class BatchOpts(ctypes.Structure):

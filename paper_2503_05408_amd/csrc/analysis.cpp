@@ -48,6 +48,57 @@ int check_csr(const CsrView &A, bool need_values, std::string *msg)
     return GLTRSV_OK;
 }
 
+int check_csr_upper(const CsrView &A, bool need_values, std::string *msg)
+{
+    auto fail = [&](int code, const std::string &m) {
+        if (msg) *msg = m;
+        return code;
+    };
+    if (A.n < 0 || A.nnz < 0) return fail(GLTRSV_EINVAL, "negative size");
+    if (A.n > kMaxRows) return fail(GLTRSV_ERANGE, "n exceeds 2^30 - 1");
+    if (A.n == 0) return GLTRSV_OK;
+    if (!A.row_ptr || !A.col) return fail(GLTRSV_EINVAL, "null row_ptr or col");
+    if (need_values && !A.val) return fail(GLTRSV_EINVAL, "null values");
+    if (A.row_ptr[0] != 0 || A.row_ptr[A.n] != A.nnz)
+        return fail(GLTRSV_ERANGE, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+    for (int64_t i = 0; i < A.n; i++) {
+        const int64_t lo = A.row_ptr[i], hi = A.row_ptr[i + 1];
+        if (hi < lo) return fail(GLTRSV_ERANGE, "row_ptr decreases at row " + std::to_string(i));
+        if (hi == lo) return fail(GLTRSV_ESINGULAR, "row " + std::to_string(i) + " has no diagonal");
+        int32_t prev = -1;
+        for (int64_t e = lo; e < hi; e++) {
+            const int32_t c = A.col[e];
+            if (c < 0 || c >= A.n) return fail(GLTRSV_ERANGE, "column out of range in row " + std::to_string(i));
+            if (c < i) return fail(GLTRSV_ENOTLOWER, "entry below the diagonal in row " + std::to_string(i));
+            if (c <= prev) return fail(GLTRSV_EUNSORTED, "columns not strictly rising in row " + std::to_string(i));
+            prev = c;
+        }
+        if (A.col[lo] != i) return fail(GLTRSV_ESINGULAR, "row " + std::to_string(i) + " has no diagonal");
+        if (need_values && A.val[lo] == 0.0)
+            return fail(GLTRSV_ESINGULAR, "zero diagonal in row " + std::to_string(i));
+    }
+    return GLTRSV_OK;
+}
+
+Mirror mirror_upper(const CsrView &U)
+{
+    Mirror m;
+    const int64_t n = U.n;
+    m.row_ptr.assign(size_t(n) + 1, 0);
+    m.col.resize(size_t(U.nnz));
+    for (int64_t v = 0; v < n; v++) {
+        const int64_t i = n - 1 - v;
+        m.row_ptr[size_t(v) + 1] = m.row_ptr[size_t(v)] + (U.row_ptr[i + 1] - U.row_ptr[i]);
+    }
+    for (int64_t v = 0; v < n; v++) {
+        const int64_t i = n - 1 - v, lo = U.row_ptr[i], hi = U.row_ptr[i + 1];
+        int64_t o = m.row_ptr[size_t(v)];
+        for (int64_t e = hi - 1; e > lo; e--) m.col[size_t(o++)] = int32_t(n - 1 - U.col[e]);   // rising
+        m.col[size_t(o)] = int32_t(v);                                                         // diagonal
+    }
+    return m;
+}
+
 int32_t wavefront_levels(const CsrView &A, std::vector<int32_t> &level)
 {
     level.assign(A.n, 0);
@@ -583,6 +634,36 @@ void pack_fill(const CsrView &A, const Schedule &sch, const std::vector<int32_t>
             pk.value[at] = A.val ? A.val[e] : 0.0;
         }
         off += hi - lo + 1;
+    }
+}
+
+void pack_fill_upper(const CsrView &U, const std::vector<int32_t> &perm, PackLayout &lay)
+{
+    Packed &pk = lay.pk;
+    const int64_t n = U.n;
+    pk.word.assign(pk.slots, kPadWord);
+    pk.value.assign(pk.slots, 0.0);
+    std::vector<int32_t> inv(n);
+    for (int64_t t = 0; t < n; t++) inv[perm[t]] = int32_t(t);
+    int64_t off = 0;
+    for (int64_t t = 0; t < n; t++) {
+        if (t == lay.pos_task0[t]) off = 0;
+        const int64_t i = n - 1 - perm[t];
+        const int64_t lo = U.row_ptr[i], hi = U.row_ptr[i + 1];   // diagonal at lo
+        const int64_t base = lay.pos_slot[t];
+        pk.word[base + int64_t(kLanes) * off] = kHdrBit | uint32_t(i);
+        pk.value[base + int64_t(kLanes) * off] = U.val[lo];
+        for (int64_t e = lo + 1; e < hi; e++) {
+            const int32_t col = U.col[e];
+            uint32_t w = uint32_t(col);
+            const int64_t ic = inv[n - 1 - col];
+            // a parent at or after the task's first position is in this task
+            if (ic >= lay.pos_task0[t] && t - ic < kRing) w = kIntBit | uint32_t(t - ic);
+            const int64_t at = base + int64_t(kLanes) * (off + (e - lo));
+            pk.word[at] = w;
+            pk.value[at] = U.val[e];
+        }
+        off += hi - lo;
     }
 }
 

@@ -52,6 +52,29 @@ struct Schedule {
 // Returns 0 or a negative GLTRSV_E* code; msg receives a description.
 int check_csr(const CsrView &A, bool need_values, std::string *msg);
 
+// Upper-triangular layout (backward substitution): in every row the
+// diagonal is the first stored entry and the other columns rise above it.
+int check_csr_upper(const CsrView &A, bool need_values, std::string *msg);
+
+// J U J for an upper-triangular U (J = the reversal i -> n-1-i): the
+// lower-triangular pattern of the same DAG with vertex n-1-i for row i,
+// columns rising, no values.  Scheduling it schedules the backward solve in
+// its own direction.
+struct Mirror {
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col;
+    CsrView view() const
+    {
+        CsrView v;
+        v.n = int64_t(row_ptr.size()) - 1;
+        v.nnz = v.n >= 0 ? row_ptr.back() : 0;
+        v.row_ptr = row_ptr.data();
+        v.col = col.data();
+        return v;
+    }
+};
+Mirror mirror_upper(const CsrView &U);
+
 // level[i] in 1..; returns the number of wavefronts.
 int32_t wavefront_levels(const CsrView &A, std::vector<int32_t> &level);
 
@@ -94,6 +117,11 @@ PackLayout pack_layout(const CsrView &A, const Schedule &sch, const std::vector<
 
 // Fills word/value of `pk` (already sized) on the host, O(nnz).
 void pack_fill(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm, PackLayout &lay);
+
+// Host fill for an upper-triangular U scheduled through mirror_upper(U):
+// perm lists vertices (row n-1-v); headers and columns carry U's row and
+// column numbers and each row's entries follow U's stored order.
+void pack_fill_upper(const CsrView &U, const std::vector<int32_t> &perm, PackLayout &lay);
 
 // Layout + host fill.
 Packed pack_stream(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm);

@@ -745,6 +745,8 @@ int check_opts(const gltrsv_plan_opts *o)
     if (o->pack != GLTRSV_PACK_AUTO && o->pack != GLTRSV_PACK_HOST && o->pack != GLTRSV_PACK_DEVICE)
         return set_error(GLTRSV_EINVAL, "unknown pack mode");
     if (o->blocks < 0) return set_error(GLTRSV_EINVAL, "blocks must be >= 0");
+    if (o->triangle != GLTRSV_LOWER && o->triangle != GLTRSV_UPPER)
+        return set_error(GLTRSV_EINVAL, "triangle must be GLTRSV_LOWER or GLTRSV_UPPER");
     return GLTRSV_OK;
 }
 
@@ -857,6 +859,7 @@ void gltrsv_default_opts(gltrsv_plan_opts *o)
     o->analysis_threads = 0;
     o->pack = GLTRSV_PACK_AUTO;
     o->blocks = 0;
+    o->triangle = GLTRSV_LOWER;
 }
 
 int gltrsv_check_csr(const gltrsv_csr *A)
@@ -886,15 +889,19 @@ int gltrsv_schedule(const gltrsv_csr *A, const gltrsv_plan_opts *opts, int32_t *
     int rc = check_opts(opts);
     if (rc) return rc;
     std::string msg;
-    rc = check_csr(view_of(A), false, &msg);
+    const bool upper = opts->triangle == GLTRSV_UPPER;
+    rc = upper ? check_csr_upper(view_of(A), false, &msg) : check_csr(view_of(A), false, &msg);
     if (rc) return set_error(rc, msg);
+    Mirror mir;
+    if (upper) mir = mirror_upper(view_of(A));
     std::vector<int32_t> perm;
     double cost = 0.0;
     int32_t chosen = 0;
-    Schedule s = build_schedule(view_of(A), opts, &perm, &cost, &chosen);
-    if (A->n) {
-        std::memcpy(core, s.core.data(), sizeof(int32_t) * A->n);
-        std::memcpy(superstep, s.superstep.data(), sizeof(int32_t) * A->n);
+    Schedule s = build_schedule(upper ? mir.view() : view_of(A), opts, &perm, &cost, &chosen);
+    const int64_t n = A->n;
+    for (int64_t i = 0; i < n; i++) {   // a backward solve's vertex v is row n-1-v
+        core[i] = s.core[size_t(upper ? n - 1 - i : i)];
+        superstep[i] = s.superstep[size_t(upper ? n - 1 - i : i)];
     }
     *S = s.S;
     return GLTRSV_OK;
@@ -937,21 +944,30 @@ int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv
     if (rc) return rc;
     const auto t0 = std::chrono::steady_clock::now();
     const CsrView V = view_of(A);
+    const bool upper = opts->triangle == GLTRSV_UPPER;
     std::string msg;
-    rc = check_csr(V, true, &msg);
+    rc = upper ? check_csr_upper(V, true, &msg) : check_csr(V, true, &msg);
     if (rc) return set_error(rc, msg);
+    // a backward solve is scheduled on its mirrored (lower) pattern
+    Mirror mir;
+    if (upper) mir = mirror_upper(V);
+    const CsrView D = upper ? mir.view() : V;   // the DAG in the solve's direction
 
     gltrsv_plan *p = new (std::nothrow) gltrsv_plan();
     if (!p) return set_error(GLTRSV_ENOMEM, "host allocation");
     p->n = A->n;
     p->nnz = A->nnz;
-    Schedule s = build_schedule(V, opts, &p->perm, &p->predicted_us, &p->schedule_kind);
+    p->upper = upper;
+    Schedule s = build_schedule(D, opts, &p->perm, &p->predicted_us, &p->schedule_kind);
     std::vector<int32_t> lv;
-    p->wavefronts = wavefront_levels(V, lv);
+    p->wavefronts = wavefront_levels(D, lv);
     const bool on_device =
         opts->pack == GLTRSV_PACK_DEVICE || (opts->pack == GLTRSV_PACK_AUTO && V.nnz >= (int64_t(1) << 20));
-    PackLayout lay = pack_layout(V, s, p->perm);
-    if (!on_device) pack_fill(V, s, p->perm, lay);
+    PackLayout lay = pack_layout(D, s, p->perm);
+    if (!on_device) {
+        if (upper) pack_fill_upper(V, p->perm, lay);
+        else pack_fill(V, s, p->perm, lay);
+    }
     Packed &pk = lay.pk;
     p->S = s.S;
     p->core = std::move(s.core);
@@ -974,7 +990,7 @@ int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv
             return set_error(e == hipErrorOutOfMemory ? GLTRSV_ENOMEM : GLTRSV_EHIP, "stream allocation");
         }
         bytes += int64_t(ns) * 12;
-        if ((rc = dev::device_pack(V, p->perm, lay, p->d_word, p->d_value))) {
+        if ((rc = dev::device_pack(V, p->perm, lay, upper, p->d_word, p->d_value))) {
             gltrsv_plan_destroy(p);
             return rc;
         }
@@ -1079,9 +1095,19 @@ int gltrsv_plan_schedule(const gltrsv_plan *p, int32_t *core, int32_t *superstep
 {
     if (!p) return set_error(GLTRSV_EINVAL, "null plan");
     const size_t nb = sizeof(int32_t) * size_t(p->n);
-    if (core && p->n) std::memcpy(core, p->core.data(), nb);
-    if (superstep && p->n) std::memcpy(superstep, p->superstep.data(), nb);
-    if (perm && p->n) std::memcpy(perm, p->perm.data(), nb);
+    if (!p->upper) {
+        if (core && p->n) std::memcpy(core, p->core.data(), nb);
+        if (superstep && p->n) std::memcpy(superstep, p->superstep.data(), nb);
+        if (perm && p->n) std::memcpy(perm, p->perm.data(), nb);
+        return GLTRSV_OK;
+    }
+    // backward solve: vertex v of the schedule is row n-1-v
+    const int64_t n = p->n;
+    for (int64_t i = 0; i < n; i++) {
+        if (core) core[i] = p->core[size_t(n - 1 - i)];
+        if (superstep) superstep[i] = p->superstep[size_t(n - 1 - i)];
+        if (perm) perm[i] = int32_t(n - 1 - p->perm[size_t(i)]);
+    }
     return GLTRSV_OK;
 }
 

@@ -69,8 +69,10 @@ __global__ void batch_reset(unsigned long long *state, uint32_t *done, int32_t c
                             uint32_t *finished, int32_t *err);
 // Fills the plan's stream (d_word, d_value: lay.pk.slots entries) on the
 // device from A, the schedule order and the host layout; synchronous.
-int device_pack(const CsrView &A, const std::vector<int32_t> &perm, const PackLayout &lay, uint32_t *d_word,
-                double *d_value);
+// upper: A is upper-triangular and perm lists vertices of its mirror (row
+// n-1-v), as for pack_fill_upper.
+int device_pack(const CsrView &A, const std::vector<int32_t> &perm, const PackLayout &lay, bool upper,
+                uint32_t *d_word, double *d_value);
 
 // finished[0] = systems completed in the launch, finished[1] = waves retired
 __global__ void trsv_batched(const SysDesc *__restrict__ sys, int32_t count, unsigned long long *state,
@@ -111,6 +113,7 @@ struct gltrsv_plan {
     int32_t schedule_kind = 0;      // the schedule actually built
     double predicted_us = 0.0;      // cost-model prediction of one solve
     bool device_packed = false;     // stream filled by the packing kernels
+    bool upper = false;             // backward solve: vertex v of core/superstep/perm is row n-1-v
     int grid_async = 0;             // workgroups of the semi-asynchronous kernel
     double *d_bcopy = nullptr;      // b when a semi-asynchronous solve runs in place
     int cooperative = 0;

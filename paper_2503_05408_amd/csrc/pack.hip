@@ -29,14 +29,16 @@ namespace {
 constexpr int kScanItems = 8;                      // per thread
 constexpr int kScanTile = kBlock * kScanItems;     // per workgroup
 
+// perm lists vertices; for an upper-triangular matrix vertex v is row n-1-v.
 __global__ __launch_bounds__(kBlock) void pack_rows(const int32_t *__restrict__ perm,
-                                                    const int64_t *__restrict__ row_ptr, int64_t n,
+                                                    const int64_t *__restrict__ row_ptr, int64_t n, int32_t upper,
                                                     int32_t *__restrict__ inv, int64_t *__restrict__ len)
 {
     const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     if (t >= n) return;
-    const int32_t row = perm[t];
-    inv[row] = int32_t(t);
+    const int32_t v = perm[t];
+    const int64_t row = upper ? n - 1 - v : v;
+    inv[v] = int32_t(t);
     len[t] = row_ptr[row + 1] - row_ptr[row];
 }
 
@@ -115,24 +117,28 @@ __global__ __launch_bounds__(kBlock) void pack_scatter(
     const int32_t *__restrict__ perm, const int32_t *__restrict__ inv, const int64_t *__restrict__ row_ptr,
     const int32_t *__restrict__ col, const double *__restrict__ val, const int64_t *__restrict__ pre,
     const int64_t *__restrict__ tops, const int64_t *__restrict__ slot, const int32_t *__restrict__ task0, int64_t n,
-    int64_t slots, uint32_t *__restrict__ word, double *__restrict__ value, int32_t *__restrict__ err)
+    int32_t upper, int64_t slots, uint32_t *__restrict__ word, double *__restrict__ value, int32_t *__restrict__ err)
 {
     const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     if (t >= n) return;
-    const int32_t row = perm[t];
+    const int32_t v = perm[t];
+    const int64_t row = upper ? n - 1 - v : v;
     const int32_t t0 = task0[t];
     const int64_t off = (pre[t] + tops[t / kScanTile]) - (pre[t0] + tops[t0 / kScanTile]);
-    const int64_t lo = row_ptr[row], hi = row_ptr[row + 1] - 1;
+    // off-diagonals [lo, hi) in stored order, diagonal at dg
+    const int64_t lo = upper ? row_ptr[row] + 1 : row_ptr[row];
+    const int64_t hi = upper ? row_ptr[row + 1] : row_ptr[row + 1] - 1;
+    const int64_t dg = upper ? row_ptr[row] : row_ptr[row + 1] - 1;
     const int64_t base = slot[t] + int64_t(kLanes) * off;
     if (off < 0 || t0 > t || base < 0 || base + int64_t(kLanes) * (hi - lo) >= slots) {
         *err = 1;   // inconsistent layout: write nothing
         return;
     }
     word[base] = kHdrBit | uint32_t(row);
-    value[base] = val[hi];
+    value[base] = val[dg];
     for (int64_t e = lo; e < hi; e++) {
         const int32_t c = col[e];
-        const int32_t ic = inv[c];
+        const int32_t ic = inv[upper ? n - 1 - c : c];
         uint32_t w = uint32_t(c);
         // a parent inside the schedule order's task range is in this task
         if (ic >= t0 && t - ic < kRing) w = kIntBit | uint32_t(t - ic);
@@ -165,8 +171,8 @@ struct Scratch {
 
 }  // namespace
 
-int device_pack(const CsrView &A, const std::vector<int32_t> &perm, const PackLayout &lay, uint32_t *d_word,
-                double *d_value)
+int device_pack(const CsrView &A, const std::vector<int32_t> &perm, const PackLayout &lay, bool upper,
+                uint32_t *d_word, double *d_value)
 {
     const int64_t n = A.n, nnz = A.nnz, slots = lay.pk.slots;
     if (n == 0 || slots == 0) return GLTRSV_OK;
@@ -196,11 +202,12 @@ int device_pack(const CsrView &A, const std::vector<int32_t> &perm, const PackLa
     HIP_TRY(hipMemsetAsync(d_word, 0xFF, sizeof(uint32_t) * size_t(slots), s.st));   // padding words
     HIP_TRY(hipMemsetAsync(d_value, 0, sizeof(double) * size_t(slots), s.st));
     const unsigned rows_grid = unsigned((n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(pack_rows, dim3(rows_grid), dim3(kBlock), 0, s.st, d_perm, d_rp, n, d_inv, d_pre);
+    const int32_t up = upper ? 1 : 0;
+    hipLaunchKernelGGL(pack_rows, dim3(rows_grid), dim3(kBlock), 0, s.st, d_perm, d_rp, n, up, d_inv, d_pre);
     hipLaunchKernelGGL(scan_tiles, dim3(unsigned(tiles)), dim3(kBlock), 0, s.st, d_pre, n, d_tops);
     hipLaunchKernelGGL(scan_tops, dim3(1), dim3(kBlock), 0, s.st, d_tops, tiles);
     hipLaunchKernelGGL(pack_scatter, dim3(rows_grid), dim3(kBlock), 0, s.st, d_perm, d_inv, d_rp, d_col, d_val, d_pre,
-                       d_tops, d_slot, d_t0, n, slots, d_word, d_value, d_err);
+                       d_tops, d_slot, d_t0, n, up, slots, d_word, d_value, d_err);
     HIP_TRY(hipGetLastError());
     int32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s.st));

@@ -154,3 +154,40 @@ def test_auto_schedule_avoids_serial_grid_and_stays_valid():
         w = B.schedule(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT))
         assert (np.array_equal(core, g[0]) and np.array_equal(sup, g[1])) or \
                (np.array_equal(core, w[0]) and np.array_equal(sup, w[1]))
+
+
+def _uppers():
+    out = [gen.upper_of(m) for m in (gen.fig_1_1(), gen.fig_3_1(), gen.chain(300), gen.edgeless(500),
+                                      gen.stencil_2d5(25, 9))]
+    for s in range(6):
+        out.append(gen.upper_of(gen.random_lower(150, 0.02 + 0.02 * (s % 4), 40 + s, band=None if s % 2 else 5)))
+    out.append(gen.upper_of(gen.narrow_band(3000, 0.05, 20, 2)))
+    return out
+
+
+@pytest.mark.parametrize("pidx", [0, 2, 3, 4])
+def test_upper_growlocal_equals_oracle(pidx):
+    p = PARAMS[pidx]
+    for u in _uppers():
+        for nb in (1, 3):
+            o = B.default_opts(triangle=B.UPPER, blocks=nb, **p)
+            core, sup, S = B.schedule(u, o)
+            pi, sg, S2 = oracle.growlocal_upper(u, o.k, L=o.L, alpha0=o.alpha0, growth=o.growth, theta=o.accept,
+                                                nblocks=nb)
+            assert S == S2 and np.array_equal(core, pi) and np.array_equal(sup, sg), (u.name, nb)
+
+
+def test_upper_wavefront_and_layout_checks():
+    for u in _uppers():
+        core, sup, S = B.schedule(u, B.default_opts(triangle=B.UPPER, schedule_kind=B.SCHED_WAVEFRONT))
+        pi, sg, S2 = oracle.wavefront_schedule(oracle.mirror_upper(u))
+        assert S == S2 and np.array_equal(core, pi[::-1]) and np.array_equal(sup, sg[::-1])
+    low = gen.random_lower(50, 0.1, 3)
+    with pytest.raises(B.GltrsvError) as e:
+        B.schedule(low, B.default_opts(triangle=B.UPPER))
+    assert e.value.code == -2                      # entries below the diagonal
+    with pytest.raises(B.GltrsvError) as e:
+        B.schedule(gen.upper_of(low), B.default_opts())
+    assert e.value.code == -2                      # entries above the diagonal
+    with pytest.raises(B.GltrsvError):
+        B.schedule(low, B.default_opts(triangle=5))
