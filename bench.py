@@ -85,10 +85,11 @@ def measured_traffic(workload_name: str, kernel: str):
 def cpu_baseline(m, budget_s: float = 15.0):
     import oracle
     b = np.ones(m.n)
+    solve = oracle.solve_upper if m.meta.get("upper") else oracle.solve
     t0 = time.perf_counter()
     reps = 0
     while True:
-        oracle.solve(m, b)
+        solve(m, b)
         reps += 1
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 50:
@@ -115,6 +116,8 @@ def main():
                          "serve: Poisson request stream against resident plans; analysis: analysis time, "
                          "supersteps and solve time against the number of scheduling blocks")
     ap.add_argument("--blocks", default="1,2,4,8,16")
+    ap.add_argument("--triangle", default="lower", choices=["lower", "upper"],
+                    help="upper: backward substitution on the transpose of the workload")
     ap.add_argument("--systems", type=int, default=64)
     ap.add_argument("--pool", type=int, default=256)
     ap.add_argument("--rate", type=float, default=2000.0)
@@ -138,9 +141,16 @@ def main():
 
     t = time.time()
     m, desc = workload(args.workload)
+    upper = args.triangle == "upper"
+    if upper:   # backward substitution on the transpose
+        from paper_2503_05408_amd import gen
+        m = gen.upper_of(m)
+        desc = "transpose (upper triangle, backward substitution) of: " + desc
     log(f"workload {m.name}: n={m.n} nnz={m.nnz} generated in {time.time() - t:.1f} s")
     kind = {"wavefront": B.SCHED_WAVEFRONT, "auto": B.SCHED_AUTO}.get(args.schedule, B.SCHED_GROWLOCAL)
-    opts = B.default_opts(k=args.k, L=args.L, alpha0=args.alpha0, schedule_kind=kind)
+    opts = B.default_opts(k=args.k, L=args.L, alpha0=args.alpha0, schedule_kind=kind,
+                          triangle=B.UPPER if upper else B.LOWER)
+    solve_ref = oracle.solve_upper if upper else oracle.solve
     t = time.time()
     plan = B.Plan(m, opts)
     info = plan.info()
@@ -152,7 +162,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     # exactness gate
-    want = oracle.solve(m, np.ones(m.n))
+    want = solve_ref(m, np.ones(m.n))
     plan.solve(b, x)
     torch.cuda.synchronize()
     if plan.device_status() != 0:
@@ -268,8 +278,9 @@ def main():
     alg = algorithmic_bytes(m.n, m.nnz)
     kern_ms = float(np.mean(per))
     achieved = alg / (kern_ms * 1e-3) / 1e9
-    default_run = args.workload == "er1e7" and args.schedule == "growlocal"
-    traffic = measured_traffic(args.workload if default_run else f"{args.workload}_{args.schedule}",
+    default_run = args.workload == "er1e7" and args.schedule == "growlocal" and not upper
+    traffic = measured_traffic(args.workload if default_run else
+                               f"{args.workload}_{args.schedule}" + ("_upper" if upper else ""),
                                "trsv_persistent")
     out = {
         "metric": "reduced elements/sec (exact) at 1 MI355X vs plain launch; p50/p99 latency",
