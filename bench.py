@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--seconds", type=float, default=60.0)
     ap.add_argument("--quantum-us", type=float, default=200.0)
+    ap.add_argument("--async-exec", action="store_true",
+                    help="serve mode: semi-asynchronous execution (no superstep barriers)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solve has no multi-GPU path",
@@ -402,9 +404,11 @@ def bench_batch(args):
     bd = [torch.ones(m.n, dtype=torch.float64, device="cuda") for m in ms]
     xd = [torch.full((m.n,), float("nan"), dtype=torch.float64, device="cuda") for m in ms]
     best = None
-    for per_claim in (1, 2, 4):                       # claim size picked by measurement
+    timings = {}
+    for async_exec, per_claim in [(False, 1), (False, 2), (False, 4), (True, 1), (True, 2), (True, 4)]:
+        # execution form and claim size picked by measurement
         with torch.cuda.stream(stream):
-            bt = B.Batch(plans, per_claim=per_claim, use_graph=True)
+            bt = B.Batch(plans, per_claim=per_claim, use_graph=True, async_exec=async_exec)
             for _ in range(max(1, args.warmup)):
                 bt.solve(bd, xd, stream)
             stream.synchronize()
@@ -416,13 +420,23 @@ def bench_batch(args):
             stream.synchronize()
             ms_b = e0.elapsed_time(e1) / args.steps
             ok = bt.status() == 0
-        log(f"per_claim={per_claim}: {ms_b:.3f} ms status_ok={ok}")
+        form = "async" if async_exec else "bsp"
+        log(f"{form} per_claim={per_claim}: {ms_b:.3f} ms status_ok={ok}")
+        timings[f"{form}_claim{per_claim}_ms"] = ms_b
         if ok and (best is None or ms_b < best[1]):
-            best = (per_claim, ms_b, bt)
+            if best is not None:
+                best[2].close()
+            best = (per_claim, ms_b, bt, form)
         else:
             bt.close()
-    per_claim, ms_b, bt = best
-    exact = all(oracle.same_bits(x.cpu().numpy(), oracle.solve(m, np.ones(m.n))) for m, x in zip(ms, xd))
+    per_claim, ms_b, bt, form = best
+    for x in xd:
+        x.fill_(float("nan"))
+    with torch.cuda.stream(stream):
+        bt.solve(bd, xd, stream)
+        stream.synchronize()
+    exact = bt.status() == 0 and all(oracle.same_bits(x.cpu().numpy(), oracle.solve(m, np.ones(m.n)))
+                                     for m, x in zip(ms, xd))
 
     def seq(fn):
         with torch.cuda.stream(stream):
@@ -451,13 +465,15 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{len(ms)} independent systems, n = floor(10^U[3,6]), ER/NB/2-D/3-D mix, "
                                "one hipGraph-replayed persistent launch",
-                   "rows": rows, "nnz": sum(m.nnz for m in ms), "per_claim": per_claim,
+                   "rows": rows, "nnz": sum(m.nnz for m in ms), "per_claim": per_claim, "form": form,
                    "schedule": "auto (GrowLocal k=65536 L=50 alpha0=1, or wavefront)"},
+        "timings": timings,
         "exact": bool(exact),
         "plain_sequential_ms": ms_plain, "persistent_sequential_ms": ms_pers,
         "speedup_vs_plain": ms_plain / ms_b,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "trsv_batched",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "trsv_batched_async" if form == "async" else "trsv_batched",
                      "alg_bytes_per_launch": alg},
     }
     bt.close()
@@ -488,7 +504,8 @@ def bench_serve(args):
     lat, rows_done, checked, bad = [], 0, 0, 0
     backlog = []
     inflight = {}
-    with B.Server(quantum_us=args.quantum_us, max_slots=512, budget_bytes=8 << 30) as sv:
+    with B.Server(quantum_us=args.quantum_us, max_slots=512, budget_bytes=8 << 30,
+                  async_exec=int(args.async_exec)) as sv:
         t0 = B.clock_ns()
         arrival = t0 + np.cumsum(gaps) * 1e9
         end = t0 + args.seconds * 1e9
@@ -533,7 +550,7 @@ def bench_serve(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"Poisson {args.rate:g} requests/s for {args.seconds:g} s, pool of {len(ms)} "
                                "resident plans n = floor(10^U[0,6]) (ER/NB/2-D/3-D mix), b = ones",
-                   "quantum_us": args.quantum_us},
+                   "quantum_us": args.quantum_us, "form": "async" if args.async_exec else "bsp"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
         "requests": int(lat.size), "checked_exact": checked, "mismatches": bad,

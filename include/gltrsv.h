@@ -246,6 +246,13 @@ typedef struct gltrsv_batch_opts {
     int32_t grid_blocks;   /* 0 = occupancy-sized grid                        */
     int32_t use_graph;     /* 1: the reset + solve kernels are captured once
                               into a hipGraph per stream and replayed         */
+    int32_t async_exec;    /* 1: semi-asynchronous execution (as
+                              gltrsv_solve_async): no superstep barriers;
+                              chunks of each system claimed in order, at most
+                              four supersteps of average width ahead of the
+                              completed ones; x filled with the
+                              not-yet-computed mark first, so b[i] must not
+                              alias x[i] (EINVAL)                             */
 } gltrsv_batch_opts;
 
 void gltrsv_default_batch_opts(gltrsv_batch_opts *opts);
@@ -289,6 +296,9 @@ typedef struct gltrsv_server_opts {
     double quantum_us;      /* device time per launch before new admissions   */
     int32_t counter_words;  /* capacity of the per-superstep counter arena    */
     int32_t grid_blocks;    /* 0 = occupancy-sized grid                       */
+    int32_t async_exec;     /* 1: semi-asynchronous execution (see
+                               gltrsv_batch_opts.async_exec); a request's b
+                               must then not alias its x (EINVAL at submit)   */
 } gltrsv_server_opts;
 
 typedef struct gltrsv_server_stats {

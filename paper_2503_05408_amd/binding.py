@@ -54,12 +54,12 @@ class PlanOpts(ctypes.Structure):
 
 
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("per_claim", i32), ("grid_blocks", i32), ("use_graph", i32)]
+    _fields_ = [("per_claim", i32), ("grid_blocks", i32), ("use_graph", i32), ("async_exec", i32)]
 
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("budget_bytes", i64), ("max_slots", i32), ("per_claim", i32), ("quantum_us", dbl),
-                ("counter_words", i32), ("grid_blocks", i32)]
+                ("counter_words", i32), ("grid_blocks", i32), ("async_exec", i32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -358,11 +358,13 @@ def _ptr_array(tensors, n_of):
 class Batch:
     """Several plans solved together in one persistent launch."""
 
-    def __init__(self, plans, per_claim: int = 1, use_graph: bool = True, grid_blocks: int = 0):
+    def __init__(self, plans, per_claim: int = 1, use_graph: bool = True, grid_blocks: int = 0,
+                 async_exec: bool = False):
         self.plans = list(plans)
         o = BatchOpts()
         load().gltrsv_default_batch_opts(ctypes.byref(o))
         o.per_claim, o.use_graph, o.grid_blocks = int(per_claim), int(bool(use_graph)), int(grid_blocks)
+        o.async_exec = int(bool(async_exec))
         handles = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
         ptr = ctypes.c_void_p()
         _check(load().gltrsv_batch_create(handles, len(self.plans), ctypes.byref(o), ctypes.byref(ptr)),

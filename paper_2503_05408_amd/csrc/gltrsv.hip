@@ -682,6 +682,112 @@ __global__ __launch_bounds__(kBlock) void gather_probe(const uint32_t *__restric
     if (row >= 0) y[row] = acc;
 }
 
+// ---------------------------------------------------------------------------
+// Semi-asynchronous batched solve.  Per system one 64-bit word: low half =
+// chunks claimed, high half = chunks completed.  Chunks are claimed in order
+// (an atomic add on the low half), at most `window` ahead of the completed
+// ones, and run with per-row readiness (await_batch) instead of barriers.
+// Progress needs no co-residency: the earliest unfinished chunk of a system
+// depends only on finished chunks and is held by a running wave, since claims
+// are made by running waves in order and a wave runs its claims in order.
+// A wave leaves when no system has an unclaimed chunk (its claimed chunks are
+// done by then), or once the quantum has passed (claimed chunks are always
+// completed, so a later launch continues from the words).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void fill_unready_sys(const SysDesc *__restrict__ sys, int32_t count)
+{
+    const int32_t i = int32_t(blockIdx.y);
+    if (i >= count) return;
+    unsigned long long *x = reinterpret_cast<unsigned long long *>(sys[i].x);
+    const int64_t n = sys[i].n;
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    for (int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x; r < n; r += stride) x[r] = kUnready;
+}
+
+__global__ __launch_bounds__(kBlock) void trsv_batched_async(const SysDesc *__restrict__ sys, int32_t count,
+                                                             unsigned long long *state, uint32_t *finished,
+                                                             int32_t *err, int64_t spin_limit, int32_t per_claim,
+                                                             int64_t quantum)
+{
+    __shared__ double ring[kRing + 1][kBlock];
+    __shared__ uint32_t done_mask[kMaskSystems / 32];   // systems with every chunk claimed
+    for (int q = threadIdx.x; q < kMaskSystems / 32; q += kBlock) done_mask[q] = 0u;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int32_t wave = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
+    int32_t home = count > 0 ? wave % count : 0;
+    const int64_t deadline = quantum > 0 ? int64_t(wall_clock64()) + quantum : -1;
+    int32_t nap = 1;
+    int64_t idle = 0;
+    for (;;) {
+        int32_t found = -1, c0 = 0, c1 = 0, open = 0;
+        const bool late = deadline >= 0 && int64_t(wall_clock64()) > deadline;
+        if (lane == 0) {
+            for (int32_t t = 0; t < count && found < 0 && !late; t++) {
+                const int32_t i = home + t < count ? home + t : home + t - count;
+                if (i < kMaskSystems && (done_mask[i >> 5] >> (i & 31)) & 1u) continue;
+                const int32_t nch = sys[i].nchunks;
+                const unsigned long long st = __hip_atomic_load(state_word(state, i), __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+                const int64_t claimed = int64_t(st & 0xffffffffull), done = int64_t(st >> 32);
+                if (claimed >= nch) {
+                    if (i < kMaskSystems) atomicOr(&done_mask[i >> 5], 1u << (i & 31));
+                    continue;
+                }
+                open++;
+                if (claimed - done >= sys[i].window) continue;   // far enough ahead
+                const unsigned long long got = __hip_atomic_fetch_add(
+                    state_word(state, i), (unsigned long long)per_claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int64_t g = int64_t(got & 0xffffffffull);
+                if (g < nch) {
+                    found = i;
+                    c0 = int32_t(g);
+                    c1 = int32_t(min<int64_t>(g + per_claim, nch));
+                }
+            }
+        }
+        found = __shfl(found, 0);
+        if (found < 0) {
+            int32_t quit = 0;
+            if (lane == 0) {
+                quit = late || open == 0 || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                if (!quit) {   // every open system is a window ahead: wait for completions
+                    for (int32_t k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(2);
+                    nap = min(2 * nap, int32_t(kIdleNapMax));
+                    if (++idle > spin_limit) {
+                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        quit = 1;
+                    }
+                }
+            }
+            if (__shfl(quit, 0)) return;
+            continue;
+        }
+        c0 = __shfl(c0, 0);
+        c1 = __shfl(c1, 0);
+        nap = 1;
+        idle = 0;
+        home = found;
+        const SysDesc d = sys[found];
+        for (int32_t c = c0; c < c1; c++) {
+            const LaneCursor cur = make_cursor(d.word, d.value, d.chunk_base[c], d.chunk_len[c], lane);
+            Batch b0, b1;
+            load_batch(cur, 0, b0);
+            load_batch(cur, kUnroll, b1);
+            run_lane<true>(cur, b0, b1, d.b, d.x, ring, err, spin_limit);
+        }
+        // the chunks' x stores are complete before they are counted as done
+        __builtin_amdgcn_s_waitcnt(0);
+        if (lane == 0) {
+            const unsigned long long old = __hip_atomic_fetch_add(
+                state_word(state, found), (unsigned long long)(c1 - c0) << 32, __ATOMIC_RELAXED,
+                __HIP_MEMORY_SCOPE_AGENT);
+            if (int64_t(old >> 32) + (c1 - c0) == d.nchunks)
+                __hip_atomic_fetch_add(finished, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 // Plain copy of 16-byte elements, grid-stride: the achievable-bandwidth
 // reference and the calibration kernel of the memory-traffic counters.
 __global__ __launch_bounds__(kBlock) void copy_probe(const double2 *__restrict__ src, double2 *__restrict__ dst,
@@ -834,6 +940,7 @@ struct gltrsv_batch {
     hipStream_t last_stream = nullptr;
     int64_t idle_ticks = 1000000000;   // 10 s of the 100 MHz wall clock
     int32_t keep_waves = 0;            // waves that never retire (see dev::kRetireTicks)
+    bool async_exec = false;           // semi-asynchronous kernel (no barriers)
 };
 
 extern "C" {
@@ -1303,6 +1410,7 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
     bt->device = dev_id;
     bt->ncalls = count;
     bt->per_claim = opts->per_claim;
+    bt->async_exec = opts->async_exec != 0;
     bt->use_graph = opts->use_graph != 0;
     for (int32_t i = 0; i < count; i++) {
         if (!plans[i]) {
@@ -1350,6 +1458,9 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
             d.x = nullptr;
             d.S = pl->S;
             d.done_off = off;
+            d.nchunks = int32_t(pl->chunks);
+            d.window = dev::async_window(pl->chunks, pl->S);
+            d.n = pl->n;
             off += pl->S;
         }
     }
@@ -1373,6 +1484,21 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
 
 static int batch_enqueue(gltrsv_batch *bt, hipStream_t st)
 {
+    if (bt->async_exec) {
+        int64_t widest_n = 1;
+        for (auto *pl : bt->plans) widest_n = std::max(widest_n, pl->n);
+        const unsigned gx = unsigned(std::min<int64_t>(256, (widest_n + dev::kBlock - 1) / dev::kBlock));
+        hipLaunchKernelGGL(dev::fill_unready_sys, dim3(gx, unsigned(bt->count)), dim3(dev::kBlock), 0, st, bt->d_desc,
+                           bt->count);
+        hipLaunchKernelGGL(dev::batch_reset, dim3(unsigned(std::max(1, (bt->count + dev::kBlock - 1) / dev::kBlock))),
+                           dim3(dev::kBlock), 0, st, bt->d_state, bt->d_done, bt->count, 0, bt->d_finished,
+                           bt->d_err);
+        hipLaunchKernelGGL(dev::trsv_batched_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st, bt->d_desc,
+                           bt->count, bt->d_state, bt->d_finished, bt->d_err, int64_t(5000000), bt->per_claim,
+                           int64_t(0));
+        HIP_TRY(hipGetLastError());
+        return GLTRSV_OK;
+    }
     hipLaunchKernelGGL(dev::batch_reset, dim3(unsigned(std::max(1, (bt->count + dev::kBlock - 1) / dev::kBlock))),
                        dim3(dev::kBlock), 0, st, bt->d_state, bt->d_done, bt->count, bt->ndone, bt->d_finished,
                        bt->d_err);
@@ -1395,6 +1521,8 @@ int gltrsv_batch_solve(gltrsv_batch *bt, const double *const *b, double *const *
     for (int32_t i = 0; i < bt->count; i++) {
         const int32_t j = bt->slot[i];
         if (!b[j] || !x[j]) return set_error(GLTRSV_EINVAL, "null vector in batch");
+        if (bt->async_exec && b[j] == x[j])
+            return set_error(GLTRSV_EINVAL, "semi-asynchronous batches need b and x apart");
         bt->h_desc[k][i].b = b[j];
         bt->h_desc[k][i].x = x[j];
     }

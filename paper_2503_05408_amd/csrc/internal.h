@@ -63,10 +63,30 @@ struct SysDesc {
     double *x;
     int32_t S;
     int32_t done_off;   // first per-superstep done counter of this system
+    int32_t nchunks;    // chunks of all supersteps
+    int32_t window;     // semi-asynchronous launches: chunks claimed ahead of the completed ones
+    int64_t n;          // rows
 };
+
+// Chunks a semi-asynchronous batched launch lets one system have in flight:
+// about four supersteps of its average width.
+inline int32_t async_window(int64_t chunks, int32_t S)
+{
+    const int64_t avg = S > 0 ? (chunks + S - 1) / S : 1;
+    return int32_t(std::max<int64_t>(8, std::min<int64_t>(int64_t(1) << 30, 4 * avg)));
+}
 
 __global__ void batch_reset(unsigned long long *state, uint32_t *done, int32_t count, int32_t ndone,
                             uint32_t *finished, int32_t *err);
+// Semi-asynchronous batched launches: x of every system filled with the
+// not-yet-computed mark, then chunks claimed in order per system.
+// state[i * kStateStride]: low half = chunks claimed, high half = chunks done.
+__global__ void fill_unready_sys(const SysDesc *__restrict__ sys, int32_t count);
+__global__ void trsv_batched_async(const SysDesc *__restrict__ sys, int32_t count, unsigned long long *state,
+                                   uint32_t *finished, int32_t *err, int64_t spin_limit, int32_t per_claim,
+                                   int64_t quantum);
+__global__ void fill_unready(unsigned long long *x, int64_t n);
+
 // Fills the plan's stream (d_word, d_value: lay.pk.slots entries) on the
 // device from A, the schedule order and the host layout; synchronous.
 // upper: A is upper-triangular and perm lists vertices of its mirror (row

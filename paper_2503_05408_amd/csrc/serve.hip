@@ -142,15 +142,28 @@ int run_quantum(gltrsv_server *sv, int32_t used, int32_t busy)
         HIP_TRY(hipMemsetAsync(sv->d_state + size_t(i) * dev::kStateStride, 0, sizeof(unsigned long long),
                                sv->stream));
         HIP_TRY(hipMemsetAsync(sv->d_done + sl.done_off, 0, sizeof(uint32_t) * size_t(sl.req.plan->S), sv->stream));
+        if (sv->opts.async_exec && sl.busy && sl.req.plan->n > 0) {
+            // semi-asynchronous: x starts as the not-yet-computed mark
+            const int64_t n = sl.req.plan->n;
+            const unsigned blocks = unsigned(std::min<int64_t>(1024, (n + dev::kBlock - 1) / dev::kBlock));
+            hipLaunchKernelGGL(dev::fill_unready, dim3(blocks), dim3(dev::kBlock), 0, sv->stream,
+                               reinterpret_cast<unsigned long long *>(sl.req.x), n);
+        }
     }
     HIP_TRY(hipMemsetAsync(sv->d_finished, 0, 2 * sizeof(uint32_t), sv->stream));
     int64_t widest = 0;
     for (int32_t i = 0; i < used; i++)
         if (sv->slots[i].busy) widest = std::max(widest, sv->slots[i].req.plan->widest);
     const int64_t quantum = int64_t(sv->opts.quantum_us * 100.0);   // 100 MHz wall clock
-    hipLaunchKernelGGL(dev::trsv_batched, dim3(unsigned(sv->grid)), dim3(dev::kBlock), 0, sv->stream, sv->d_desc, used,
-                       sv->d_state, sv->d_done, sv->d_finished, sv->d_err, int64_t(1000000000), sv->opts.per_claim,
-                       busy, std::max<int64_t>(quantum, 1), dev::keep_waves_for(widest, sv->opts.per_claim, sv->grid));
+    if (sv->opts.async_exec)
+        hipLaunchKernelGGL(dev::trsv_batched_async, dim3(unsigned(sv->grid)), dim3(dev::kBlock), 0, sv->stream,
+                           sv->d_desc, used, sv->d_state, sv->d_finished, sv->d_err, int64_t(5000000),
+                           sv->opts.per_claim, std::max<int64_t>(quantum, 1));
+    else
+        hipLaunchKernelGGL(dev::trsv_batched, dim3(unsigned(sv->grid)), dim3(dev::kBlock), 0, sv->stream, sv->d_desc,
+                           used, sv->d_state, sv->d_done, sv->d_finished, sv->d_err, int64_t(1000000000),
+                           sv->opts.per_claim, busy, std::max<int64_t>(quantum, 1),
+                           dev::keep_waves_for(widest, sv->opts.per_claim, sv->grid));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpy2DAsync(sv->h_state, sizeof(unsigned long long), sv->d_state,
                              sizeof(unsigned long long) * dev::kStateStride, sizeof(unsigned long long), size_t(used),
@@ -201,6 +214,9 @@ void worker_main(gltrsv_server *sv)
                 d.x = r.x;
                 d.S = r.plan->S;
                 d.done_off = off;
+                d.nchunks = int32_t(r.plan->chunks);
+                d.window = dev::async_window(r.plan->chunks, r.plan->S);
+                d.n = r.plan->n;
                 sv->queue.pop_front();
             }
             for (int32_t i = 0; i < int32_t(sv->slots.size()); i++)
@@ -235,7 +251,9 @@ void worker_main(gltrsv_server *sv)
         for (int32_t i = 0; i < used; i++) {
             Slot &sl = sv->slots[i];
             if (!sl.busy) continue;
-            if (int32_t(sv->h_state[i] >> 32) >= sl.req.plan->S) {
+            // complete: the open superstep passed S, or (semi-asynchronous) every chunk is done
+            const int64_t hi = int64_t(sv->h_state[i] >> 32);
+            if (sv->opts.async_exec ? hi >= sl.req.plan->chunks : hi >= sl.req.plan->S) {
                 sv->completed.emplace_back(sl.req.ticket, t);
                 sv->stats.completed++;
                 sv->stats.rows_completed += sl.req.plan->n;
@@ -243,6 +261,7 @@ void worker_main(gltrsv_server *sv)
                 sv->arena->give(sl.done_off, std::max(1, sl.req.plan->S));
                 sl.busy = false;
                 sv->h_desc[i].S = 0;
+                sv->h_desc[i].nchunks = 0;
                 sl.fresh = true;   // upload the emptied descriptor with the next launch
             }
         }
@@ -317,7 +336,9 @@ int gltrsv_server_submit(gltrsv_server *sv, gltrsv_plan *plan, const double *b, 
     if (!sv || !plan || !ticket || (plan->n && (!b || !x))) return set_error(GLTRSV_EINVAL, "null argument");
     if (plan->device != sv->device) return set_error(GLTRSV_EINVAL, "plan lives on another device");
     if (plan->S > sv->opts.counter_words) return set_error(GLTRSV_ERANGE, "plan has more supersteps than counters");
-    const int64_t bytes = 16 * plan->n + 4 * int64_t(std::max(1, plan->S)) + int64_t(sizeof(dev::SysDesc));
+    if (sv->opts.async_exec && plan->n && b == x)
+        return set_error(GLTRSV_EINVAL, "semi-asynchronous server: b must not alias x");
+    const int64_t bytes = 16 * plan->n + 4 * int64_t(std::max(1, plan->S)) + 64;   // b, x, counters, slot
     std::lock_guard<std::mutex> g(sv->mu);
     if (sv->failure) return set_error(sv->failure, sv->failure_text);
     if (bytes > sv->opts.budget_bytes) return set_error(GLTRSV_ERANGE, "request larger than the whole budget");

@@ -32,14 +32,15 @@ def plans():
         p.close()
 
 
+@pytest.mark.parametrize("async_exec", [False, True])
 @pytest.mark.parametrize("per_claim", [1, 4])
 @pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_matches_oracle(plans, per_claim, use_graph):
+def test_batch_matches_oracle(plans, per_claim, use_graph, async_exec):
     import torch
     ms, ps = plans
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        with B.Batch(ps, per_claim=per_claim, use_graph=use_graph) as bt:
+        with B.Batch(ps, per_claim=per_claim, use_graph=use_graph, async_exec=async_exec) as bt:
             assert bt.info()["systems"] == len(ps)
             for rep in range(3):
                 bs = [gen.rhs_uniform(m.n, 100 * rep + i) for i, m in enumerate(ms)]
@@ -80,5 +81,32 @@ def test_batch_mix_small():
         assert bt.status() == 0
     for i, m in enumerate(ms):
         assert oracle.same_bits(xd[i].cpu().numpy(), oracle.solve(m, bs[i])), m.name
+    for p in ps:
+        p.close()
+
+
+def test_async_batch_rejects_in_place(plans):
+    import torch
+    ms, ps = plans
+    xd = [torch.from_numpy(gen.rhs_ones(m.n)).cuda() for m in ms]
+    with B.Batch(ps, async_exec=True) as bt:
+        with pytest.raises(B.GltrsvError):
+            bt.solve(xd, xd)
+
+
+def test_async_batch_mix_small():
+    import torch
+    ms = gen.batch_mix(12, lo_exp=2.0, hi_exp=4.0)
+    ps = [B.Plan(m, B.gpu_opts(schedule_kind=B.SCHED_AUTO)) for m in ms]
+    bs = [gen.rhs_uniform(m.n, i) for i, m in enumerate(ms)]
+    bd = [torch.from_numpy(b).cuda() for b in bs]
+    xd = [torch.empty_like(b) for b in bd]
+    for per_claim in (1, 3):
+        with B.Batch(ps, per_claim=per_claim, async_exec=True) as bt:
+            bt.solve(bd, xd)
+            torch.cuda.synchronize()
+            assert bt.status() == 0
+        for i, m in enumerate(ms):
+            assert oracle.same_bits(xd[i].cpu().numpy(), oracle.solve(m, bs[i])), (m.name, per_claim)
     for p in ps:
         p.close()

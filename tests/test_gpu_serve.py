@@ -35,13 +35,14 @@ def drain(server, pending, timeout=30.0):
     return done
 
 
+@pytest.mark.parametrize("async_exec", [0, 1])
 @pytest.mark.parametrize("quantum_us", [50.0, 400.0])
-def test_mixed_requests_match_oracle_and_alone(pool, quantum_us):
+def test_mixed_requests_match_oracle_and_alone(pool, quantum_us, async_exec):
     import torch
     ms, plans = pool
     rng = np.random.default_rng(7)
     reqs = []
-    with B.Server(quantum_us=quantum_us, max_slots=16) as sv:
+    with B.Server(quantum_us=quantum_us, max_slots=16, async_exec=async_exec) as sv:
         for r in range(60):
             i = int(rng.integers(0, len(ms)))
             b = gen.rhs_uniform(ms[i].n, 1000 + r)
