@@ -227,6 +227,27 @@ def main():
     if plan.device_status() != 0:
         exact_async = False
 
+    # several right-hand sides per pass (SpTRSM): columns x rows per second
+    multi = {}
+    for nrhs in (4, 8):
+        Bm = torch.ones(m.n, nrhs, dtype=torch.float64, device="cuda")
+        Xm = torch.empty_like(Bm)
+        plan.solve_multi(Bm, Xm)
+        torch.cuda.synchronize()
+        ok = plan.device_status() == 0 and all(oracle.same_bits(Xm[:, r].cpu().numpy(), want) for r in (0, nrhs - 1))
+        q0 = torch.cuda.Event(enable_timing=True)
+        q1 = torch.cuda.Event(enable_timing=True)
+        q0.record(stream)
+        reps = max(1, args.steps // 4)
+        for _ in range(reps):
+            plan.solve_multi(Bm, Xm)
+        q1.record(stream)
+        torch.cuda.synchronize()
+        ms_m = q0.elapsed_time(q1) / reps
+        multi[str(nrhs)] = {"ms_per_step": ms_m, "exact": bool(ok),
+                            "rhs_rows_per_s": (m.n * nrhs / (ms_m * 1e-3)) if ok else 0.0}
+        del Bm, Xm
+
     # plain form with its S launches captured once in a hipGraph and replayed
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
@@ -311,6 +332,7 @@ def main():
         "plain": {"value": rows_s_plain, "ms_per_step": ms_plain, "launches_per_step": info["supersteps"],
                   "graph_ms_per_step": ms_graph},
         "speedup_vs_plain": (ms_plain / ms) if ms > 0 else None,
+        "multi_rhs": multi,
         "async": {"ms_per_step": ms_async, "exact": bool(exact_async),
                   "value": (m.n / (ms_async * 1e-3)) if exact_async else 0.0},
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),

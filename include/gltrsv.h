@@ -344,6 +344,16 @@ int gltrsv_server_destroy(gltrsv_server *server);
  * gltrsv_plan_device_status (GLTRSV_ETIMEDOUT). */
 int gltrsv_solve_async(gltrsv_plan *plan, const double *b, double *x, void *stream);
 
+/* Several right-hand sides (SpTRSM): solves A X = B for nrhs columns, B and X
+ * row-major n x nrhs (element (i, r) at [i * nrhs + r]), device memory,
+ * original numbering, not overlapping (EINVAL).  Column r of X is bit-for-bit
+ * the gltrsv_solve result for column r of B.  Semi-asynchronous (as
+ * gltrsv_solve_async); each launch walks the stream once for up to 4
+ * columns, so the matrix bytes and the gathers' memory requests are shared
+ * by those columns.  Asynchronous on `stream`; errors are reported by
+ * gltrsv_plan_device_status. */
+int gltrsv_solve_multi(gltrsv_plan *plan, const double *b, double *x, int32_t nrhs, void *stream);
+
 /* Plain device-to-device copy of `bytes` (a multiple of 16) from src to dst
  * (device pointers, caller-owned, non-overlapping), asynchronous on `stream`.
  * The achievable-bandwidth reference for the solve kernels and the

@@ -101,6 +101,7 @@ SIGNATURES = {
     "gltrsv_copy_probe": ([P, P, i64, P], i32),
     "gltrsv_plan_gather_probe": ([P, P, P, P], i32),
     "gltrsv_solve_async": ([P, P, P, P], i32),
+    "gltrsv_solve_multi": ([P, P, P, i32, P], i32),
     "gltrsv_plan_stream": ([P, P, P, i64], i32),
     "gltrsv_default_batch_opts": ([P], None),
     "gltrsv_batch_create": ([P, i32, P, P], i32),
@@ -303,6 +304,20 @@ class Plan:
             x = torch.empty_like(b)
         _check(load().gltrsv_solve_async(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
                "gltrsv_solve_async")
+        return x
+
+    def solve_multi(self, b, x=None, stream=None):
+        """Several right-hand sides: b and x are (n, nrhs) row-major CUDA
+        float64 tensors; column r of x solves column r of b."""
+        import torch
+        if b.dim() != 2 or b.shape[0] != self.n or not b.is_contiguous() or b.dtype != torch.float64:
+            raise ValueError("b must be a contiguous (n, nrhs) float64 tensor")
+        if x is None:
+            x = torch.empty_like(b)
+        if x.shape != b.shape or not x.is_contiguous():
+            raise ValueError("x must match b")
+        _check(load().gltrsv_solve_multi(self._p, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                         int(b.shape[1]), _stream_ptr(stream)), "gltrsv_solve_multi")
         return x
 
     def solve_plain(self, b, x=None, stream=None):

@@ -470,6 +470,171 @@ __global__ __launch_bounds__(kBlock) void trsv_async(const uint32_t *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Several right-hand sides at once (SpTRSM): B and X are row-major n x ld,
+// a launch handles R consecutive columns.  Each lane runs its task once for
+// all R columns: one pass over the stream, and the R values of a gathered
+// column lie next to each other in memory.  Per column the operations and
+// their order are exactly those of the one-column solve.  Semi-asynchronous
+// (per-row readiness, as trsv_async); one wave per workgroup keeps the
+// R-column ring of recent rows within LDS.
+// ---------------------------------------------------------------------------
+template <int R>
+struct MultiState {
+    double acc[R], last_y[R];
+    double diag;
+    int32_t cur;
+    uint32_t pos;
+};
+
+template <int R>
+using MultiRing = double (*)[R][64];
+
+template <int R>
+__device__ __forceinline__ void gather_multi(const Batch &B, const double *b, const double *x, int64_t ld,
+                                             double (&g)[kUnroll][R])
+{
+#pragma unroll
+    for (int j = 0; j < kUnroll; j++) {
+        const uint32_t c = B.w[j];
+        const bool ext = (c & (HDR | INTL)) == 0;
+        const bool hdr = (c & HDR) && c != PAD;
+        const double *src = ext ? x + int64_t(c) * ld : (hdr ? b + int64_t(c & MASK) * ld : b);
+#pragma unroll
+        for (int r = 0; r < R; r++) g[j][r] = load_x(src + r);
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void await_multi(const Batch &B, double (&g)[kUnroll][R], const double *x, int64_t ld,
+                                            int32_t *err, int64_t spin_limit)
+{
+    bool miss = false;
+#pragma unroll
+    for (int j = 0; j < kUnroll; j++)
+#pragma unroll
+        for (int r = 0; r < R; r++) miss |= unready(B.w[j], g[j][r]);
+    if (__ballot(miss) == 0ull) return;
+    for (int64_t spins = 1;; spins++) {
+        __builtin_amdgcn_s_sleep(1);
+        miss = false;
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++)
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                if (unready(B.w[j], g[j][r])) g[j][r] = load_x(x + int64_t(B.w[j]) * ld + r);
+                miss |= unready(B.w[j], g[j][r]);
+            }
+        if (__ballot(miss) == 0ull) return;
+        if (spins > spin_limit) {
+            if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    }
+}
+
+// process_batch for R columns: the same branch-free sequence per column.
+template <int R>
+__device__ __forceinline__ void process_multi(const Batch &B, const double (&g)[kUnroll][R], MultiState<R> &st,
+                                              double *x, int64_t ld, MultiRing<R> ring)
+{
+    const int lane = threadIdx.x & 63;
+    double ys[kUnroll][R];
+    int32_t yrow[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; j++) {
+        const uint32_t c = B.w[j];
+        const bool hdr = (c & HDR) != 0;
+        const bool intl = (c >> 30) == 1u;
+        const bool fin = hdr && st.cur >= 0;
+        const uint32_t slot = fin ? (st.pos % kRing) : kRing;
+        yrow[j] = fin ? st.cur : -1;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const double y = st.acc[r] / st.diag;
+            ys[j][r] = y;
+            st.last_y[r] = fin ? y : st.last_y[r];
+            ring[slot][r][lane] = y;
+        }
+        st.pos += fin ? 1u : 0u;
+        const uint32_t back = c & MASK;
+        const uint32_t rs = (st.pos - back) % kRing;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            double xv = g[j][r];
+            if (intl && back >= 2u) xv = ring[rs][r][lane];
+            xv = (intl && back == 1u) ? st.last_y[r] : xv;
+            const double prod = B.v[j] * xv;
+            const double nacc = st.acc[r] - prod;
+            st.acc[r] = hdr ? g[j][r] : nacc;
+        }
+        st.diag = hdr ? B.v[j] : st.diag;
+        st.cur = hdr ? (c == PAD ? -1 : int32_t(back)) : st.cur;
+    }
+#pragma unroll
+    for (int j = 0; j < kUnroll; j++)
+        if (yrow[j] >= 0)
+#pragma unroll
+            for (int r = 0; r < R; r++) store_x(x + int64_t(yrow[j]) * ld + r, ys[j][r]);
+}
+
+template <int R>
+__device__ __forceinline__ void run_lane_multi(const LaneCursor &cur, const double *b, double *x, int64_t ld,
+                                               MultiRing<R> ring, int32_t *err, int64_t spin_limit)
+{
+    MultiState<R> st;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        st.acc[r] = 0.0;
+        st.last_y[r] = 0.0;
+    }
+    st.diag = 1.0;
+    st.cur = -1;
+    st.pos = 0;
+    Batch now, nxt;
+    double gnow[kUnroll][R], gnxt[kUnroll][R];
+    load_batch(cur, 0, now);
+    gather_multi<R>(now, b, x, ld, gnow);
+    for (int32_t t0 = 0; t0 < cur.len; t0 += kUnroll) {
+        load_batch(cur, t0 + kUnroll, nxt);
+        gather_multi<R>(nxt, b, x, ld, gnxt);
+        await_multi<R>(now, gnow, x, ld, err, spin_limit);
+        process_multi<R>(now, gnow, st, x, ld, ring);
+        now = nxt;
+#pragma unroll
+        for (int j = 0; j < kUnroll; j++)
+#pragma unroll
+            for (int r = 0; r < R; r++) gnow[j][r] = gnxt[j][r];
+    }
+    if (st.cur >= 0)
+#pragma unroll
+        for (int r = 0; r < R; r++) store_x(x + int64_t(st.cur) * ld + r, st.acc[r] / st.diag);
+}
+
+template <int R>
+__global__ __launch_bounds__(64) void trsv_async_multi(const uint32_t *__restrict__ word,
+                                                       const double *__restrict__ value,
+                                                       const int64_t *__restrict__ chunk_base,
+                                                       const int32_t *__restrict__ chunk_len, int32_t chunks,
+                                                       const double *b, double *x, int64_t ld, int32_t *err,
+                                                       int64_t spin_limit)
+{
+    __shared__ double ring[kRing + 1][R][64];
+    const int lane = threadIdx.x & 63;
+    for (int32_t c = int32_t(blockIdx.x); c < chunks; c += int32_t(gridDim.x)) {
+        const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
+        run_lane_multi<R>(cur, b, x, ld, ring, err, spin_limit);
+    }
+}
+
+template __global__ void trsv_async_multi<1>(const uint32_t *, const double *, const int64_t *, const int32_t *,
+                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t);
+template __global__ void trsv_async_multi<2>(const uint32_t *, const double *, const int64_t *, const int32_t *,
+                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t);
+template __global__ void trsv_async_multi<4>(const uint32_t *, const double *, const int64_t *, const int32_t *,
+                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t);
+
+// ---------------------------------------------------------------------------
 // Batched solve: many independent systems in one launch.
 //
 // Every system i has a 64-bit state word: high half = its open superstep,
@@ -1297,6 +1462,37 @@ int gltrsv_solve_async(gltrsv_plan *p, const double *b, double *x, void *stream)
                            p->d_chunk_base, p->d_chunk_len, chunks, bb, x, p->d_err, lim);
     }
     HIP_TRY(hipGetLastError());
+    p->last_stream = st;
+    return GLTRSV_OK;
+}
+
+int gltrsv_solve_multi(gltrsv_plan *p, const double *b, double *x, int32_t nrhs, void *stream)
+{
+    if (!p || nrhs < 1 || (p->n && (!b || !x))) return set_error(GLTRSV_EINVAL, "bad argument");
+    if (p->n == 0) return GLTRSV_OK;
+    const int64_t total = p->n * int64_t(nrhs);
+    if (b < x + total && x < b + total) return set_error(GLTRSV_EINVAL, "B and X must not overlap");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t fill_blocks = std::min<int64_t>(4096, (total + dev::kBlock - 1) / dev::kBlock);
+    hipLaunchKernelGGL(dev::fill_unready, dim3(unsigned(fill_blocks)), dim3(dev::kBlock), 0, st,
+                       reinterpret_cast<unsigned long long *>(x), total);
+    const int32_t chunks = int32_t(p->chunks);
+    const unsigned grid = unsigned(std::min<int64_t>(int64_t(p->grid_async) * dev::kWavesPerBlock, chunks));
+    const int64_t ld = nrhs;
+    for (int32_t r0 = 0; r0 < nrhs;) {
+        const int32_t R = nrhs - r0 >= 4 ? 4 : (nrhs - r0 >= 2 ? 2 : 1);
+        if (R == 4)
+            hipLaunchKernelGGL(dev::trsv_async_multi<4>, dim3(grid), dim3(64), 0, st, p->d_word, p->d_value,
+                               p->d_chunk_base, p->d_chunk_len, chunks, b + r0, x + r0, ld, p->d_err, p->spin_limit);
+        else if (R == 2)
+            hipLaunchKernelGGL(dev::trsv_async_multi<2>, dim3(grid), dim3(64), 0, st, p->d_word, p->d_value,
+                               p->d_chunk_base, p->d_chunk_len, chunks, b + r0, x + r0, ld, p->d_err, p->spin_limit);
+        else
+            hipLaunchKernelGGL(dev::trsv_async_multi<1>, dim3(grid), dim3(64), 0, st, p->d_word, p->d_value,
+                               p->d_chunk_base, p->d_chunk_len, chunks, b + r0, x + r0, ld, p->d_err, p->spin_limit);
+        HIP_TRY(hipGetLastError());
+        r0 += R;
+    }
     p->last_stream = st;
     return GLTRSV_OK;
 }
