@@ -334,3 +334,121 @@ def same_bits(a, b) -> bool:
         return False
     ia, ib = a.view(np.uint64), b.view(np.uint64)
     return bool(np.array_equal(ia[~na], ib[~nb]))
+
+
+# ---------------------------------------------------------------------------
+# Funnel coarsening (Sec. 4)
+# ---------------------------------------------------------------------------
+
+def _parents_children(m):
+    """Parent and child lists of the DAG of a lower-triangular CSR (edge
+    (j, i) for every stored off-diagonal A_ij)."""
+    rp, c, _ = _csr(m)
+    parents = [sorted({int(j) for j in c[rp[i]:rp[i + 1] - 1]}) for i in range(m.n)]
+    children = [[] for _ in range(m.n)]
+    for i in range(m.n):
+        for j in parents[i]:
+            children[j].append(i)
+    return parents, children
+
+
+def transitive_reduction(m):
+    """Approximate transitive reduction of Sec. 4.2 ("remove all long edges
+    in triangles"): an edge (u, w) is removed when some v has edges (u, v)
+    and (v, w) in the original DAG.  Returns the kept parent lists."""
+    parents, children = _parents_children(m)
+    kept = []
+    for w in range(m.n):
+        pw = set(parents[w])
+        kept.append([u for u in parents[w] if not any(v in pw for v in children[u])])
+    return kept
+
+
+def funnel_partition(m, max_weight):
+    """In-funnel coarsening, Algorithm 4.1, on the transitively reduced DAG.
+    Vertices are visited in reverse topological order (n-1 down to 0); the
+    priority queue pops the largest vertex ID first; a parent joins once all
+    of its children are in the part; a popped vertex that would lift the
+    part's weight (stored entries of the rows) above max_weight is left out
+    (it starts or joins a later part).  Returns part[v], parts numbered by
+    their root (the vertex the part grew from) in rising order."""
+    import heapq
+    rp, _, _ = _csr(m)
+    w_of = [int(rp[i + 1] - rp[i]) for i in range(m.n)]
+    par = transitive_reduction(m)
+    outdeg = [0] * m.n
+    for w in range(m.n):
+        for u in par[w]:
+            outdeg[u] += 1
+    visited = [False] * m.n
+    part_root = {}
+    roots = []
+    for v in range(m.n - 1, -1, -1):
+        if visited[v]:
+            continue
+        members, weight = [], 0
+        count = {}
+        heap = [-v]
+        while heap:
+            x = -heapq.heappop(heap)
+            if weight + w_of[x] > max_weight and members:
+                continue
+            members.append(x)
+            weight += w_of[x]
+            for u in par[x]:
+                count[u] = count.get(u, 0) + 1
+                if count[u] == outdeg[u]:
+                    heapq.heappush(heap, -u)
+        for x in members:
+            visited[x] = True
+            part_root[x] = v
+        roots.append(v)
+    order = {r: i for i, r in enumerate(sorted(roots))}
+    return np.array([order[part_root[v]] for v in range(m.n)], dtype=np.int32)
+
+
+def coarse_dag(m, part):
+    """Coarsened graph (Definition 4.1) of the transitively reduced DAG along
+    the partition, as a lower-triangular pattern CSR over the parts (parts are
+    numbered in a topological order: by root) with part weights = summed row
+    weights.  Returns (CSR, weights)."""
+    from paper_2503_05408_amd.gen import CSR
+    rp, _, _ = _csr(m)
+    par = transitive_reduction(m)
+    P = int(part.max()) + 1 if m.n else 0
+    cparents = [set() for _ in range(P)]
+    weight = np.zeros(P, dtype=np.int64)
+    for w in range(m.n):
+        weight[part[w]] += rp[w + 1] - rp[w]
+        for u in par[w]:
+            if part[u] != part[w]:
+                cparents[part[w]].add(int(part[u]))
+    row_ptr = [0]
+    col = []
+    for q in range(P):
+        ps = sorted(cparents[q])
+        assert all(p < q for p in ps), "parts are not in topological order"
+        col += ps + [q]
+        row_ptr.append(len(col))
+    return CSR(P, np.array(row_ptr, np.int64), np.array(col, np.int32), np.ones(len(col))), weight
+
+
+def funnel_growlocal(m, k, max_weight, L=PAPER_L, alpha0=PAPER_ALPHA0, growth=PAPER_GROWTH, theta=PAPER_THETA):
+    """Funnel + GrowLocal: Algorithm 3.1 on the coarsened DAG (part weights),
+    pulled back so that every row takes its part's core and superstep.
+    Returns (pi, sigma, S, part)."""
+    part = funnel_partition(m, max_weight)
+    cm, weight = coarse_dag(m, part)
+    rp, c, _ = _csr(cm)
+    P = cm.n
+    pc = np.empty(P, dtype=np.int32)
+    sc = np.empty(P, dtype=np.int32)
+    S = ctypes.c_int32(0)
+    nt = ctypes.c_int64(0)
+    w = np.ascontiguousarray(weight, dtype=np.int64)
+    rc = _load().oracle_growlocal_weighted(P, _p(rp), _p(c), _p(w), int(k), float(L), float(alpha0), float(growth),
+                                           float(theta), _p(pc), _p(sc), ctypes.byref(S), 0, None, None, None,
+                                           None, ctypes.byref(nt))
+    if rc:
+        raise OracleError(f"oracle_growlocal_weighted: {rc}")
+    return pc[part].astype(np.int32), sc[part].astype(np.int32), S.value, part
