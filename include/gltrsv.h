@@ -142,6 +142,17 @@ typedef struct gltrsv_plan_opts {
                                vertex n-1-i) so GrowLocal runs in the solve's
                                direction; gltrsv_schedule and
                                gltrsv_plan_schedule report it per row.       */
+    int32_t funnel_max_weight; /* > 0: Funnel coarsening (Sec. 4) before
+                               GrowLocal: the long edges of triangles are
+                               removed (approximate transitive reduction),
+                               the DAG is cut into in-funnels (Algorithm 4.1:
+                               reverse topological order, largest vertex
+                               first, a parent joins once all its children
+                               have) of at most this weight (stored entries;
+                               a single vertex may exceed it), GrowLocal
+                               schedules the coarsened DAG and every row
+                               takes its part's core and superstep; overrides
+                               `blocks`.  0 = off                            */
 } gltrsv_plan_opts;
 
 /* Fills the paper's parameters: k = 22 (the core count of the main

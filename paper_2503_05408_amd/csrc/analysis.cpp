@@ -11,6 +11,7 @@
 #include <cstring>
 #include <functional>
 #include <numeric>
+#include <queue>
 
 #include "../../include/gltrsv.h"
 
@@ -509,9 +510,143 @@ Schedule schedule_growlocal_blocks(const CsrView &A, const SchedParams &p)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Funnel coarsening (Sec. 4)
+// ---------------------------------------------------------------------------
+
+ReducedDag transitive_reduction(const CsrView &A)
+{
+    const int64_t n = A.n;
+    // children lists, rising
+    std::vector<int64_t> cb(size_t(n) + 1, 0);
+    for (int64_t w = 0; w < n; w++)
+        for (int64_t e = A.row_ptr[w]; e < A.row_ptr[w + 1] - 1; e++) cb[size_t(A.col[e]) + 1]++;
+    std::partial_sum(cb.begin(), cb.end(), cb.begin());
+    std::vector<int32_t> ch(size_t(cb[size_t(n)]));
+    {
+        std::vector<int64_t> pos(cb.begin(), cb.end() - 1);
+        for (int64_t w = 0; w < n; w++)
+            for (int64_t e = A.row_ptr[w]; e < A.row_ptr[w + 1] - 1; e++) ch[size_t(pos[size_t(A.col[e])]++)] = int32_t(w);
+    }
+    ReducedDag r;
+    r.beg.assign(size_t(n) + 1, 0);
+    r.par.reserve(size_t(A.nnz - n));
+    std::vector<int32_t> mark(size_t(n), -1);   // mark[u] == w: u is a parent of w
+    for (int64_t w = 0; w < n; w++) {
+        const int64_t lo = A.row_ptr[w], hi = A.row_ptr[w + 1] - 1;
+        for (int64_t e = lo; e < hi; e++) mark[size_t(A.col[e])] = int32_t(w);
+        for (int64_t e = lo; e < hi; e++) {
+            const int32_t u = A.col[e];
+            bool is_long = false;   // u -> v -> w for some parent v of w
+            for (int64_t q = cb[size_t(u)]; q < cb[size_t(u) + 1]; q++) {
+                const int32_t v = ch[size_t(q)];
+                if (v >= w) break;
+                if (mark[size_t(v)] == int32_t(w)) {
+                    is_long = true;
+                    break;
+                }
+            }
+            if (!is_long) r.par.push_back(u);
+        }
+        r.beg[size_t(w) + 1] = int64_t(r.par.size());
+    }
+    return r;
+}
+
+std::vector<int32_t> funnel_partition(const CsrView &A, const ReducedDag &r, int64_t max_weight, int32_t *nparts)
+{
+    const int64_t n = A.n;
+    std::vector<int32_t> outdeg(size_t(n), 0);
+    for (int32_t u : r.par) outdeg[size_t(u)]++;
+    std::vector<char> visited(size_t(n), 0);
+    std::vector<int32_t> count(size_t(n), 0), touched, members, root_of(size_t(n), -1);
+    std::priority_queue<int32_t> heap;   // largest vertex first
+    int32_t parts = 0;
+    for (int64_t v = n - 1; v >= 0; v--) {
+        if (visited[size_t(v)]) continue;
+        members.clear();
+        int64_t weight = 0;
+        heap.push(int32_t(v));
+        while (!heap.empty()) {
+            const int32_t x = heap.top();
+            heap.pop();
+            const int64_t wx = A.row_ptr[x + 1] - A.row_ptr[x];
+            if (weight + wx > max_weight && !members.empty()) continue;   // over the cap
+            members.push_back(x);
+            weight += wx;
+            for (int64_t e = r.beg[size_t(x)]; e < r.beg[size_t(x) + 1]; e++) {
+                const int32_t u = r.par[size_t(e)];
+                if (count[size_t(u)]++ == 0) touched.push_back(u);
+                if (count[size_t(u)] == outdeg[size_t(u)]) heap.push(u);
+            }
+        }
+        for (int32_t u : touched) count[size_t(u)] = 0;
+        touched.clear();
+        for (int32_t x : members) {
+            visited[size_t(x)] = 1;
+            root_of[size_t(x)] = parts;   // discovery index; roots fall, so parts renumber below
+        }
+        parts++;
+    }
+    // parts numbered by root in rising order (a topological order of the coarsened DAG)
+    for (int32_t &q : root_of) q = parts - 1 - q;
+    *nparts = parts;
+    return root_of;
+}
+
+namespace {
+
+Schedule schedule_funnel_growlocal(const CsrView &A, const SchedParams &p)
+{
+    const int64_t n = A.n;
+    const ReducedDag r = transitive_reduction(A);
+    int32_t P = 0;
+    const std::vector<int32_t> part = funnel_partition(A, r, p.funnel_max_weight, &P);
+    // coarsened DAG (Definition 4.1) of the reduced DAG, as a lower pattern
+    std::vector<std::pair<int32_t, int32_t>> edges;   // (part of child, part of parent)
+    std::vector<int64_t> weight(size_t(P), 0);
+    for (int64_t w = 0; w < n; w++) {
+        weight[size_t(part[size_t(w)])] += A.row_ptr[w + 1] - A.row_ptr[w];
+        for (int64_t e = r.beg[size_t(w)]; e < r.beg[size_t(w) + 1]; e++) {
+            const int32_t u = r.par[size_t(e)];
+            if (part[size_t(u)] != part[size_t(w)]) edges.emplace_back(part[size_t(w)], part[size_t(u)]);
+        }
+    }
+    std::sort(edges.begin(), edges.end());
+    edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+    std::vector<int64_t> crp(size_t(P) + 1, 0);
+    std::vector<int32_t> ccol;
+    ccol.reserve(edges.size() + size_t(P));
+    size_t q = 0;
+    for (int32_t c = 0; c < P; c++) {
+        while (q < edges.size() && edges[q].first == c) ccol.push_back(edges[q++].second);
+        ccol.push_back(c);
+        crp[size_t(c) + 1] = int64_t(ccol.size());
+    }
+    CsrView cv;
+    cv.n = P;
+    cv.nnz = int64_t(ccol.size());
+    cv.row_ptr = crp.data();
+    cv.col = ccol.data();
+    GrowLocalScheduler g(cv, p, growlocal_workers(P, p.threads), weight.data());
+    const Schedule cs = g.run();
+    Schedule out;
+    out.core.resize(size_t(n));
+    out.superstep.resize(size_t(n));
+    for (int64_t v = 0; v < n; v++) {
+        out.core[size_t(v)] = cs.core[size_t(part[size_t(v)])];
+        out.superstep[size_t(v)] = cs.superstep[size_t(part[size_t(v)])];
+    }
+    out.S = cs.S;
+    return out;
+}
+
+}  // namespace
+
 Schedule schedule_growlocal(const CsrView &A, const SchedParams &p)
 {
     if (A.n == 0) return Schedule{};
+    if (p.funnel_max_weight > 0) return schedule_funnel_growlocal(A, p);
     if (p.blocks > 1) return schedule_growlocal_blocks(A, p);
     GrowLocalScheduler g(A, p, growlocal_workers(A.n, p.threads));
     return g.run();

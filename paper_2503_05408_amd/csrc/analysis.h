@@ -42,6 +42,7 @@ struct SchedParams {
     int32_t kind = 0;  // 0 GrowLocal, 1 wavefront
     int32_t threads = 0;  // GrowLocal workers, 0 = automatic
     int32_t blocks = 0;   // > 1: block-parallel scheduling over that many diagonal blocks
+    int64_t funnel_max_weight = 0;   // > 0: Funnel coarsening first, parts up to this weight
 };
 
 struct Schedule {
@@ -80,6 +81,20 @@ int32_t wavefront_levels(const CsrView &A, std::vector<int32_t> &level);
 
 Schedule schedule_wavefront(const CsrView &A);
 Schedule schedule_growlocal(const CsrView &A, const SchedParams &p);
+// Funnel coarsening (Sec. 4).  The approximate transitive reduction keeps
+// the parents of each vertex except those u with u -> v -> w for another
+// parent v (a long edge of a triangle); parents rising.
+struct ReducedDag {
+    std::vector<int64_t> beg;   // [n+1]
+    std::vector<int32_t> par;
+};
+ReducedDag transitive_reduction(const CsrView &A);
+// Algorithm 4.1 on the reduced DAG: vertices in reverse topological order,
+// the largest vertex popped first, a parent joins once all its children are
+// in the part, a vertex that would lift the part weight (stored entries)
+// above max_weight stays out.  part[v], parts numbered by root, rising.
+std::vector<int32_t> funnel_partition(const CsrView &A, const ReducedDag &r, int64_t max_weight, int32_t *nparts);
+
 // Row bounds of the diagonal blocks of block-parallel scheduling (Sec. 3.1):
 // block b = rows [floor(b n / B), floor((b+1) n / B)).
 std::vector<int64_t> block_bounds(int64_t n, int32_t nblocks);

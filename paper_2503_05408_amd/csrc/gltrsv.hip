@@ -1016,6 +1016,7 @@ int check_opts(const gltrsv_plan_opts *o)
     if (o->pack != GLTRSV_PACK_AUTO && o->pack != GLTRSV_PACK_HOST && o->pack != GLTRSV_PACK_DEVICE)
         return set_error(GLTRSV_EINVAL, "unknown pack mode");
     if (o->blocks < 0) return set_error(GLTRSV_EINVAL, "blocks must be >= 0");
+    if (o->funnel_max_weight < 0) return set_error(GLTRSV_EINVAL, "funnel_max_weight must be >= 0");
     if (o->triangle != GLTRSV_LOWER && o->triangle != GLTRSV_UPPER)
         return set_error(GLTRSV_EINVAL, "triangle must be GLTRSV_LOWER or GLTRSV_UPPER");
     return GLTRSV_OK;
@@ -1032,6 +1033,7 @@ SchedParams params_of(const gltrsv_plan_opts *o)
     p.kind = o->schedule_kind;
     p.threads = o->analysis_threads;
     p.blocks = o->blocks;
+    p.funnel_max_weight = o->funnel_max_weight;
     return p;
 }
 
@@ -1132,6 +1134,7 @@ void gltrsv_default_opts(gltrsv_plan_opts *o)
     o->pack = GLTRSV_PACK_AUTO;
     o->blocks = 0;
     o->triangle = GLTRSV_LOWER;
+    o->funnel_max_weight = 0;
 }
 
 int gltrsv_check_csr(const gltrsv_csr *A)

@@ -132,3 +132,12 @@ def test_async_in_place_and_repeated():
             plan.solve_async(bd, x)
         torch.cuda.synchronize()
         assert oracle.same_bits(x.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("cap", [8, 64])
+def test_funnel_schedule_solves_exactly(cap):
+    for m in (gen.random_lower(6000, 0.003, 43), gen.narrow_band(20000, 0.05, 20, 7), gen.stencil_2d5(80, 50)):
+        want, x1, x2, info = _solve_both(m, B.gpu_opts(funnel_max_weight=cap), seed=cap)
+        pi, sg, S, _ = oracle.funnel_growlocal(m, 1 << 16, cap, L=50.0, alpha0=1.0)
+        assert info["supersteps"] == S
+        assert oracle.same_bits(x1, want) and oracle.same_bits(x2, want), m.name

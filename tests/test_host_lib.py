@@ -57,7 +57,7 @@ def test_check_csr_codes(case, code):
 def test_bad_options_rejected():
     m = gen.fig_1_1()
     for bad in (dict(k=0), dict(alpha0=0.5), dict(growth=1.0), dict(L=-1.0), dict(schedule_kind=7),
-                dict(analysis_threads=-1), dict(pack=9), dict(blocks=-2)):
+                dict(analysis_threads=-1), dict(pack=9), dict(blocks=-2), dict(funnel_max_weight=-1)):
         with pytest.raises(B.GltrsvError):
             B.schedule(m, B.default_opts(**bad))
 
@@ -191,3 +191,23 @@ def test_upper_wavefront_and_layout_checks():
     assert e.value.code == -2                      # entries above the diagonal
     with pytest.raises(B.GltrsvError):
         B.schedule(low, B.default_opts(triangle=5))
+
+
+@pytest.mark.parametrize("cap", [1, 6, 30, 400])
+def test_funnel_growlocal_equals_oracle(cap):
+    for p in (PARAMS[0], PARAMS[2], PARAMS[3]):
+        for m in cases()[:12]:
+            o = B.default_opts(funnel_max_weight=cap, **p)
+            core, sup, S = B.schedule(m, o)
+            pi, sg, S2, part = oracle.funnel_growlocal(m, o.k, cap, L=o.L, alpha0=o.alpha0, growth=o.growth,
+                                                       theta=o.accept)
+            assert S == S2 and np.array_equal(core, pi) and np.array_equal(sup, sg), (m.name, cap)
+
+
+def test_funnel_upper_equals_oracle_on_the_mirror():
+    for u in _uppers()[:8]:
+        o = B.default_opts(triangle=B.UPPER, funnel_max_weight=25, **PARAMS[3])
+        core, sup, S = B.schedule(u, o)
+        pi, sg, S2, _ = oracle.funnel_growlocal(oracle.mirror_upper(u), o.k, 25, L=o.L, alpha0=o.alpha0,
+                                                growth=o.growth, theta=o.accept)
+        assert S == S2 and np.array_equal(core, pi[::-1]) and np.array_equal(sup, sg[::-1]), u.name
