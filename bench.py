@@ -47,6 +47,9 @@ def workload(name: str):
     elif name == "er1e5":
         m = gen.erdos_renyi_paper(100_000, 1e-4, gen.SEED_BASE)
         desc = "Erdos-Renyi n=1e5 p=1e-4 (q=2p), Table A.4 family"
+    elif name == "nb1e5":
+        m = gen.narrow_band(100_000, 0.03, 42.0, gen.SEED_BASE + 10)
+        desc = "narrow band n=1e5 p=0.03 B=42, Table A.5 family"
     else:
         raise SystemExit(f"unknown workload {name}")
     return m, desc
@@ -116,6 +119,8 @@ def main():
                          "serve: Poisson request stream against resident plans; analysis: analysis time, "
                          "supersteps and solve time against the number of scheduling blocks")
     ap.add_argument("--blocks", default="1,2,4,8,16")
+    ap.add_argument("--funnel", default="",
+                    help="analysis mode: comma-separated Funnel part-weight caps to measure as well")
     ap.add_argument("--triangle", default="lower", choices=["lower", "upper"],
                     help="upper: backward substitution on the transpose of the workload")
     ap.add_argument("--systems", type=int, default=64)
@@ -403,7 +408,13 @@ def bench_analysis(args):
         r["repay_solves_vs_cpu_serial"] = r["analysis_s"] / (serial_s - r["solve_ms"] * 1e-3)
         log(f"blocks={nb}: {r}")
         rows.append(r)
-    print(json.dumps({"mode": "analysis", "workload": desc, "n": m.n, "nnz": m.nnz,
+    frows = []
+    for cap in [int(v) for v in args.funnel.split(",") if v]:
+        r = measure(B.default_opts(k=args.k, L=args.L, alpha0=args.alpha0, funnel_max_weight=cap))
+        r["funnel_max_weight"] = cap
+        log(f"funnel cap={cap}: {r}")
+        frows.append(r)
+    print(json.dumps({"mode": "analysis", "workload": desc, "n": m.n, "nnz": m.nnz, "funnel": frows,
                       "schedule": f"growlocal k={args.k} L={args.L:g} alpha0={args.alpha0:g}",
                       "host_threads": os.cpu_count(), "serial_cpu_solve_s": serial_s, "wavefront": wf,
                       "blocks": rows}), flush=True)
