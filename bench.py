@@ -114,11 +114,12 @@ def main():
     ap.add_argument("--k", type=int, default=1 << 16)
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "analysis"],
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "analysis", "paper"],
                     help="single: one n=1e7 system (the headline line); batch: 64 systems in one launch; "
                          "serve: Poisson request stream against resident plans; analysis: analysis time, "
                          "supersteps and solve time against the number of scheduling blocks")
     ap.add_argument("--blocks", default="1,2,4,8,16")
+    ap.add_argument("--instances", type=int, default=10, help="paper mode: instances per set")
     ap.add_argument("--funnel", default="",
                     help="analysis mode: comma-separated Funnel part-weight caps to measure as well")
     ap.add_argument("--triangle", default="lower", choices=["lower", "upper"],
@@ -141,6 +142,8 @@ def main():
         return bench_serve(args)
     if args.mode == "analysis":
         return bench_analysis(args)
+    if args.mode == "paper":
+        return bench_paper(args)
 
     import torch
     import oracle
@@ -418,6 +421,75 @@ def bench_analysis(args):
                       "schedule": f"growlocal k={args.k} L={args.L:g} alpha0={args.alpha0:g}",
                       "host_threads": os.cpu_count(), "serial_cpu_solve_s": serial_s, "wavefront": wf,
                       "blocks": rows}), flush=True)
+
+
+def bench_paper(args):
+    """The paper's synthetic sets at paper size (ER p in {1e-4, 5e-4, 2e-3} and
+    NB (p, B) in {(0.14, 10), (0.05, 20), (0.03, 42)}, n = 1e5, ten instances
+    each): per set, the geometric mean over instances of the speed-up over one
+    serial solve on one host core (the kind of number of Table 7.1) for each
+    schedule and execution form, and the mean ratio wavefronts / supersteps
+    (Table 7.2).  Every timed result is checked against the oracle bit for
+    bit."""
+    import torch
+    import oracle
+    from paper_2503_05408_amd import binding as B
+    from paper_2503_05408_amd import gen
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    sets = [("ER", p, None) for p in gen.ER_PROBS] + [("NB", p, Bw) for p, Bw in gen.NB_PAIRS]
+    o_gl, o_wf, o_auto = B.gpu_opts(), B.default_opts(schedule_kind=B.SCHED_WAVEFRONT), \
+        B.gpu_opts(schedule_kind=B.SCHED_AUTO)
+    forms = {"GL persistent": (o_gl, "solve"), "GL async": (o_gl, "solve_async"),
+             "wavefront persistent": (o_wf, "solve"), "wavefront async": (o_wf, "solve_async"),
+             "AUTO persistent": (o_auto, "solve")}
+    report = []
+    for fam, p, Bw in sets:
+        logs = {f: [] for f in forms}
+        ratios, all_exact = [], True
+        for i in range(args.instances):
+            m = (gen.erdos_renyi_paper(100_000, p, gen.SEED_BASE + i) if fam == "ER"
+                 else gen.narrow_band(100_000, p, Bw, gen.SEED_BASE + 10 + i))
+            bh = np.ones(m.n)
+            t0 = time.perf_counter()
+            want = oracle.solve(m, bh)
+            serial = time.perf_counter() - t0
+            b = torch.ones(m.n, dtype=torch.float64, device="cuda")
+            x = torch.empty_like(b)
+            plans = {}
+            for f, (o, meth) in forms.items():
+                key = id(o)
+                if key not in plans:
+                    plans[key] = B.Plan(m, o)
+                plan = plans[key]
+                t = timed(lambda: getattr(plan, meth)(b, x), args.steps)
+                ok = plan.device_status() == 0 and oracle.same_bits(x.cpu().numpy(), want)
+                all_exact &= ok
+                logs[f].append(serial / t)
+                if f == "GL persistent":
+                    inf = plan.info()
+                    ratios.append(inf["wavefronts"] / inf["supersteps"])
+            for plan in plans.values():
+                plan.close()
+        row = {"set": f"{fam} p={p}" + (f" B={Bw:g}" if Bw else ""), "instances": args.instances,
+               "exact": bool(all_exact), "wavefronts_per_superstep_GL": float(np.mean(ratios)),
+               "geomean_speedup_vs_serial": {f: float(np.exp(np.mean(np.log(v)))) for f, v in logs.items()}}
+        log(json.dumps(row))
+        report.append(row)
+    print(json.dumps({"mode": "paper", "n": 100_000, "serial": "oracle, one host core, one solve",
+                      "sets": report}), flush=True)
 
 
 def auto_plan(m):
