@@ -459,6 +459,7 @@ def bench_paper(args):
     for fam, p, Bw in sets:
         logs = {f: [] for f in forms}
         ratios, all_exact = [], True
+        kept, serial_total = [], 0.0   # (matrix, wavefront plan, AUTO plan, want) for the batched launches
         for i in range(args.instances):
             m = (gen.erdos_renyi_paper(100_000, p, gen.SEED_BASE + i) if fam == "ER"
                  else gen.narrow_band(100_000, p, Bw, gen.SEED_BASE + 10 + i))
@@ -466,6 +467,7 @@ def bench_paper(args):
             t0 = time.perf_counter()
             want = oracle.solve(m, bh)
             serial = time.perf_counter() - t0
+            serial_total += serial
             b = torch.ones(m.n, dtype=torch.float64, device="cuda")
             x = torch.empty_like(b)
             plans = {}
@@ -481,11 +483,26 @@ def bench_paper(args):
                 if f == "GL persistent":
                     inf = plan.info()
                     ratios.append(inf["wavefronts"] / inf["supersteps"])
+            kept.append((m, plans.pop(id(o_wf)), plans.pop(id(o_auto)), want))
             for plan in plans.values():
                 plan.close()
+        # every instance of the set in one launch: throughput against the serial solves one after another
+        batched = {}
+        bs = [torch.ones(k[0].n, dtype=torch.float64, device="cuda") for k in kept]
+        xs = [torch.empty_like(v) for v in bs]
+        for label, idx, async_exec in (("wavefront async batch", 1, True), ("AUTO BSP batch", 2, False)):
+            with B.Batch([k[idx] for k in kept], per_claim=2, use_graph=False, async_exec=async_exec) as bt:
+                t = timed(lambda: bt.solve(bs, xs), args.steps)
+                ok = bt.status() == 0 and all(oracle.same_bits(x.cpu().numpy(), k[3]) for x, k in zip(xs, kept))
+            all_exact &= ok
+            batched[label] = serial_total / t
+        for k in kept:
+            k[1].close()
+            k[2].close()
         row = {"set": f"{fam} p={p}" + (f" B={Bw:g}" if Bw else ""), "instances": args.instances,
                "exact": bool(all_exact), "wavefronts_per_superstep_GL": float(np.mean(ratios)),
-               "geomean_speedup_vs_serial": {f: float(np.exp(np.mean(np.log(v)))) for f, v in logs.items()}}
+               "geomean_speedup_vs_serial": {f: float(np.exp(np.mean(np.log(v)))) for f, v in logs.items()},
+               "batched_speedup_vs_serial_sum": batched}
         log(json.dumps(row))
         report.append(row)
     print(json.dumps({"mode": "paper", "n": 100_000, "serial": "oracle, one host core, one solve",
