@@ -67,3 +67,49 @@ def test_full_size_single_system():
         p.solve_plain(b, x)
         torch.cuda.synchronize()
         assert oracle.same_bits(x.cpu().numpy(), want)
+        p.solve_async(b, x)
+        torch.cuda.synchronize()
+        assert p.device_status() == 0
+        assert oracle.same_bits(x.cpu().numpy(), want)
+        X = p.solve_multi(torch.ones(n, 4, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        for r in (0, 3):
+            assert oracle.same_bits(X[:, r].cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("maker", [lambda: gen.stencil_3d7(216), lambda: gen.stencil_3d27(216)])
+def test_full_size_grids(maker):
+    """The 216^3 grids of the benchmark (AUTO schedule), persistent, plain
+    and semi-asynchronous, against the full oracle solve."""
+    import torch
+    m = maker()
+    want = oracle.solve(m, np.ones(m.n))
+    with B.Plan(m, B.gpu_opts(schedule_kind=B.SCHED_AUTO)) as p:
+        b = torch.ones(m.n, dtype=torch.float64, device="cuda")
+        x = torch.full_like(b, float("nan"))
+        for solve in (p.solve, p.solve_plain, p.solve_async):
+            x.fill_(float("nan"))
+            solve(b, x)
+            torch.cuda.synchronize()
+            assert p.device_status() == 0
+            assert oracle.same_bits(x.cpu().numpy(), want), (m.name, solve.__name__)
+
+
+def test_full_size_batch_mix():
+    """The 64-system batching workload (9.5e6 rows) in one launch, BSP and
+    semi-asynchronous, every system against the oracle."""
+    import torch
+    ms = gen.batch_mix()
+    plans = [B.Plan(m, B.gpu_opts(schedule_kind=B.SCHED_AUTO)) for m in ms]
+    bs = [torch.from_numpy(gen.rhs_uniform(m.n, i)).cuda() for i, m in enumerate(ms)]
+    wants = [oracle.solve(m, b.cpu().numpy()) for m, b in zip(ms, bs)]
+    for async_exec in (False, True):
+        xs = [torch.full_like(b, float("nan")) for b in bs]
+        with B.Batch(plans, per_claim=2, async_exec=async_exec) as bt:
+            bt.solve(bs, xs)
+            torch.cuda.synchronize()
+            assert bt.status() == 0
+        for m, x, w in zip(ms, xs, wants):
+            assert oracle.same_bits(x.cpu().numpy(), w), (m.name, async_exec)
+    for p in plans:
+        p.close()
