@@ -153,6 +153,15 @@ typedef struct gltrsv_plan_opts {
                                schedules the coarsened DAG and every row
                                takes its part's core and superstep; overrides
                                `blocks`.  0 = off                            */
+    int32_t exec_hint;        /* the execution AUTO predicts: 0 = persistent
+                               (barriers; per superstep 3 us plus the larger
+                               of 0.18 us per entry of its longest task and
+                               its entries at 4e4 entries/us), 1 =
+                               semi-asynchronous (gltrsv_solve_async: the
+                               larger of the critical path -- rows of a task
+                               one after another at 0.18 us per entry, a
+                               parent in another task adding 1.5 us -- and
+                               all entries at 4e4 entries/us, plus 10 us)    */
 } gltrsv_plan_opts;
 
 /* Fills the paper's parameters: k = 22 (the core count of the main
@@ -207,10 +216,8 @@ typedef struct gltrsv_plan_info {
     int32_t block_size;     /* threads per workgroup                          */
     int64_t max_task_rows;  /* longest row sequence on one core in a superstep */
     int32_t schedule_kind;  /* the schedule built (AUTO resolves to one)      */
-    double predicted_us;    /* cost-model prediction of one solve: per
-                               superstep 3 us plus the larger of 0.18 us per
-                               entry of its longest task and its entries at
-                               4e4 entries/us                                */
+    double predicted_us;    /* cost-model prediction of one solve in the
+                               execution named by opts.exec_hint              */
     int32_t device_packed;  /* 1 if the stream was filled on the device       */
     int32_t async_grid_blocks; /* workgroups of gltrsv_solve_async            */
 } gltrsv_plan_info;

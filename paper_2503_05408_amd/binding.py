@@ -50,7 +50,8 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("k", i32), ("L", dbl), ("alpha0", dbl), ("growth", dbl), ("accept", dbl),
                 ("schedule_kind", i32), ("reorder", i32), ("block_size", i32), ("grid_blocks", i32),
                 ("cooperative", i32), ("analysis_threads", i32), ("pack", i32),
-                ("blocks", i32), ("triangle", i32), ("funnel_max_weight", i32)]
+                ("blocks", i32), ("triangle", i32), ("funnel_max_weight", i32),
+                ("exec_hint", i32)]
 
 
 class BatchOpts(ctypes.Structure):

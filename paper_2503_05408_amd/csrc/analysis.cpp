@@ -832,6 +832,27 @@ double predict_cost_us(const CsrView &A, const Schedule &sch, const std::vector<
     return total;
 }
 
+double predict_async_us(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm, const CostModel &cm)
+{
+    const int64_t n = A.n;
+    std::vector<double> finish(size_t(n), 0.0);
+    double path = 0.0;
+    for (int64_t t = 0; t < n; t++) {
+        const int32_t i = perm[size_t(t)];
+        const bool same = t > 0 && sch.superstep[size_t(perm[size_t(t - 1)])] == sch.superstep[size_t(i)] &&
+                          sch.core[size_t(perm[size_t(t - 1)])] == sch.core[size_t(i)];
+        double start = same ? finish[size_t(perm[size_t(t - 1)])] : 0.0;
+        for (int64_t e = A.row_ptr[i]; e < A.row_ptr[i + 1] - 1; e++) {
+            const int32_t j = A.col[e];
+            if (sch.superstep[size_t(j)] != sch.superstep[size_t(i)] || sch.core[size_t(j)] != sch.core[size_t(i)])
+                start = std::max(start, finish[size_t(j)] + cm.hop_us);
+        }
+        finish[size_t(i)] = start + cm.entry_us * double(A.row_ptr[i + 1] - A.row_ptr[i]);
+        path = std::max(path, finish[size_t(i)]);
+    }
+    return cm.launch_us + std::max(path, double(A.nnz) / cm.entries_per_us);
+}
+
 uint64_t pattern_key(const CsrView &A)
 {
     // 64-bit multiply-xorshift mix over n, row pointers and columns

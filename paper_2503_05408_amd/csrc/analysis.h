@@ -43,6 +43,7 @@ struct SchedParams {
     int32_t threads = 0;  // GrowLocal workers, 0 = automatic
     int32_t blocks = 0;   // > 1: block-parallel scheduling over that many diagonal blocks
     int64_t funnel_max_weight = 0;   // > 0: Funnel coarsening first, parts up to this weight
+    int32_t exec_hint = 0;           // AUTO predicts 0: persistent execution, 1: semi-asynchronous
 };
 
 struct Schedule {
@@ -149,8 +150,16 @@ struct CostModel {
     double superstep_us = 3.0;     // barrier + first gather round trip
     double entry_us = 0.18;        // one lane, one stored entry
     double entries_per_us = 4.0e4; // whole device, random gathers
+    double hop_us = 1.5;           // a value passed between lanes through memory (semi-asynchronous)
+    double launch_us = 10.0;       // fill of x + launch (semi-asynchronous)
 };
+// Persistent (barrier) execution: per superstep, the barrier plus the larger
+// of its longest task and its entries at the device rate.
 double predict_cost_us(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm, const CostModel &cm);
+// Semi-asynchronous execution: the larger of the critical path (rows of a
+// task one after another in their lane, a parent in another task adding a
+// memory hop) and all entries at the device rate.
+double predict_async_us(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm, const CostModel &cm);
 
 uint64_t pattern_key(const CsrView &A);
 

@@ -1017,6 +1017,7 @@ int check_opts(const gltrsv_plan_opts *o)
         return set_error(GLTRSV_EINVAL, "unknown pack mode");
     if (o->blocks < 0) return set_error(GLTRSV_EINVAL, "blocks must be >= 0");
     if (o->funnel_max_weight < 0) return set_error(GLTRSV_EINVAL, "funnel_max_weight must be >= 0");
+    if (o->exec_hint != 0 && o->exec_hint != 1) return set_error(GLTRSV_EINVAL, "exec_hint must be 0 or 1");
     if (o->triangle != GLTRSV_LOWER && o->triangle != GLTRSV_UPPER)
         return set_error(GLTRSV_EINVAL, "triangle must be GLTRSV_LOWER or GLTRSV_UPPER");
     return GLTRSV_OK;
@@ -1054,20 +1055,23 @@ Schedule build_schedule(const CsrView &V, const gltrsv_plan_opts *o, std::vector
                         int32_t *chosen)
 {
     const CostModel cm;
+    auto predict = [&](const Schedule &sc, const std::vector<int32_t> &pm) {
+        return o->exec_hint == 1 ? predict_async_us(V, sc, pm, cm) : predict_cost_us(V, sc, pm, cm);
+    };
     if (o->schedule_kind == GLTRSV_SCHED_WAVEFRONT) {
         Schedule w = schedule_wavefront(V);
         *perm = schedule_order(V.n, w.core.data(), w.superstep.data(), w.S);
-        *cost_us = predict_cost_us(V, w, *perm, cm);
+        *cost_us = predict(w, *perm);
         *chosen = GLTRSV_SCHED_WAVEFRONT;
         return w;
     }
     Schedule g = schedule_growlocal(V, params_of(o));
     std::vector<int32_t> pg = schedule_order(V.n, g.core.data(), g.superstep.data(), g.S);
-    const double cg = predict_cost_us(V, g, pg, cm);
+    const double cg = predict(g, pg);
     if (o->schedule_kind == GLTRSV_SCHED_AUTO) {
         Schedule w = schedule_wavefront(V);
         std::vector<int32_t> pw = schedule_order(V.n, w.core.data(), w.superstep.data(), w.S);
-        const double cw = predict_cost_us(V, w, pw, cm);
+        const double cw = predict(w, pw);
         if (cw < cg) {
             *perm = std::move(pw);
             *cost_us = cw;
@@ -1135,6 +1139,7 @@ void gltrsv_default_opts(gltrsv_plan_opts *o)
     o->blocks = 0;
     o->triangle = GLTRSV_LOWER;
     o->funnel_max_weight = 0;
+    o->exec_hint = 0;
 }
 
 int gltrsv_check_csr(const gltrsv_csr *A)

@@ -141,3 +141,21 @@ def test_funnel_schedule_solves_exactly(cap):
         pi, sg, S, _ = oracle.funnel_growlocal(m, 1 << 16, cap, L=50.0, alpha0=1.0)
         assert info["supersteps"] == S
         assert oracle.same_bits(x1, want) and oracle.same_bits(x2, want), m.name
+
+
+def test_auto_for_async_execution_picks_the_lower_prediction():
+    import torch
+    for m in (gen.narrow_band(20000, 0.03, 42, 11), gen.erdos_renyi_paper(20000, 1e-4, gen.SEED_BASE + 5),
+              gen.stencil_2d5(90, 60)):
+        pred = {}
+        for kind in (B.SCHED_GROWLOCAL, B.SCHED_WAVEFRONT, B.SCHED_AUTO):
+            with B.Plan(m, B.gpu_opts(schedule_kind=kind, exec_hint=1)) as plan:
+                inf = plan.info()
+                pred[kind] = (inf["predicted_us"], inf["schedule_kind"])
+                if kind == B.SCHED_AUTO:
+                    b = torch.from_numpy(gen.rhs_uniform(m.n, 2)).cuda()
+                    x = plan.solve_async(b)
+                    torch.cuda.synchronize()
+                    assert oracle.same_bits(x.cpu().numpy(), oracle.solve(m, b.cpu().numpy()))
+        best = min(pred[B.SCHED_GROWLOCAL][0], pred[B.SCHED_WAVEFRONT][0])
+        assert pred[B.SCHED_AUTO][0] == best, (m.name, pred)
