@@ -355,6 +355,10 @@ def main():
             "traffic_GBs": (traffic / (kern_ms * 1e-3) / 1e9) if traffic else None,
         },
     }
+    prop = torch.cuda.get_device_properties(0)
+    out["device"] = {"name": prop.name, "arch": getattr(prop, "gcnArchName", ""),
+                     "compute_units": prop.multi_processor_count,
+                     "memory_GB": round(prop.total_memory / 1e9, 1)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(m)
