@@ -250,6 +250,14 @@ int gltrsv_solve_plain(gltrsv_plan *plan, const double *b, double *x, void *stre
  * 1 = spin limit hit).  Synchronises the plan's last stream. */
 int gltrsv_plan_device_status(gltrsv_plan *plan, int32_t *status);
 
+/* Watchdog of the plan's device-side waits (the persistent kernel's barrier,
+ * the semi-asynchronous readiness waits): the number of polls a wait may take
+ * before the solve gives up and sets the error word that
+ * gltrsv_plan_device_status reports (default 5,000,000, about 5 s).  A small
+ * value forces that path from the host, e.g. to test error handling: every
+ * wave still leaves the kernel normally.  polls >= 1, else EINVAL. */
+int gltrsv_plan_set_spin_limit(gltrsv_plan *plan, int64_t polls);
+
 /* ---------------------------------------------------------------- batches */
 /* Many independent systems in one persistent launch (the schedules compose:
  * systems share no data, so each advances through its own supersteps,

@@ -103,6 +103,7 @@ SIGNATURES = {
     "gltrsv_plan_gather_probe": ([P, P, P, P], i32),
     "gltrsv_solve_async": ([P, P, P, P], i32),
     "gltrsv_solve_multi": ([P, P, P, i32, P], i32),
+    "gltrsv_plan_set_spin_limit": ([P, i64], i32),
     "gltrsv_plan_stream": ([P, P, P, i64], i32),
     "gltrsv_default_batch_opts": ([P], None),
     "gltrsv_batch_create": ([P, i32, P, P], i32),
@@ -297,6 +298,10 @@ class Plan:
         _check(load().gltrsv_solve(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
                "gltrsv_solve")
         return x
+
+    def set_spin_limit(self, polls: int):
+        """Polls a device-side wait may take before the solve reports a time-out."""
+        _check(load().gltrsv_plan_set_spin_limit(self._p, int(polls)), "gltrsv_plan_set_spin_limit")
 
     def solve_async(self, b, x=None, stream=None):
         """Semi-asynchronous solve: no barriers, per-row readiness."""

@@ -1571,6 +1571,13 @@ int gltrsv_plan_device_status(gltrsv_plan *p, int32_t *status)
     return GLTRSV_OK;
 }
 
+int gltrsv_plan_set_spin_limit(gltrsv_plan *p, int64_t polls)
+{
+    if (!p || polls < 1) return set_error(GLTRSV_EINVAL, "polls must be >= 1");
+    p->spin_limit = polls;
+    return GLTRSV_OK;
+}
+
 void gltrsv_default_batch_opts(gltrsv_batch_opts *o)
 {
     if (!o) return;

@@ -159,3 +159,34 @@ def test_auto_for_async_execution_picks_the_lower_prediction():
                     assert oracle.same_bits(x.cpu().numpy(), oracle.solve(m, b.cpu().numpy()))
         best = min(pred[B.SCHED_GROWLOCAL][0], pred[B.SCHED_WAVEFRONT][0])
         assert pred[B.SCHED_AUTO][0] == best, (m.name, pred)
+
+
+def test_watchdog_reports_a_forced_timeout_and_the_plan_recovers():
+    # a spin limit of one poll, forced from the host: some barrier / readiness
+    # wait of this 118-level grid takes longer, the solve sets the error word,
+    # every wave leaves normally, the status reports it once, and the plan
+    # solves exactly again with the default limit
+    import torch
+    m = gen.stencil_3d7(40)
+    b = gen.rhs_uniform(m.n, 9)
+    want = oracle.solve(m, b)
+    bd = torch.from_numpy(b).cuda()
+    with B.Plan(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT)) as plan:
+        assert plan.info()["grid_blocks"] > 1
+        plan.set_spin_limit(1)
+        x = plan.solve(bd)
+        torch.cuda.synchronize()
+        assert plan.device_status() == 1
+        assert plan.device_status() == 0            # reported once, then cleared
+        plan.solve_async(bd, x)
+        torch.cuda.synchronize()
+        assert plan.device_status() == 1
+        plan.set_spin_limit(5_000_000)
+        for solve in (plan.solve, plan.solve_async, plan.solve_plain):
+            x.fill_(float("nan"))
+            solve(bd, x)
+            torch.cuda.synchronize()
+            assert plan.device_status() == 0
+            assert oracle.same_bits(x.cpu().numpy(), want)
+        with pytest.raises(B.GltrsvError):
+            plan.set_spin_limit(0)
