@@ -78,6 +78,7 @@ int gltrsv_check_csr(const gltrsv_csr *A);
 #define GLTRSV_SCHED_GROWLOCAL 0   /* Algorithm 3.1                           */
 #define GLTRSV_SCHED_WAVEFRONT 1   /* level sets: one superstep per wavefront */
 #define GLTRSV_SCHED_AUTO      2   /* both; keep the lower predicted time     */
+#define GLTRSV_SCHED_GIVEN     3   /* plan info only: schedule passed in      */
 
 /* gltrsv_plan_opts.triangle */
 #define GLTRSV_LOWER 0
@@ -245,6 +246,15 @@ int gltrsv_solve(gltrsv_plan *plan, const double *b, double *x, void *stream);
 /* Baseline: one kernel launch per superstep; the kernel boundary is the
  * barrier.  Same arguments and results as gltrsv_solve. */
 int gltrsv_solve_plain(gltrsv_plan *plan, const double *b, double *x, void *stream);
+
+/* As gltrsv_plan_create, but with the schedule of an earlier analysis of
+ * the same pattern (gltrsv_plan_schedule or gltrsv_schedule: core[n] and
+ * superstep[n] per row, host arrays, caller-owned) instead of running the
+ * scheduler: analysis results can be kept and reused across processes.  The
+ * schedule is checked against Definition 2.1 (EINVAL with a description
+ * otherwise); opts supply the triangle, packing and device settings. */
+int gltrsv_plan_create_with_schedule(const gltrsv_csr *A, const gltrsv_plan_opts *opts, const int32_t *core,
+                                     const int32_t *superstep, gltrsv_plan **out);
 
 /* Device-side error word of the last persistent solve on this plan (0 = none,
  * 1 = spin limit hit).  Synchronises the plan's last stream. */

@@ -29,6 +29,7 @@ ERRORS = {
 SCHED_GROWLOCAL = 0
 SCHED_WAVEFRONT = 1
 SCHED_AUTO = 2
+SCHED_GIVEN = 3
 LOWER = 0
 UPPER = 1
 PACK_AUTO = 0
@@ -92,6 +93,7 @@ SIGNATURES = {
     "gltrsv_schedule": ([P, P, P, P, P], i32),
     "gltrsv_reorder": ([i64, P, P, P], i32),
     "gltrsv_plan_create": ([P, P, P], i32),
+    "gltrsv_plan_create_with_schedule": ([P, P, P, P, P], i32),
     "gltrsv_plan_info_get": ([P, P], i32),
     "gltrsv_plan_schedule": ([P, P, P, P], i32),
     "gltrsv_plan_destroy": ([P], i32),
@@ -248,13 +250,46 @@ def copy_probe(src, dst, stream=None):
 class Plan:
     """A matrix analysed and resident on the current device."""
 
-    def __init__(self, m, opts: PlanOpts | None = None):
+    def __init__(self, m, opts: PlanOpts | None = None, schedule=None):
+        """schedule: optional (core, superstep) per row from an earlier
+        analysis of the same pattern; the scheduler is then skipped."""
         self.n = int(m.n)
         self.opts = opts or default_opts()
         h = _HostCsr(m)
         ptr = ctypes.c_void_p()
-        _check(load().gltrsv_plan_create(h.ref, ctypes.byref(self.opts), ctypes.byref(ptr)), "gltrsv_plan_create")
+        if schedule is None:
+            _check(load().gltrsv_plan_create(h.ref, ctypes.byref(self.opts), ctypes.byref(ptr)),
+                   "gltrsv_plan_create")
+        else:
+            core = np.ascontiguousarray(schedule[0], dtype=np.int32)
+            sup = np.ascontiguousarray(schedule[1], dtype=np.int32)
+            if core.shape != (self.n,) or sup.shape != (self.n,):
+                raise ValueError("schedule arrays must have n entries")
+            _check(load().gltrsv_plan_create_with_schedule(h.ref, ctypes.byref(self.opts), _np_ptr(core),
+                                                            _np_ptr(sup), ctypes.byref(ptr)),
+                   "gltrsv_plan_create_with_schedule")
         self._p = ptr
+
+    def save_schedule(self, path: str):
+        """Stores the plan's schedule (per row) with the pattern key, so a later
+        process can rebuild the plan without rescheduling (load_schedule)."""
+        core, sup, _ = self.schedule()
+        inf = self.info()
+        np.savez(path, core=core, superstep=sup, pattern_key=np.uint64(inf["pattern_key"]),
+                 n=np.int64(inf["n"]), nnz=np.int64(inf["nnz"]))
+
+    @classmethod
+    def load_schedule(cls, m, path: str, opts: PlanOpts | None = None):
+        """A plan for m from a schedule stored by save_schedule; the stored
+        pattern key must equal m's."""
+        with np.load(path, allow_pickle=False) as z:
+            core, sup = z["core"], z["superstep"]
+            key, n, nnz = int(z["pattern_key"]), int(z["n"]), int(z["nnz"])
+        plan = cls(m, opts, schedule=(core, sup))
+        if (plan.info()["pattern_key"], n, nnz) != (key, int(m.n), int(m.row_ptr[-1])):
+            plan.close()
+            raise ValueError("the stored schedule belongs to another sparsity pattern")
+        return plan
 
     def close(self):
         if self._p:

@@ -114,6 +114,26 @@ int32_t wavefront_levels(const CsrView &A, std::vector<int32_t> &level)
     return top;
 }
 
+int validate_schedule(const CsrView &A, const Schedule &s, std::string *msg)
+{
+    for (int64_t i = 0; i < A.n; i++) {
+        if (s.core[size_t(i)] < 0 || s.superstep[size_t(i)] < 0 || s.superstep[size_t(i)] >= s.S) {
+            if (msg) *msg = "core or superstep out of range at vertex " + std::to_string(i);
+            return GLTRSV_EINVAL;
+        }
+        for (int64_t e = A.row_ptr[i]; e < A.row_ptr[i + 1] - 1; e++) {
+            const int32_t j = A.col[e];
+            const bool before = s.superstep[size_t(j)] < s.superstep[size_t(i)];
+            const bool same = s.superstep[size_t(j)] == s.superstep[size_t(i)] && s.core[size_t(j)] == s.core[size_t(i)];
+            if (!before && !same) {
+                if (msg) *msg = "edge " + std::to_string(j) + " -> " + std::to_string(i) + " violates Definition 2.1";
+                return GLTRSV_EINVAL;
+            }
+        }
+    }
+    return GLTRSV_OK;
+}
+
 Schedule schedule_wavefront(const CsrView &A)
 {
     Schedule s;

@@ -81,6 +81,11 @@ Mirror mirror_upper(const CsrView &U);
 int32_t wavefront_levels(const CsrView &A, std::vector<int32_t> &level);
 
 Schedule schedule_wavefront(const CsrView &A);
+
+// Definition 2.1 for a given schedule: cores >= 0, supersteps in [0, S), and
+// for every edge (j, i) either sigma(j) < sigma(i), or the same superstep on
+// the same core.  Returns 0 or GLTRSV_EINVAL with a description.
+int validate_schedule(const CsrView &A, const Schedule &s, std::string *msg);
 Schedule schedule_growlocal(const CsrView &A, const SchedParams &p);
 // Funnel coarsening (Sec. 4).  The approximate transitive reduction keeps
 // the parents of each vertex except those u with u -> v -> w for another

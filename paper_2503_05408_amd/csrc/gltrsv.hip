@@ -1216,7 +1216,23 @@ int gltrsv_plan_destroy(gltrsv_plan *p)
     return GLTRSV_OK;
 }
 
+static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, const int32_t *core_in,
+                            const int32_t *superstep_in, gltrsv_plan **out);
+
 int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv_plan **out)
+{
+    return plan_create_impl(A, opts, nullptr, nullptr, out);
+}
+
+int gltrsv_plan_create_with_schedule(const gltrsv_csr *A, const gltrsv_plan_opts *opts, const int32_t *core,
+                                     const int32_t *superstep, gltrsv_plan **out)
+{
+    if (!A || (A->n > 0 && (!core || !superstep))) return set_error(GLTRSV_EINVAL, "null schedule");
+    return plan_create_impl(A, opts, core, superstep, out);
+}
+
+static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, const int32_t *core_in,
+                            const int32_t *superstep_in, gltrsv_plan **out)
 {
     if (!A || !out) return set_error(GLTRSV_EINVAL, "null argument");
     *out = nullptr;
@@ -1238,7 +1254,30 @@ int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv
     p->n = A->n;
     p->nnz = A->nnz;
     p->upper = upper;
-    Schedule s = build_schedule(D, opts, &p->perm, &p->predicted_us, &p->schedule_kind);
+    Schedule s;
+    if (core_in) {
+        // a schedule from an earlier analysis (per row; for a backward solve
+        // vertex v is row n-1-v): checked against Definition 2.1
+        const int64_t n = A->n;
+        s.core.resize(size_t(n));
+        s.superstep.resize(size_t(n));
+        for (int64_t v = 0; v < n; v++) {
+            const int64_t row = upper ? n - 1 - v : v;
+            s.core[size_t(v)] = core_in[row];
+            s.superstep[size_t(v)] = superstep_in[row];
+            s.S = std::max(s.S, superstep_in[row] + 1);
+        }
+        if ((rc = validate_schedule(D, s, &msg))) {
+            delete p;
+            return set_error(rc, "given schedule: " + msg);
+        }
+        p->perm = schedule_order(n, s.core.data(), s.superstep.data(), s.S);
+        const CostModel cm;
+        p->predicted_us = opts->exec_hint == 1 ? predict_async_us(D, s, p->perm, cm) : predict_cost_us(D, s, p->perm, cm);
+        p->schedule_kind = GLTRSV_SCHED_GIVEN;
+    } else {
+        s = build_schedule(D, opts, &p->perm, &p->predicted_us, &p->schedule_kind);
+    }
     std::vector<int32_t> lv;
     p->wavefronts = wavefront_levels(D, lv);
     const bool on_device =

@@ -190,3 +190,37 @@ def test_watchdog_reports_a_forced_timeout_and_the_plan_recovers():
             assert oracle.same_bits(x.cpu().numpy(), want)
         with pytest.raises(B.GltrsvError):
             plan.set_spin_limit(0)
+
+
+def test_plan_from_a_stored_schedule(tmp_path):
+    # the analysis of one process reused by another: same schedule, same
+    # stream, same bits, without rescheduling; invalid schedules and other
+    # patterns are refused
+    import torch
+    for m, opts in ((gen.random_lower(7000, 0.002, 95), B.gpu_opts()),
+                    (gen.upper_of(gen.narrow_band(9000, 0.05, 20, 14)), B.gpu_opts(triangle=B.UPPER))):
+        path = str(tmp_path / "sched.npz")
+        b = torch.from_numpy(gen.rhs_uniform(m.n, 1)).cuda()
+        with B.Plan(m, opts) as p1:
+            p1.save_schedule(path)
+            w1, v1 = p1.stream()
+            x1 = p1.solve(b)
+            core, sup, _ = p1.schedule()
+        with B.Plan.load_schedule(m, path, opts) as p2:
+            assert p2.info()["schedule_kind"] == B.SCHED_GIVEN
+            w2, v2 = p2.stream()
+            x2 = p2.solve(b)
+            torch.cuda.synchronize()
+            assert np.array_equal(w1, w2) and np.array_equal(v1.view(np.uint64), v2.view(np.uint64))
+            assert oracle.same_bits(x1.cpu().numpy(), x2.cpu().numpy())
+        bad = sup.copy()
+        bad[:] = 0
+        core_bad = np.arange(m.n, dtype=np.int32)        # everything in one superstep on different cores
+        if m.row_ptr[-1] > m.n:
+            with pytest.raises(B.GltrsvError):
+                B.Plan(m, opts, schedule=(core_bad, bad))
+    other = gen.random_lower(7000, 0.002, 96)
+    with B.Plan(gen.random_lower(7000, 0.002, 95), B.gpu_opts()) as p1:
+        p1.save_schedule(str(tmp_path / "s2.npz"))
+    with pytest.raises((ValueError, B.GltrsvError)):
+        B.Plan.load_schedule(other, str(tmp_path / "s2.npz"), B.gpu_opts())

@@ -212,3 +212,17 @@ def test_funnel_upper_equals_oracle_on_the_mirror():
         pi, sg, S2, _ = oracle.funnel_growlocal(oracle.mirror_upper(u), o.k, 25, L=o.L, alpha0=o.alpha0,
                                                 growth=o.growth, theta=o.accept)
         assert S == S2 and np.array_equal(core, pi[::-1]) and np.array_equal(sup, sg[::-1]), u.name
+
+
+def test_given_schedule_is_checked_against_definition_2_1():
+    # rejected before any device work, so this runs on the CPU
+    m = gen.random_lower(300, 0.02, 7)
+    core, sup, S = B.schedule(m, B.gpu_opts())
+    bad_edge = np.zeros(m.n, np.int32), np.zeros(m.n, np.int32)
+    bad_edge[0][:] = np.arange(m.n)                     # one superstep, every row on its own core
+    bad_range = core.copy(), sup.copy()
+    bad_range[0][5] = -1
+    for sched in (bad_edge, bad_range):
+        with pytest.raises(B.GltrsvError) as e:
+            B.Plan(m, B.gpu_opts(), schedule=sched)
+        assert e.value.code == -1 and "given schedule" in str(e.value)
