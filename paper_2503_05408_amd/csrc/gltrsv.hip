@@ -1350,7 +1350,6 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         widest = std::max<int64_t>(widest, p->super_chunk_host[q + 1] - p->super_chunk_host[q]);
     p->widest = widest;
     const int64_t useful = (widest + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
-    const int cap = grid;
     grid = int(std::max<int64_t>(1, std::min<int64_t>(grid, useful)));
     p->grid = grid;
     // semi-asynchronous kernel: waves in flight = about four supersteps of
@@ -1367,7 +1366,6 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         const int64_t avg_width = p->S > 0 ? (p->chunks + p->S - 1) / p->S : 1;
         ga = std::min<int64_t>(ga, avg_width);   // avg_width chunks x 4 waves per block = 4 supersteps
         if (opts->grid_blocks > 0) ga = opts->grid_blocks < per_cu_a * cus ? opts->grid_blocks : per_cu_a * cus;
-        (void)cap;
         p->grid_async = int(std::max<int64_t>(
             1, std::min<int64_t>(ga, (p->chunks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
     }
@@ -1652,7 +1650,8 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
     gltrsv_batch_opts dflt;
     gltrsv_default_batch_opts(&dflt);
     if (!opts) opts = &dflt;
-    if (opts->per_claim < 1 || opts->grid_blocks < 0) return set_error(GLTRSV_EINVAL, "bad batch options");
+    if (opts->per_claim < 1 || opts->grid_blocks < 0 || (opts->async_exec != 0 && opts->async_exec != 1))
+        return set_error(GLTRSV_EINVAL, "bad batch options");
     int dev_id = 0;
     HIP_TRY(hipGetDevice(&dev_id));
     gltrsv_batch *bt = new (std::nothrow) gltrsv_batch();

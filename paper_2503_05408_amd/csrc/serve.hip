@@ -292,7 +292,7 @@ int gltrsv_server_create(const gltrsv_server_opts *opts, gltrsv_server **out)
     gltrsv_default_server_opts(&dflt);
     if (!opts) opts = &dflt;
     if (opts->budget_bytes <= 0 || opts->max_slots < 1 || opts->per_claim < 1 || !(opts->quantum_us > 0.0) ||
-        opts->counter_words < 1 || opts->grid_blocks < 0)
+        opts->counter_words < 1 || opts->grid_blocks < 0 || (opts->async_exec != 0 && opts->async_exec != 1))
         return set_error(GLTRSV_EINVAL, "bad server options");
     gltrsv_server *sv = new (std::nothrow) gltrsv_server();
     if (!sv) return set_error(GLTRSV_ENOMEM, "host allocation");
