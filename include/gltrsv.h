@@ -1,13 +1,17 @@
 /*
- * gltrsv -- GrowLocal-scheduled sparse lower-triangular solve on AMD MI355X
+ * gltrsv -- GrowLocal-scheduled sparse triangular solves on AMD MI355X
  * (gfx950).  C ABI of the shared library libgltrsv.so.
  *
- * The library solves A x = b for a sparse, non-singular, lower-triangular A by
- * forward substitution (Eq. (2.1) of Boehnlein, Papp, Steiner, Matzoros and
- * Yzelman, "Efficient parallel scheduling for sparse triangular solvers",
- * arxiv 2503.05408), executed on the GPU under a bulk-synchronous schedule
- * (Definition 2.1) built by the GrowLocal scheduler (Algorithm 3.1) and laid
- * out in the schedule's order (Sec. 5).
+ * The library solves A x = b for a sparse, non-singular, triangular A by
+ * forward substitution (lower-triangular A, Eq. (2.1) of Boehnlein, Papp,
+ * Steiner, Matzoros and Yzelman, "Efficient parallel scheduling for sparse
+ * triangular solvers", arxiv 2503.05408) or backward substitution (upper-
+ * triangular A, its mirror, Sec. 2.2), for one or several right-hand sides,
+ * executed on the GPU under a bulk-synchronous schedule (Definition 2.1)
+ * built by the GrowLocal scheduler (Algorithm 3.1, optionally block-parallel,
+ * Sec. 3.1, or after Funnel coarsening, Sec. 4) and laid out in the
+ * schedule's order (Sec. 5).  One system, many systems in one launch, and a
+ * continuous-batching server share the same kernels.
  *
  * Conventions shared by every call:
  *  - Return value: 0 (GLTRSV_OK) on success, a negative GLTRSV_E* code on
@@ -15,10 +19,11 @@
  *    a text for the last failure of the calling thread.
  *  - Matrices are CSR with int64 row pointers, int32 column indices and
  *    binary64 values, in host memory owned by the caller; the library copies
- *    what it needs.  Within each row the off-diagonal columns ascend strictly
- *    and the diagonal is the last stored entry; it must be non-zero (the
- *    matrix is non-singular, Sec. 2.2).  Every stored entry is an edge of the
- *    DAG (Sec. 2.2), explicit zeros included.
+ *    what it needs.  Within each row the columns ascend strictly and the
+ *    diagonal is the last stored entry of a lower-triangular A (the first of
+ *    an upper-triangular one, see gltrsv_plan_opts.triangle); it must be
+ *    non-zero (the matrix is non-singular, Sec. 2.2).  Every stored entry is
+ *    an edge of the DAG (Sec. 2.2), explicit zeros included.
  *  - Vectors passed to solve calls are device pointers (hipMalloc'd or torch
  *    CUDA tensors), caller-owned, n binary64 values in the original row
  *    numbering.
@@ -28,7 +33,9 @@
  *    for the stored off-diagonals of row i in stored order, each operation
  *    rounded on its own (no fused multiply-add), then x_i <- acc / A_ii with
  *    one correctly rounded division.  The result is therefore bit-identical
- *    for every schedule, every core count, batched or not.
+ *    for every schedule, every core count and every execution form
+ *    (persistent, plain, semi-asynchronous, several right-hand sides,
+ *    batched, served).
  */
 #ifndef GLTRSV_H
 #define GLTRSV_H
@@ -69,9 +76,10 @@ typedef struct gltrsv_csr {
     const double *val;       /* [nnz]; may be NULL for pattern-only calls     */
 } gltrsv_csr;
 
-/* Checks the conventions above.  Returns GLTRSV_OK or the first violation
- * (ENOTLOWER, ESINGULAR, EUNSORTED, ERANGE, EINVAL).  n is limited to
- * 2^30 - 1 rows (the device stream packs a row index into 30 bits). */
+/* Checks the conventions above for a lower-triangular A (plan creation
+ * checks an upper-triangular one itself).  Returns GLTRSV_OK or the first
+ * violation (ENOTLOWER, ESINGULAR, EUNSORTED, ERANGE, EINVAL).  n is limited
+ * to 2^30 - 1 rows (the device stream packs a row index into 30 bits). */
 int gltrsv_check_csr(const gltrsv_csr *A);
 
 /* ------------------------------------------------------------- schedules */
