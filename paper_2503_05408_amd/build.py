@@ -43,7 +43,7 @@ def build(verbose: bool = False, out: str | None = None, defines=()) -> str:
     common = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", os.path.join(ROOT, "include")]
     for src in SOURCES_HOST:
         obj = os.path.join(bdir, src + ".o")
-        cmd = ["g++", *common, "-Wall", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["g++", *common, "-Wall", *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd))
         subprocess.run(cmd, check=True)

@@ -25,7 +25,10 @@ constexpr uint32_t kHdrBit = 0x80000000u;
 constexpr uint32_t kIntBit = 0x40000000u;
 constexpr uint32_t kIdxMask = 0x3FFFFFFFu;
 constexpr uint32_t kPadWord = 0xFFFFFFFFu;
-constexpr int kRing = 16;  // recent rows of a lane kept on chip
+#ifndef GLTRSV_RING
+#define GLTRSV_RING 16
+#endif
+constexpr int kRing = GLTRSV_RING;  // recent rows of a lane kept on chip
 constexpr int64_t kMaxRows = (int64_t(1) << 30) - 1;
 constexpr int kLanes = 64;  // tasks per chunk = lanes of a wavefront
 

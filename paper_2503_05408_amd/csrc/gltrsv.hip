@@ -31,15 +31,24 @@ constexpr uint32_t HDR = 0x80000000u;
 constexpr uint32_t INTL = 0x40000000u;
 constexpr uint32_t MASK = 0x3FFFFFFFu;
 constexpr uint32_t PAD = 0xFFFFFFFFu;
+// Entries per batch (below).  A short batch shortens a lane's serial path,
+// since each batch waits for its own gathers; a long one keeps more gathers
+// in flight per lane.  Measured on MI355X: 4 is fastest for the single-system
+// kernels and BSP batches, 8 for semi-asynchronous batches and several
+// right-hand sides.
 #ifndef GLTRSV_UNROLL
-#define GLTRSV_UNROLL 8
+#define GLTRSV_UNROLL 4
+#endif
+#ifndef GLTRSV_UNROLL_WIDE
+#define GLTRSV_UNROLL_WIDE 8
 #endif
 constexpr int kUnroll = GLTRSV_UNROLL;
+constexpr int kUnrollWide = GLTRSV_UNROLL_WIDE;
 using gltrsv::kRing;
 
 // One lane processes the packed entries of its task: entry t at
 // word/value[base + 64 t + lane], t < len.  Entries are handled in batches of
-// kUnroll through a two-deep pipeline:
+// U (kUnroll or kUnrollWide) through a two-deep pipeline:
 //   while batch i is processed, the gathers of batch i+1 and the words and
 //   values of batch i+2 are in flight;
 //   every operand that is final before batch i+1 starts (x of an earlier
@@ -48,17 +57,19 @@ using gltrsv::kRing;
 //   from an on-chip ring (a register for the previous row, LDS for older);
 //   the x values finished in a batch are stored after the batch, so no store
 //   sits in front of a wait.
-// A row read from memory by batch j finished at least kRing >= 2 kUnroll
+// A row read from memory by batch j finished at least kRing >= 2 U
 // entries earlier, i.e. in batch j-2 or before, whose stores precede the
 // gathers of batch j in the lane's program order.
 // Loads are issued unconditionally (padding slots re-read the chunk's first
 // slot, non-gathered operands re-read b[0]) so their count per iteration is
 // fixed and the compiler can wait for exactly the batch it needs.
-static_assert(2 * kUnroll <= gltrsv::kRing, "the ring must cover two batches");
+static_assert(2 * kUnroll <= gltrsv::kRing && 2 * kUnrollWide <= gltrsv::kRing,
+              "the ring must cover two batches");
 
+template <int U>
 struct Batch {
-    uint32_t w[kUnroll];
-    double v[kUnroll];
+    uint32_t w[U];
+    double v[U];
 };
 
 // Cross-workgroup data protocol.  x is the only array written during a
@@ -109,10 +120,11 @@ __device__ __forceinline__ LaneCursor make_cursor(const uint32_t *__restrict__ w
     return c;
 }
 
-__device__ __forceinline__ void load_batch(const LaneCursor &c, int32_t t0, Batch &B)
+template <int U>
+__device__ __forceinline__ void load_batch(const LaneCursor &c, int32_t t0, Batch<U> &B)
 {
 #pragma unroll
-    for (int j = 0; j < kUnroll; j++) {
+    for (int j = 0; j < U; j++) {
         const bool in = t0 + j < c.len;
         const int64_t off = in ? int64_t(t0 + j) * 64 : 0;
         const uint32_t w = __builtin_nontemporal_load(c.wp + off);
@@ -122,10 +134,11 @@ __device__ __forceinline__ void load_batch(const LaneCursor &c, int32_t t0, Batc
     }
 }
 
-__device__ __forceinline__ void gather_batch(const Batch &B, const double *b, const double *x, double (&g)[kUnroll])
+template <int U>
+__device__ __forceinline__ void gather_batch(const Batch<U> &B, const double *b, const double *x, double (&g)[U])
 {
 #pragma unroll
-    for (int j = 0; j < kUnroll; j++) {
+    for (int j = 0; j < U; j++) {
         const uint32_t c = B.w[j];
         const bool ext = (c & (HDR | INTL)) == 0;
         const bool hdr = (c & HDR) && c != PAD;
@@ -145,16 +158,17 @@ struct LaneState {
 // write needs no branch.
 using Ring = double (*)[kBlock];
 
-// Handles kUnroll entries in order.  Every entry runs the same instruction
+// Handles U entries in order.  Every entry runs the same instruction
 // sequence: the division that closes a row is evaluated for every entry and
 // kept only at row headers, so the wave never splits on the entry kind.
-__device__ __forceinline__ void process_batch(const Batch &B, const double (&g)[kUnroll], LaneState &st, double *x,
+template <int U>
+__device__ __forceinline__ void process_batch(const Batch<U> &B, const double (&g)[U], LaneState &st, double *x,
                                               Ring ring)
 {
-    double ys[kUnroll];
-    int32_t yrow[kUnroll];
+    double ys[U];
+    int32_t yrow[U];
 #pragma unroll
-    for (int j = 0; j < kUnroll; j++) {
+    for (int j = 0; j < U; j++) {
         const uint32_t c = B.w[j];
         const bool hdr = (c & HDR) != 0;           // row header or padding
         const bool intl = (c >> 30) == 1u;         // same task, a few rows back
@@ -176,7 +190,7 @@ __device__ __forceinline__ void process_batch(const Batch &B, const double (&g)[
         st.cur = hdr ? (c == PAD ? -1 : int32_t(back)) : st.cur;
     }
 #pragma unroll
-    for (int j = 0; j < kUnroll; j++)
+    for (int j = 0; j < U; j++)
         if (yrow[j] >= 0) store_x(x + yrow[j], ys[j]);
 }
 
@@ -198,23 +212,24 @@ __device__ __forceinline__ bool unready(uint32_t c, double g)
 // Waits until every gathered column of the batch holds a computed value.
 // Gives up after spin_limit rounds (setting *err) or once another wave has
 // set *err; the solve's status then reports the failure.
-__device__ __forceinline__ void await_batch(const Batch &B, double (&g)[kUnroll], const double *x, int32_t *err,
+template <int U>
+__device__ __forceinline__ void await_batch(const Batch<U> &B, double (&g)[U], const double *x, int32_t *err,
                                             int64_t spin_limit)
 {
     bool miss = false;
 #pragma unroll
-    for (int j = 0; j < kUnroll; j++) miss |= unready(B.w[j], g[j]);
+    for (int j = 0; j < U; j++) miss |= unready(B.w[j], g[j]);
     if (__ballot(miss) == 0ull) return;
     int32_t nap = 1;
     for (int64_t spins = 1;; spins++) {
         for (int32_t k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(1);
         nap = min(2 * nap, int32_t(kAwaitNapMax));
 #pragma unroll
-        for (int j = 0; j < kUnroll; j++)
+        for (int j = 0; j < U; j++)
             if (unready(B.w[j], g[j])) g[j] = load_x(x + B.w[j]);
         miss = false;
 #pragma unroll
-        for (int j = 0; j < kUnroll; j++) miss |= unready(B.w[j], g[j]);
+        for (int j = 0; j < U; j++) miss |= unready(B.w[j], g[j]);
         if (__ballot(miss) == 0ull) return;
         if (spins > spin_limit) {
             if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -230,7 +245,7 @@ __device__ __forceinline__ void await_batch(const Batch &B, double (&g)[kUnroll]
 #define GLTRSV_STEP(NOW, GNOW, NXT, GNXT, FUT, T0)                                                       \
     do {                                                                                                 \
         gather_batch(NXT, b, x, GNXT);                                                                   \
-        load_batch(cur, (T0) + 2 * kUnroll, FUT);                                                        \
+        load_batch(cur, (T0) + 2 * U, FUT);                                                              \
         if constexpr (kAsync) await_batch(NOW, GNOW, x, err, spin_limit);                                \
         process_batch(NOW, GNOW, st, x, ring);                                                           \
     } while (0)
@@ -239,9 +254,9 @@ __device__ __forceinline__ void await_batch(const Batch &B, double (&g)[kUnroll]
 // loaded by the caller, possibly before the superstep's barrier).  The loop
 // is unrolled three times so the three batch buffers change roles without
 // register copies.
-template <bool kAsync = false>
-__device__ __forceinline__ void run_lane(const LaneCursor &cur, Batch &b0, Batch &b1, const double *b, double *x,
-                                         Ring ring, int32_t *err = nullptr, int64_t spin_limit = 0)
+template <int U, bool kAsync = false>
+__device__ __forceinline__ void run_lane(const LaneCursor &cur, Batch<U> &b0, Batch<U> &b1, const double *b,
+                                         double *x, Ring ring, int32_t *err = nullptr, int64_t spin_limit = 0)
 {
     LaneState st;
     st.acc = 0.0;
@@ -249,19 +264,19 @@ __device__ __forceinline__ void run_lane(const LaneCursor &cur, Batch &b0, Batch
     st.last_y = 0.0;
     st.cur = -1;
     st.pos = 0;
-    Batch b2;
-    double g0[kUnroll], g1[kUnroll], g2[kUnroll];
+    Batch<U> b2;
+    double g0[U], g1[U], g2[U];
     gather_batch(b0, b, x, g0);
     int32_t t0 = 0;
     for (;;) {
         GLTRSV_STEP(b0, g0, b1, g1, b2, t0);
-        t0 += kUnroll;
+        t0 += U;
         if (t0 >= cur.len) break;
         GLTRSV_STEP(b1, g1, b2, g2, b0, t0);
-        t0 += kUnroll;
+        t0 += U;
         if (t0 >= cur.len) break;
         GLTRSV_STEP(b2, g2, b0, g0, b1, t0);
-        t0 += kUnroll;
+        t0 += U;
         if (t0 >= cur.len) break;
     }
     if (st.cur >= 0) store_x(x + st.cur, st.acc / st.diag);
@@ -276,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void trsv_superstep_plain(
     const int32_t c = c0 + int32_t((blockIdx.x * kBlock + threadIdx.x) >> 6);
     if (c >= c1) return;
     const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], threadIdx.x & 63);
-    Batch b0, b1;
+    Batch<kUnroll> b0, b1;
     load_batch(cur, 0, b0);
     load_batch(cur, kUnroll, b1);
     run_lane(cur, b0, b1, b, x, ring);
@@ -398,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void trsv_persistent(
     int32_t c = super_chunk[0] + wave;
     int32_t c_end = super_chunk[1];
     LaneCursor cur = make_cursor(word, value, c < c_end ? chunk_base[c] : 0, c < c_end ? chunk_len[c] : 0, lane);
-    Batch b0, b1;
+    Batch<kUnroll> b0, b1;
     load_batch(cur, 0, b0);
     load_batch(cur, kUnroll, b1);
     for (int32_t s = 0; s < S; s++) {
@@ -462,10 +477,10 @@ __global__ __launch_bounds__(kBlock) void trsv_async(const uint32_t *__restrict_
     const int lane = threadIdx.x & 63;
     for (int32_t c = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6); c < chunks; c += waves) {
         const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
-        Batch b0, b1;
+        Batch<kUnroll> b0, b1;
         load_batch(cur, 0, b0);
         load_batch(cur, kUnroll, b1);
-        run_lane<true>(cur, b0, b1, b, x, ring, err, spin_limit);
+        run_lane<kUnroll, true>(cur, b0, b1, b, x, ring, err, spin_limit);
     }
 }
 
@@ -490,11 +505,11 @@ template <int R>
 using MultiRing = double (*)[R][64];
 
 template <int R>
-__device__ __forceinline__ void gather_multi(const Batch &B, const double *b, const double *x, int64_t ld,
-                                             double (&g)[kUnroll][R])
+__device__ __forceinline__ void gather_multi(const Batch<kUnrollWide> &B, const double *b, const double *x,
+                                             int64_t ld, double (&g)[kUnrollWide][R])
 {
 #pragma unroll
-    for (int j = 0; j < kUnroll; j++) {
+    for (int j = 0; j < kUnrollWide; j++) {
         const uint32_t c = B.w[j];
         const bool ext = (c & (HDR | INTL)) == 0;
         const bool hdr = (c & HDR) && c != PAD;
@@ -505,12 +520,12 @@ __device__ __forceinline__ void gather_multi(const Batch &B, const double *b, co
 }
 
 template <int R>
-__device__ __forceinline__ void await_multi(const Batch &B, double (&g)[kUnroll][R], const double *x, int64_t ld,
-                                            int32_t *err, int64_t spin_limit)
+__device__ __forceinline__ void await_multi(const Batch<kUnrollWide> &B, double (&g)[kUnrollWide][R], const double *x,
+                                            int64_t ld, int32_t *err, int64_t spin_limit)
 {
     bool miss = false;
 #pragma unroll
-    for (int j = 0; j < kUnroll; j++)
+    for (int j = 0; j < kUnrollWide; j++)
 #pragma unroll
         for (int r = 0; r < R; r++) miss |= unready(B.w[j], g[j][r]);
     if (__ballot(miss) == 0ull) return;
@@ -518,7 +533,7 @@ __device__ __forceinline__ void await_multi(const Batch &B, double (&g)[kUnroll]
         __builtin_amdgcn_s_sleep(1);
         miss = false;
 #pragma unroll
-        for (int j = 0; j < kUnroll; j++)
+        for (int j = 0; j < kUnrollWide; j++)
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (unready(B.w[j], g[j][r])) g[j][r] = load_x(x + int64_t(B.w[j]) * ld + r);
@@ -535,14 +550,14 @@ __device__ __forceinline__ void await_multi(const Batch &B, double (&g)[kUnroll]
 
 // process_batch for R columns: the same branch-free sequence per column.
 template <int R>
-__device__ __forceinline__ void process_multi(const Batch &B, const double (&g)[kUnroll][R], MultiState<R> &st,
-                                              double *x, int64_t ld, MultiRing<R> ring)
+__device__ __forceinline__ void process_multi(const Batch<kUnrollWide> &B, const double (&g)[kUnrollWide][R],
+                                              MultiState<R> &st, double *x, int64_t ld, MultiRing<R> ring)
 {
     const int lane = threadIdx.x & 63;
-    double ys[kUnroll][R];
-    int32_t yrow[kUnroll];
+    double ys[kUnrollWide][R];
+    int32_t yrow[kUnrollWide];
 #pragma unroll
-    for (int j = 0; j < kUnroll; j++) {
+    for (int j = 0; j < kUnrollWide; j++) {
         const uint32_t c = B.w[j];
         const bool hdr = (c & HDR) != 0;
         const bool intl = (c >> 30) == 1u;
@@ -572,7 +587,7 @@ __device__ __forceinline__ void process_multi(const Batch &B, const double (&g)[
         st.cur = hdr ? (c == PAD ? -1 : int32_t(back)) : st.cur;
     }
 #pragma unroll
-    for (int j = 0; j < kUnroll; j++)
+    for (int j = 0; j < kUnrollWide; j++)
         if (yrow[j] >= 0)
 #pragma unroll
             for (int r = 0; r < R; r++) store_x(x + int64_t(yrow[j]) * ld + r, ys[j][r]);
@@ -591,18 +606,18 @@ __device__ __forceinline__ void run_lane_multi(const LaneCursor &cur, const doub
     st.diag = 1.0;
     st.cur = -1;
     st.pos = 0;
-    Batch now, nxt;
-    double gnow[kUnroll][R], gnxt[kUnroll][R];
+    Batch<kUnrollWide> now, nxt;
+    double gnow[kUnrollWide][R], gnxt[kUnrollWide][R];
     load_batch(cur, 0, now);
     gather_multi<R>(now, b, x, ld, gnow);
-    for (int32_t t0 = 0; t0 < cur.len; t0 += kUnroll) {
-        load_batch(cur, t0 + kUnroll, nxt);
+    for (int32_t t0 = 0; t0 < cur.len; t0 += kUnrollWide) {
+        load_batch(cur, t0 + kUnrollWide, nxt);
         gather_multi<R>(nxt, b, x, ld, gnxt);
         await_multi<R>(now, gnow, x, ld, err, spin_limit);
         process_multi<R>(now, gnow, st, x, ld, ring);
         now = nxt;
 #pragma unroll
-        for (int j = 0; j < kUnroll; j++)
+        for (int j = 0; j < kUnrollWide; j++)
 #pragma unroll
             for (int r = 0; r < R; r++) gnow[j][r] = gnxt[j][r];
     }
@@ -780,7 +795,7 @@ __global__ __launch_bounds__(kBlock) void trsv_batched(const SysDesc *__restrict
         const SysDesc d = sys[found];
         for (int32_t c = c0; c < c1; c++) {
             const LaneCursor cur = make_cursor(d.word, d.value, d.chunk_base[c], d.chunk_len[c], lane);
-            Batch b0, b1;
+            Batch<kUnroll> b0, b1;
             load_batch(cur, 0, b0);
             load_batch(cur, kUnroll, b1);
             run_lane(cur, b0, b1, d.b, d.x, ring);
@@ -819,20 +834,20 @@ __global__ __launch_bounds__(kBlock) void gather_probe(const uint32_t *__restric
     const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
     double acc = 0.0;
     int32_t row = -1;
-    Batch now, nxt;
+    Batch<kUnrollWide> now, nxt;
     load_batch(cur, 0, now);
-    for (int32_t t0 = 0; t0 < cur.len; t0 += kUnroll) {
-        load_batch(cur, t0 + kUnroll, nxt);
-        double g[kUnroll];
+    for (int32_t t0 = 0; t0 < cur.len; t0 += kUnrollWide) {
+        load_batch(cur, t0 + kUnrollWide, nxt);
+        double g[kUnrollWide];
 #pragma unroll
-        for (int j = 0; j < kUnroll; j++) {
+        for (int j = 0; j < kUnrollWide; j++) {
             const uint32_t w = now.w[j];
             const bool ext = (w & (HDR | INTL)) == 0;
             const double gx = load_x(ext ? x + w : x);
             g[j] = ext ? gx : 1.0;
         }
 #pragma unroll
-        for (int j = 0; j < kUnroll; j++) {
+        for (int j = 0; j < kUnrollWide; j++) {
             const uint32_t w = now.w[j];
             if (w & HDR) {
                 if (row >= 0) y[row] = acc;
@@ -936,10 +951,10 @@ __global__ __launch_bounds__(kBlock) void trsv_batched_async(const SysDesc *__re
         const SysDesc d = sys[found];
         for (int32_t c = c0; c < c1; c++) {
             const LaneCursor cur = make_cursor(d.word, d.value, d.chunk_base[c], d.chunk_len[c], lane);
-            Batch b0, b1;
+            Batch<kUnrollWide> b0, b1;
             load_batch(cur, 0, b0);
-            load_batch(cur, kUnroll, b1);
-            run_lane<true>(cur, b0, b1, d.b, d.x, ring, err, spin_limit);
+            load_batch(cur, kUnrollWide, b1);
+            run_lane<kUnrollWide, true>(cur, b0, b1, d.b, d.x, ring, err, spin_limit);
         }
         // the chunks' x stores are complete before they are counted as done
         __builtin_amdgcn_s_waitcnt(0);
