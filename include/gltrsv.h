@@ -229,6 +229,8 @@ typedef struct gltrsv_plan_info {
                                execution named by opts.exec_hint              */
     int32_t device_packed;  /* 1 if the stream was filled on the device       */
     int32_t async_grid_blocks; /* workgroups of gltrsv_solve_async            */
+    int32_t exec_form;      /* preferred execution form of gltrsv_solve_auto
+                               (GLTRSV_EXEC_*)                                */
 } gltrsv_plan_info;
 
 /* Analyses A (checks, schedule, Sec. 5 order) and uploads the packed matrix
@@ -397,6 +399,37 @@ int gltrsv_solve_async(gltrsv_plan *plan, const double *b, double *x, void *stre
  * by those columns.  Asynchronous on `stream`; errors are reported by
  * gltrsv_plan_device_status. */
 int gltrsv_solve_multi(gltrsv_plan *plan, const double *b, double *x, int32_t nrhs, void *stream);
+
+/* ------------------------------------------------------- execution forms */
+/* The three single-system forms give the same bits; which is fastest depends
+ * on the matrix and its schedule (many short supersteps favour the
+ * semi-asynchronous form, a few wide ones the persistent form). */
+#define GLTRSV_EXEC_PERSISTENT 0   /* gltrsv_solve       */
+#define GLTRSV_EXEC_PLAIN      1   /* gltrsv_solve_plain */
+#define GLTRSV_EXEC_ASYNC      2   /* gltrsv_solve_async */
+
+/* Solves with the plan's preferred form: the one given to
+ * gltrsv_plan_set_exec or found by gltrsv_plan_tune, initially the form that
+ * opts.exec_hint names (persistent, or semi-asynchronous).  Arguments as for
+ * gltrsv_solve (b may alias x). */
+int gltrsv_solve_auto(gltrsv_plan *plan, const double *b, double *x, void *stream);
+
+/* Sets the preferred form (GLTRSV_EXEC_*, else EINVAL), e.g. from a stored
+ * tuning result. */
+int gltrsv_plan_set_exec(gltrsv_plan *plan, int32_t form);
+
+/* Times the three forms on this plan and makes the fastest the preferred
+ * one (an autotuner; the cost-model choice of opts.exec_hint is a
+ * prediction, this is a measurement).  Each form solves b -> x once untimed,
+ * then `reps` times (>= 1) between two HIP events on `stream`.  b and x:
+ * device, n values each, caller-owned, not overlapping (EINVAL); x ends
+ * holding the solution.  us_out (host, 3 doubles, may be NULL) receives the
+ * mean microseconds per solve in GLTRSV_EXEC_* order, *best (may be NULL)
+ * the chosen form.  Synchronises `stream`.  If a device-side wait ran out
+ * during the measurement the preference is left unchanged and the call
+ * returns GLTRSV_ETIMEDOUT. */
+int gltrsv_plan_tune(gltrsv_plan *plan, const double *b, double *x, int32_t reps, void *stream, double *us_out,
+                     int32_t *best);
 
 /* Plain device-to-device copy of `bytes` (a multiple of 16) from src to dst
  * (device pointers, caller-owned, non-overlapping), asynchronous on `stream`.

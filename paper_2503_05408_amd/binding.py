@@ -35,6 +35,10 @@ UPPER = 1
 PACK_AUTO = 0
 PACK_HOST = 1
 PACK_DEVICE = 2
+EXEC_PERSISTENT = 0
+EXEC_PLAIN = 1
+EXEC_ASYNC = 2
+EXEC_NAMES = {EXEC_PERSISTENT: "persistent", EXEC_PLAIN: "plain", EXEC_ASYNC: "async"}
 
 
 class GltrsvError(RuntimeError):
@@ -77,7 +81,7 @@ class PlanInfo(ctypes.Structure):
                 ("chunks", i64), ("stream_slots", i64), ("device_bytes", i64), ("analysis_ns", i64),
                 ("pattern_key", u64), ("grid_blocks", i32), ("block_size", i32), ("max_task_rows", i64),
                 ("schedule_kind", i32), ("predicted_us", dbl), ("device_packed", i32),
-                ("async_grid_blocks", i32)]
+                ("async_grid_blocks", i32), ("exec_form", i32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -106,6 +110,9 @@ SIGNATURES = {
     "gltrsv_solve_async": ([P, P, P, P], i32),
     "gltrsv_solve_multi": ([P, P, P, i32, P], i32),
     "gltrsv_plan_set_spin_limit": ([P, i64], i32),
+    "gltrsv_solve_auto": ([P, P, P, P], i32),
+    "gltrsv_plan_set_exec": ([P, i32], i32),
+    "gltrsv_plan_tune": ([P, P, P, i32, P, P, P], i32),
     "gltrsv_plan_stream": ([P, P, P, i64], i32),
     "gltrsv_default_batch_opts": ([P], None),
     "gltrsv_batch_create": ([P, i32, P, P], i32),
@@ -129,10 +136,16 @@ def lib_path() -> str:
 
 
 def load(build_if_missing: bool = True):
-    """Loads the HIP library (building it only if no build exists)."""
+    """Loads the HIP library (building it only if no build exists).
+
+    torch is imported first: its wheel carries its own HIP runtime, and the
+    library must bind to that same runtime (loading the library first would
+    bring a second runtime into the process, and the one initialised second
+    finds no device)."""
     global _lib
     with _lock:
         if _lib is None:
+            import torch  # noqa: F401
             if not os.path.exists(_build.LIB):
                 if not build_if_missing:
                     raise RuntimeError(f"{_build.LIB} is not built")
@@ -333,6 +346,34 @@ class Plan:
         _check(load().gltrsv_solve(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
                "gltrsv_solve")
         return x
+
+    def solve_auto(self, b, x=None, stream=None):
+        """Solve with the plan's preferred execution form (tune / set_exec)."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        _check(load().gltrsv_solve_auto(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
+               "gltrsv_solve_auto")
+        return x
+
+    def set_exec(self, form: int):
+        """Sets the preferred execution form (EXEC_PERSISTENT/PLAIN/ASYNC)."""
+        _check(load().gltrsv_plan_set_exec(self._p, int(form)), "gltrsv_plan_set_exec")
+
+    def tune(self, b=None, x=None, reps: int = 5, stream=None) -> dict:
+        """Times the three execution forms and makes the fastest the
+        preferred one; returns {"form": name, "us": {name: microseconds}}.
+        b defaults to ones; b and x must not overlap."""
+        import torch
+        if b is None:
+            b = torch.ones(self.n, dtype=torch.float64, device="cuda")
+        if x is None:
+            x = torch.empty_like(b)
+        us = (ctypes.c_double * 3)()
+        best = i32(0)
+        _check(load().gltrsv_plan_tune(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), int(reps),
+                                       _stream_ptr(stream), us, ctypes.byref(best)), "gltrsv_plan_tune")
+        return {"form": EXEC_NAMES[best.value], "us": {EXEC_NAMES[f]: us[f] for f in range(3)}}
 
     def set_spin_limit(self, polls: int):
         """Polls a device-side wait may take before the solve reports a time-out."""

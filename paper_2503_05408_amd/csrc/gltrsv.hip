@@ -1333,6 +1333,7 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         return rc;
     }
     p->device_packed = on_device;
+    p->exec_form = opts->exec_hint == 1 ? GLTRSV_EXEC_ASYNC : GLTRSV_EXEC_PERSISTENT;
     if ((rc = upload(&p->d_chunk_base, pk.chunk_base, &bytes)) || (rc = upload(&p->d_chunk_len, pk.chunk_len, &bytes)) ||
         (rc = upload(&p->d_super_chunk, pk.super_chunk, &bytes))) {
         gltrsv_plan_destroy(p);
@@ -1420,6 +1421,7 @@ int gltrsv_plan_info_get(const gltrsv_plan *p, gltrsv_plan_info *o)
     o->predicted_us = p->predicted_us;
     o->device_packed = p->device_packed ? 1 : 0;
     o->async_grid_blocks = p->grid_async;
+    o->exec_form = p->exec_form;
     return GLTRSV_OK;
 }
 
@@ -1627,6 +1629,78 @@ int gltrsv_plan_set_spin_limit(gltrsv_plan *p, int64_t polls)
 {
     if (!p || polls < 1) return set_error(GLTRSV_EINVAL, "polls must be >= 1");
     p->spin_limit = polls;
+    return GLTRSV_OK;
+}
+
+int gltrsv_solve_auto(gltrsv_plan *p, const double *b, double *x, void *stream)
+{
+    if (!p) return set_error(GLTRSV_EINVAL, "null plan");
+    switch (p->exec_form) {
+    case GLTRSV_EXEC_PLAIN: return gltrsv_solve_plain(p, b, x, stream);
+    case GLTRSV_EXEC_ASYNC: return gltrsv_solve_async(p, b, x, stream);
+    default: return gltrsv_solve(p, b, x, stream);
+    }
+}
+
+int gltrsv_plan_set_exec(gltrsv_plan *p, int32_t form)
+{
+    if (!p) return set_error(GLTRSV_EINVAL, "null plan");
+    if (form != GLTRSV_EXEC_PERSISTENT && form != GLTRSV_EXEC_PLAIN && form != GLTRSV_EXEC_ASYNC)
+        return set_error(GLTRSV_EINVAL, "unknown execution form");
+    p->exec_form = form;
+    return GLTRSV_OK;
+}
+
+namespace {
+// Event pair released on every return path.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+}  // namespace
+
+int gltrsv_plan_tune(gltrsv_plan *p, const double *b, double *x, int32_t reps, void *stream, double *us_out,
+                     int32_t *best)
+{
+    if (!p || reps < 1) return set_error(GLTRSV_EINVAL, "null plan or reps < 1");
+    if (p->n && (!b || !x)) return set_error(GLTRSV_EINVAL, "null argument");
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(b), x0 = reinterpret_cast<uintptr_t>(x);
+    const uintptr_t len = uintptr_t(p->n) * sizeof(double);
+    if (p->n && b0 < x0 + len && x0 < b0 + len) return set_error(GLTRSV_EINVAL, "b and x overlap");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    using SolveFn = int (*)(gltrsv_plan *, const double *, double *, void *);
+    const SolveFn forms[3] = {gltrsv_solve, gltrsv_solve_plain, gltrsv_solve_async};
+    double us[3] = {0.0, 0.0, 0.0};
+    EventPair ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    for (int f = 0; f < 3; f++) {
+        int rc = forms[f](p, b, x, stream);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(ev.a, st));
+        for (int32_t r = 0; r < reps && rc == 0; r++) rc = forms[f](p, b, x, stream);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(ev.b, st));
+        HIP_TRY(hipEventSynchronize(ev.b));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+        us[f] = 1000.0 * double(ms) / reps;
+    }
+    int32_t status = 0;
+    int rc = gltrsv_plan_device_status(p, &status);
+    if (rc) return rc;
+    if (status) return set_error(GLTRSV_ETIMEDOUT, "a device-side wait ran out during tuning");
+    int32_t f_best = 0;
+    for (int32_t f = 1; f < 3; f++)
+        if (us[f] < us[f_best]) f_best = f;
+    p->exec_form = f_best;
+    if (us_out)
+        for (int f = 0; f < 3; f++) us_out[f] = us[f];
+    if (best) *best = f_best;
     return GLTRSV_OK;
 }
 

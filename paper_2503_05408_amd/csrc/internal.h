@@ -137,6 +137,7 @@ struct gltrsv_plan {
     int grid_async = 0;             // workgroups of the semi-asynchronous kernel
     double *d_bcopy = nullptr;      // b when a semi-asynchronous solve runs in place
     int cooperative = 0;
+    int32_t exec_form = 0;          // preferred form of gltrsv_solve_auto (GLTRSV_EXEC_*)
 };
 
 inline int64_t widest_of(const std::vector<gltrsv_plan *> &plans)
