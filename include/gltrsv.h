@@ -60,6 +60,7 @@ extern "C" {
 #define GLTRSV_EHIP       -8   /* a HIP runtime call failed                  */
 #define GLTRSV_ETIMEDOUT  -9   /* a device-side wait exceeded its spin limit */
 #define GLTRSV_ENOTSUP   -10   /* not supported on this device/build         */
+#define GLTRSV_ENOENT    -11   /* server: no pending request with this ticket */
 
 /* Text for the last error on the calling thread (never NULL). */
 const char *gltrsv_last_error(void);
@@ -349,6 +350,7 @@ typedef struct gltrsv_server_opts {
 
 typedef struct gltrsv_server_stats {
     int64_t submitted, completed, failed, launches, rows_completed, queued, inflight_bytes;
+    int64_t cancelled;
 } gltrsv_server_stats;
 
 void gltrsv_default_server_opts(gltrsv_server_opts *opts);
@@ -370,6 +372,15 @@ int gltrsv_server_submit(gltrsv_server *server, gltrsv_plan *plan, const double 
 int gltrsv_server_poll(gltrsv_server *server, uint64_t *tickets, int64_t *done_ns, int32_t max, int32_t *ndone);
 
 int gltrsv_server_get_stats(gltrsv_server *server, gltrsv_server_stats *out);
+
+/* Withdraws a request that has not completed.  A queued request is removed
+ * at once; one already on the device is dropped at the next quantum boundary
+ * (the worker stops scheduling its chunks; chunks already claimed finish).
+ * Either way the ticket is never reported by gltrsv_server_poll, its budget
+ * is released, and its x is left partly written (undefined).  GLTRSV_ENOENT
+ * if no pending request has this ticket (unknown, completed or cancelled).
+ * Thread-safe. */
+int gltrsv_server_cancel(gltrsv_server *server, uint64_t ticket);
 
 /* Monotonic host clock used for completion times, in nanoseconds. */
 int64_t gltrsv_clock_ns(void);

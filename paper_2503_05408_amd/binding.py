@@ -24,7 +24,7 @@ i32, i64, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_d
 GLTRSV_OK = 0
 ERRORS = {
     -1: "EINVAL", -2: "ENOTLOWER", -3: "ESINGULAR", -4: "EUNSORTED", -5: "ERANGE",
-    -6: "ENOMEM", -7: "EAGAIN", -8: "EHIP", -9: "ETIMEDOUT", -10: "ENOTSUP",
+    -6: "ENOMEM", -7: "EAGAIN", -8: "EHIP", -9: "ETIMEDOUT", -10: "ENOTSUP", -11: "ENOENT",
 }
 SCHED_GROWLOCAL = 0
 SCHED_WAVEFRONT = 1
@@ -70,7 +70,7 @@ class ServerOpts(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", i64), ("completed", i64), ("failed", i64), ("launches", i64),
-                ("rows_completed", i64), ("queued", i64), ("inflight_bytes", i64)]
+                ("rows_completed", i64), ("queued", i64), ("inflight_bytes", i64), ("cancelled", i64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -126,6 +126,7 @@ SIGNATURES = {
     "gltrsv_server_submit": ([P, P, P, P, P], i32),
     "gltrsv_server_poll": ([P, P, P, i32, P], i32),
     "gltrsv_server_get_stats": ([P, P], i32),
+    "gltrsv_server_cancel": ([P, u64], i32),
     "gltrsv_clock_ns": ([], i64),
     "gltrsv_server_destroy": ([P], i32),
 }
@@ -549,6 +550,15 @@ class Server:
         k = ctypes.c_int32(0)
         _check(load().gltrsv_server_poll(self._p, tk, ns, max_items, ctypes.byref(k)), "gltrsv_server_poll")
         return [(tk[i], ns[i]) for i in range(k.value)]
+
+    def cancel(self, ticket: int) -> bool:
+        """Withdraws a pending request (never reported by poll afterwards);
+        False if no pending request has this ticket."""
+        rc = load().gltrsv_server_cancel(self._p, ctypes.c_uint64(int(ticket)))
+        if rc == -11:
+            return False
+        _check(rc, "gltrsv_server_cancel")
+        return True
 
     def stats(self) -> dict:
         st = ServerStats()

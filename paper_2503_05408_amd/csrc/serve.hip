@@ -42,6 +42,7 @@ struct Request {
 struct Slot {
     bool busy = false;
     bool fresh = false;     // admitted since the last launch
+    bool cancel = false;    // withdrawn: dropped at the next quantum boundary
     Request req;
     int32_t done_off = 0;
 };
@@ -175,6 +176,21 @@ int run_quantum(gltrsv_server *sv, int32_t used, int32_t busy)
     return GLTRSV_OK;
 }
 
+// Frees slot i of a withdrawn request (caller holds the lock, no launch in
+// flight): its descriptor is emptied, so the next launch sees it finished.
+void release_slot(gltrsv_server *sv, int32_t i)
+{
+    Slot &sl = sv->slots[i];
+    sv->stats.cancelled++;
+    sv->inflight_bytes -= sl.req.bytes;
+    sv->arena->give(sl.done_off, std::max(1, sl.req.plan->S));
+    sl.busy = false;
+    sl.cancel = false;
+    sv->h_desc[i].S = 0;
+    sv->h_desc[i].nchunks = 0;
+    sl.fresh = true;
+}
+
 void worker_main(gltrsv_server *sv)
 {
     if (hipSetDevice(sv->device) != hipSuccess) {
@@ -187,6 +203,9 @@ void worker_main(gltrsv_server *sv)
         int32_t used = 0, busy = 0;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
+            // drop withdrawn requests: no chunk of theirs is in flight between quanta
+            for (int32_t i = 0; i < int32_t(sv->slots.size()); i++)
+                if (sv->slots[i].busy && sv->slots[i].cancel) release_slot(sv, i);
             // admit queued requests into the lowest free slots
             while (!sv->queue.empty()) {
                 int32_t free_slot = -1;
@@ -202,6 +221,7 @@ void worker_main(gltrsv_server *sv)
                 Slot &sl = sv->slots[free_slot];
                 sl.busy = true;
                 sl.fresh = true;
+                sl.cancel = false;
                 sl.req = r;
                 sl.done_off = off;
                 dev::SysDesc &d = sv->h_desc[free_slot];
@@ -253,7 +273,9 @@ void worker_main(gltrsv_server *sv)
             if (!sl.busy) continue;
             // complete: the open superstep passed S, or (semi-asynchronous) every chunk is done
             const int64_t hi = int64_t(sv->h_state[i] >> 32);
-            if (sv->opts.async_exec ? hi >= sl.req.plan->chunks : hi >= sl.req.plan->S) {
+            if (sl.cancel) {
+                release_slot(sv, i);   // withdrawn during the quantum: never reported
+            } else if (sv->opts.async_exec ? hi >= sl.req.plan->chunks : hi >= sl.req.plan->S) {
                 sv->completed.emplace_back(sl.req.ticket, t);
                 sv->stats.completed++;
                 sv->stats.rows_completed += sl.req.plan->n;
@@ -386,6 +408,25 @@ int gltrsv_server_get_stats(gltrsv_server *sv, gltrsv_server_stats *out)
     out->queued = int64_t(sv->queue.size());
     out->inflight_bytes = sv->inflight_bytes;
     return GLTRSV_OK;
+}
+
+int gltrsv_server_cancel(gltrsv_server *sv, uint64_t ticket)
+{
+    if (!sv) return set_error(GLTRSV_EINVAL, "null server");
+    std::lock_guard<std::mutex> g(sv->mu);
+    for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
+        if (it->ticket == ticket) {
+            sv->inflight_bytes -= it->bytes;
+            sv->stats.cancelled++;
+            sv->queue.erase(it);
+            return GLTRSV_OK;
+        }
+    for (Slot &sl : sv->slots)
+        if (sl.busy && !sl.cancel && sl.req.ticket == ticket) {
+            sl.cancel = true;
+            return GLTRSV_OK;
+        }
+    return set_error(GLTRSV_ENOENT, "no pending request with this ticket");
 }
 
 int64_t gltrsv_clock_ns(void) { return now_ns(); }

@@ -98,3 +98,45 @@ def test_request_larger_than_budget_rejected(pool):
         bd = torch.ones(ms[0].n, dtype=torch.float64, device="cuda")
         with pytest.raises(B.GltrsvError):
             sv.submit(plans[0], bd, torch.empty_like(bd))
+
+
+@pytest.mark.parametrize("async_exec", [0, 1])
+def test_cancel_queued_and_running_requests(async_exec):
+    # one slot: the first request runs while the others wait in the queue; a
+    # queued request is withdrawn at once, a running one at the next quantum
+    # boundary; withdrawn tickets are never reported, the others stay exact,
+    # and the budget and the slot are released
+    import torch
+    long_m = gen.narrow_band(100_000, 0.03, 42, gen.SEED_BASE + 10)   # thousands of tiny supersteps
+    short_m = gen.erdos_renyi(3000, 0.003, gen.SEED_BASE + 44)
+    with B.Plan(long_m, B.gpu_opts(schedule_kind=B.SCHED_WAVEFRONT)) as pl, B.Plan(short_m, B.gpu_opts()) as ps:
+        want_s = oracle.solve(short_m, np.ones(short_m.n))
+        want_l = oracle.solve(long_m, np.ones(long_m.n))
+        bl = torch.ones(long_m.n, dtype=torch.float64, device="cuda")
+        bs = torch.ones(short_m.n, dtype=torch.float64, device="cuda")
+        xs = [torch.full_like(bs, float("nan")) for _ in range(3)]
+        xl = [torch.full_like(bl, float("nan")) for _ in range(2)]
+        torch.cuda.synchronize()
+        with B.Server(quantum_us=100.0, max_slots=1, async_exec=async_exec) as sv:
+            t_run = sv.submit(pl, bl, xl[0])          # admitted first, runs for many quanta
+            t_q1 = sv.submit(ps, bs, xs[0])           # waits behind it
+            t_q2 = sv.submit(ps, bs, xs[1])
+            t_q3 = sv.submit(pl, bl, xl[1])
+            assert None not in (t_run, t_q1, t_q2, t_q3)
+            assert sv.cancel(t_q2)                    # still queued
+            assert not sv.cancel(t_q2)                # no longer pending
+            time.sleep(0.002)
+            assert sv.cancel(t_run)                   # on the device by now (or still queued)
+            assert not sv.cancel(987654321)           # unknown ticket
+            done = drain(sv, 2)
+            assert set(done) == {t_q1, t_q3}, (done, sv.stats())
+            t_after = sv.submit(ps, bs, xs[2])        # the slot is usable again
+            done.update(drain(sv, 1))
+            assert t_after in done and t_run not in done and t_q2 not in done
+            st = sv.stats()
+            assert st["cancelled"] == 2 and st["completed"] == 3 and st["failed"] == 0, st
+            assert st["inflight_bytes"] == 0 and st["queued"] == 0, st
+        torch.cuda.synchronize()
+        assert oracle.same_bits(xs[0].cpu().numpy(), want_s)
+        assert oracle.same_bits(xs[2].cpu().numpy(), want_s)
+        assert oracle.same_bits(xl[1].cpu().numpy(), want_l)
