@@ -61,3 +61,71 @@ def tune_cached(plan, path: str, reps: int = 5) -> str:
     table[key] = res
     store_table(path, table)
     return res["form"]
+
+
+SCHEDULES = {B.SCHED_GROWLOCAL: "growlocal", B.SCHED_WAVEFRONT: "wavefront"}
+
+
+def matrix_key(m, opts) -> str:
+    """Identifies a plan before it exists: a hash of the sparsity pattern,
+    the triangle, every schedule parameter except the kind, and the device."""
+    import hashlib
+
+    import numpy as np
+    import torch
+    h = hashlib.blake2b(digest_size=12)
+    h.update(np.int64(m.n).tobytes())
+    h.update(np.ascontiguousarray(m.row_ptr, dtype=np.int64).tobytes())
+    h.update(np.ascontiguousarray(m.col, dtype=np.int32).tobytes())
+    tri = "upper" if opts.triangle == B.UPPER else "lower"
+    sig = (f"k{opts.k}-L{opts.L:g}-a{opts.alpha0:g}-g{opts.growth:g}-t{opts.accept:g}-b{opts.blocks}"
+           f"-f{opts.funnel_max_weight}")
+    dev = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{h.hexdigest()}/{tri}/{sig}/{dev.name}/{getattr(dev, 'gcnArchName', '')}"
+
+
+def best_plan(m, opts=None, path: str | None = None, reps: int = 5):
+    """A plan for m with the measured-fastest schedule (GrowLocal or
+    wavefront) and execution form (persistent, plain, semi-asynchronous) for
+    gltrsv_solve_auto.  With `path`, the choice is read from / stored in the
+    JSON table there, so a later process builds only the chosen schedule.
+    Returns (plan, entry) with entry = {"schedule", "form", "us"}."""
+    import ctypes
+    base = opts if opts is not None else B.gpu_opts()
+
+    def with_kind(kind):
+        o = B.PlanOpts()
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(base), ctypes.sizeof(o))
+        o.schedule_kind = kind
+        return o
+
+    names = {v: k for k, v in SCHEDULES.items()}
+    forms = {v: k for k, v in B.EXEC_NAMES.items()}
+    key = matrix_key(m, base) if path else None
+    if path:
+        hit = load_table(path).get(key)
+        if isinstance(hit, dict) and hit.get("schedule") in names and hit.get("form") in forms:
+            plan = B.Plan(m, with_kind(names[hit["schedule"]]))
+            plan.set_exec(forms[hit["form"]])
+            return plan, hit
+    best, best_us, times = None, None, {}
+    for kind, sname in SCHEDULES.items():
+        plan = B.Plan(m, with_kind(kind))
+        res = plan.tune(reps=reps)
+        for f, us in res["us"].items():
+            times[f"{sname}/{f}"] = us
+        us = res["us"][res["form"]]
+        if best_us is None or us < best_us:
+            if best is not None:
+                best[0].close()
+            best, best_us = (plan, sname, res["form"]), us
+        else:
+            plan.close()
+    plan, sname, form = best
+    plan.set_exec(forms[form])
+    entry = {"schedule": sname, "form": form, "us": times}
+    if path:
+        table = load_table(path)
+        table[key] = entry
+        store_table(path, table)
+    return plan, entry

@@ -1,7 +1,8 @@
 """Execution forms and their autotuner (GPU): gltrsv_solve_auto runs the
 preferred form, gltrsv_plan_set_exec sets it, gltrsv_plan_tune measures the
 three forms and keeps the fastest; every form stays bit-identical to the
-oracle, and the JSON table of tuning.tune_cached reproduces a stored choice."""
+oracle, the JSON tables of tuning.tune_cached and tuning.best_plan (schedule
+and form) reproduce a stored choice."""
 import json
 
 import numpy as np
@@ -124,3 +125,37 @@ def test_tuning_table_round_trip(tmp_path):
     # a different schedule of the same pattern has its own entry
     with B.Plan(m, B.gpu_opts(schedule_kind=B.SCHED_GROWLOCAL, k=7)) as plan:
         assert tuning.tuning_key(plan) != key
+
+
+def test_best_plan_over_schedules_and_forms(tmp_path):
+    import torch
+    path = str(tmp_path / "best.json")
+    m = gen.erdos_renyi(20000, 2e-4, gen.SEED_BASE + 45)
+    want = oracle.solve(m, np.ones(m.n))
+    plan, entry = tuning.best_plan(m, B.gpu_opts(), path, reps=3)
+    print(entry, flush=True)
+    with plan:
+        assert len(entry["us"]) == 6
+        fastest = min(entry["us"], key=entry["us"].get)
+        assert fastest == f"{entry['schedule']}/{entry['form']}"
+        kind = {"growlocal": B.SCHED_GROWLOCAL, "wavefront": B.SCHED_WAVEFRONT}[entry["schedule"]]
+        assert plan.info()["schedule_kind"] == kind
+        assert B.EXEC_NAMES[plan.info()["exec_form"]] == entry["form"]
+        x = plan.solve_auto(torch.ones(m.n, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        assert oracle.same_bits(x.cpu().numpy(), want)
+    # from the table: only the stored choice is built, nothing is measured
+    table = tuning.load_table(path)
+    (key,) = table
+    table[key] = {"schedule": "wavefront", "form": "plain", "us": {}}
+    tuning.store_table(path, table)
+    plan, entry = tuning.best_plan(m, B.gpu_opts(), path)
+    with plan:
+        assert entry["schedule"] == "wavefront" and entry["form"] == "plain"
+        assert plan.info()["schedule_kind"] == B.SCHED_WAVEFRONT
+        assert plan.info()["exec_form"] == B.EXEC_PLAIN
+        x = plan.solve_auto(torch.ones(m.n, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        assert oracle.same_bits(x.cpu().numpy(), want)
+    # other schedule parameters are another entry
+    assert tuning.matrix_key(m, B.gpu_opts(L=20.0)) != key
