@@ -406,7 +406,12 @@ __global__ __launch_bounds__(kBlock) void trsv_persistent(
     double *x, uint32_t *bar, int32_t *err, int64_t spin_limit, int64_t *trace)
 {
     const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
-    const int32_t wave = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
+    // wave slot: the i-th wave of workgroup g is slot i G + g.  Chunks of a
+    // superstep are sorted longest first, so every workgroup (one per CU)
+    // takes one chunk from each quarter of that order, and a narrow
+    // superstep spreads over as many CUs as it has chunks, instead of
+    // filling the first CUs with the longest chunks four at a time.
+    const int32_t wave = int32_t(threadIdx.x >> 6) * int32_t(gridDim.x) + int32_t(blockIdx.x);
     const int lane = threadIdx.x & 63;
     __shared__ double ring[kRing + 1][kBlock];
     // first chunk of this wave in superstep 0, and its first two batches
