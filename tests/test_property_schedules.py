@@ -30,14 +30,16 @@ params = st.fixed_dictionaries({
     "accept": st.sampled_from([0.9, 0.97, 1.0]),
 })
 
-SETTINGS = settings(max_examples=400, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+# 10,000 random cases in all (4,000 for plain GrowLocal, 2,000 for each variant)
+SETTINGS = settings(max_examples=2000, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+SETTINGS_MAIN = settings(max_examples=4000, deadline=None, suppress_health_check=[HealthCheck.too_slow])
 
 
 def _oracle_args(p):
     return dict(L=p["L"], alpha0=p["alpha0"], growth=p["growth"], theta=p["accept"])
 
 
-@SETTINGS
+@SETTINGS_MAIN
 @given(lower_patterns(), params)
 def test_growlocal_library_equals_oracle(m, p):
     core, sup, S = B.schedule(m, B.default_opts(**p))
