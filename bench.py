@@ -13,6 +13,7 @@ the CPU oracle's (checked before timing).
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import platform
@@ -224,6 +225,28 @@ def main():
     torch.cuda.synchronize()
     ms_plain = p0.elapsed_time(p1) / args.plain_steps
 
+    # the same schedule without the reorder of Sec. 5 (A in its CSR order,
+    # one launch per superstep): the locality comparison of Table 7.3
+    core, sup, _ = plan.schedule()
+    uopts = B.PlanOpts()
+    ctypes.memmove(ctypes.byref(uopts), ctypes.byref(opts), ctypes.sizeof(uopts))
+    uopts.reorder = 0
+    with B.Plan(m, uopts, schedule=(core, sup)) as uplan:
+        x.fill_(float("nan"))
+        uplan.solve_unordered(b, x)
+        torch.cuda.synchronize()
+        exact_unordered = oracle.same_bits(x.cpu().numpy(), want)
+        uplan.solve_unordered(b, x)
+        u0 = torch.cuda.Event(enable_timing=True)
+        u1 = torch.cuda.Event(enable_timing=True)
+        u0.record(stream)
+        for _ in range(args.plain_steps):
+            uplan.solve_unordered(b, x)
+        u1.record(stream)
+        torch.cuda.synchronize()
+        ms_unordered = u0.elapsed_time(u1) / args.plain_steps
+    del core, sup
+
     # semi-asynchronous form: no barriers, per-row readiness
     x.fill_(0.0)
     plan.solve_async(b, x)
@@ -345,6 +368,8 @@ def main():
         "plain": {"value": rows_s_plain, "ms_per_step": ms_plain, "launches_per_step": info["supersteps"],
                   "graph_ms_per_step": ms_graph},
         "speedup_vs_plain": (ms_plain / ms) if ms > 0 else None,
+        "unordered": {"ms_per_step": ms_unordered, "exact": bool(exact_unordered),
+                      "reorder_speedup": (ms_unordered / ms_plain) if ms_plain > 0 else None},
         "multi_rhs": multi,
         "async": {"ms_per_step": ms_async, "exact": bool(exact_async),
                   "value": (m.n / (ms_async * 1e-3)) if exact_async else 0.0},
@@ -430,197 +455,6 @@ def bench_analysis(args):
                       "schedule": f"growlocal k={args.k} L={args.L:g} alpha0={args.alpha0:g}",
                       "host_threads": os.cpu_count(), "serial_cpu_solve_s": serial_s, "wavefront": wf,
                       "blocks": rows}), flush=True)
-
-
-def bench_paper(args):
-    """The paper's synthetic sets at paper size (ER p in {1e-4, 5e-4, 2e-3} and
-    NB (p, B) in {(0.14, 10), (0.05, 20), (0.03, 42)}, n = 1e5, ten instances
-    each): per set, the geometric mean over instances of the speed-up over one
-    serial solve on one host core (the kind of number of Table 7.1) for each
-    schedule and execution form, and the mean ratio wavefronts / supersteps
-    (Table 7.2).  Every timed result is checked against the oracle bit for
-    bit."""
-    import torch
-    import oracle
-    from paper_2503_05408_amd import binding as B
-    from paper_2503_05408_amd import gen
-    stream = torch.cuda.current_stream()
-
-    def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps * 1e-3
-
-    sets = [("ER", p, None) for p in gen.ER_PROBS] + [("NB", p, Bw) for p, Bw in gen.NB_PAIRS]
-    o_gl, o_wf, o_auto = B.gpu_opts(), B.default_opts(schedule_kind=B.SCHED_WAVEFRONT), \
-        B.gpu_opts(schedule_kind=B.SCHED_AUTO)
-    o_auto_a = B.gpu_opts(schedule_kind=B.SCHED_AUTO, exec_hint=1)
-    forms = {"GL persistent": (o_gl, "solve"), "GL async": (o_gl, "solve_async"),
-             "wavefront persistent": (o_wf, "solve"), "wavefront async": (o_wf, "solve_async"),
-             "AUTO persistent": (o_auto, "solve"), "AUTO async": (o_auto_a, "solve_async")}
-    report = []
-    for fam, p, Bw in sets:
-        logs = {f: [] for f in forms}
-        ratios, all_exact = [], True
-        kept, serial_total = [], 0.0   # (matrix, wavefront plan, AUTO plan, want) for the batched launches
-        for i in range(args.instances):
-            m = (gen.erdos_renyi_paper(100_000, p, gen.SEED_BASE + i) if fam == "ER"
-                 else gen.narrow_band(100_000, p, Bw, gen.SEED_BASE + 10 + i))
-            bh = np.ones(m.n)
-            t0 = time.perf_counter()
-            want = oracle.solve(m, bh)
-            serial = time.perf_counter() - t0
-            serial_total += serial
-            b = torch.ones(m.n, dtype=torch.float64, device="cuda")
-            x = torch.empty_like(b)
-            plans = {}
-            for f, (o, meth) in forms.items():
-                key = id(o)
-                if key not in plans:
-                    plans[key] = B.Plan(m, o)
-                plan = plans[key]
-                t = timed(lambda: getattr(plan, meth)(b, x), args.steps)
-                ok = plan.device_status() == 0 and oracle.same_bits(x.cpu().numpy(), want)
-                all_exact &= ok
-                logs[f].append(serial / t)
-                if f == "GL persistent":
-                    inf = plan.info()
-                    ratios.append(inf["wavefronts"] / inf["supersteps"])
-            kept.append((m, plans.pop(id(o_auto_a)), plans.pop(id(o_auto)), want))
-            for plan in plans.values():
-                plan.close()
-        # every instance of the set in one launch: throughput against the serial solves one after another
-        batched = {}
-        bs = [torch.ones(k[0].n, dtype=torch.float64, device="cuda") for k in kept]
-        xs = [torch.empty_like(v) for v in bs]
-        for label, idx, async_exec in (("AUTO async batch", 1, True), ("AUTO BSP batch", 2, False)):
-            with B.Batch([k[idx] for k in kept], per_claim=2, use_graph=False, async_exec=async_exec) as bt:
-                t = timed(lambda: bt.solve(bs, xs), args.steps)
-                ok = bt.status() == 0 and all(oracle.same_bits(x.cpu().numpy(), k[3]) for x, k in zip(xs, kept))
-            all_exact &= ok
-            batched[label] = serial_total / t
-        for k in kept:
-            k[1].close()
-            k[2].close()
-        row = {"set": f"{fam} p={p}" + (f" B={Bw:g}" if Bw else ""), "instances": args.instances,
-               "exact": bool(all_exact), "wavefronts_per_superstep_GL": float(np.mean(ratios)),
-               "geomean_speedup_vs_serial": {f: float(np.exp(np.mean(np.log(v)))) for f, v in logs.items()},
-               "batched_speedup_vs_serial_sum": batched}
-        log(json.dumps(row))
-        report.append(row)
-    print(json.dumps({"mode": "paper", "n": 100_000, "serial": "oracle, one host core, one solve",
-                      "sets": report}), flush=True)
-
-
-def auto_plan(m, async_exec: bool = False):
-    """AUTO schedule, predicted for the execution form that will run it."""
-    from paper_2503_05408_amd import binding as B
-    return B.Plan(m, B.gpu_opts(schedule_kind=B.SCHED_AUTO, exec_hint=1 if async_exec else 0))
-
-
-def bench_batch(args):
-    """64 independent systems (n = 10^U[3,6], ER/NB/2-D/3-D mix) in one
-    hipGraph-replayed persistent launch, against 64 sequential plain solves."""
-    import torch
-    import oracle
-    from paper_2503_05408_amd import binding as B
-    from paper_2503_05408_amd import gen
-
-    t = time.time()
-    ms = gen.batch_mix(args.systems)
-    log(f"batch: {len(ms)} systems, {sum(m.n for m in ms)} rows, generated in {time.time() - t:.1f} s")
-    t = time.time()
-    plans = [auto_plan(m) for m in ms]
-    plans_async = [auto_plan(m, async_exec=True) for m in ms]
-    log(f"plans in {time.time() - t:.1f} s; supersteps total {sum(p.info()['supersteps'] for p in plans)}, "
-        f"max {max(p.info()['supersteps'] for p in plans)}; async-predicted plans: max supersteps "
-        f"{max(p.info()['supersteps'] for p in plans_async)}")
-    stream = torch.cuda.Stream()
-    bd = [torch.ones(m.n, dtype=torch.float64, device="cuda") for m in ms]
-    xd = [torch.full((m.n,), float("nan"), dtype=torch.float64, device="cuda") for m in ms]
-    best = None
-    timings = {}
-    for async_exec, per_claim in [(False, 1), (False, 2), (False, 4), (True, 1), (True, 2), (True, 4)]:
-        # execution form and claim size picked by measurement
-        with torch.cuda.stream(stream):
-            bt = B.Batch(plans_async if async_exec else plans, per_claim=per_claim, use_graph=True,
-                         async_exec=async_exec)
-            for _ in range(max(1, args.warmup)):
-                bt.solve(bd, xd, stream)
-            stream.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(args.steps):
-                bt.solve(bd, xd, stream)
-            e1.record(stream)
-            stream.synchronize()
-            ms_b = e0.elapsed_time(e1) / args.steps
-            ok = bt.status() == 0
-        form = "async" if async_exec else "bsp"
-        log(f"{form} per_claim={per_claim}: {ms_b:.3f} ms status_ok={ok}")
-        timings[f"{form}_claim{per_claim}_ms"] = ms_b
-        if ok and (best is None or ms_b < best[1]):
-            if best is not None:
-                best[2].close()
-            best = (per_claim, ms_b, bt, form)
-        else:
-            bt.close()
-    per_claim, ms_b, bt, form = best
-    for x in xd:
-        x.fill_(float("nan"))
-    with torch.cuda.stream(stream):
-        bt.solve(bd, xd, stream)
-        stream.synchronize()
-    exact = bt.status() == 0 and all(oracle.same_bits(x.cpu().numpy(), oracle.solve(m, np.ones(m.n)))
-                                     for m, x in zip(ms, xd))
-
-    def seq(fn):
-        with torch.cuda.stream(stream):
-            for p, b, x in zip(plans, bd, xd):
-                fn(p)(b, x, stream)
-            stream.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            reps = max(1, args.plain_steps // 5)
-            for _ in range(reps):
-                for p, b, x in zip(plans, bd, xd):
-                    fn(p)(b, x, stream)
-            e1.record(stream)
-            stream.synchronize()
-        return e0.elapsed_time(e1) / reps
-
-    ms_plain = seq(lambda p: p.solve_plain)
-    ms_pers = seq(lambda p: p.solve)
-    rows = sum(m.n for m in ms)
-    alg = sum(algorithmic_bytes(m.n, m.nnz) for m in ms)
-    achieved = alg / (ms_b * 1e-3) / 1e9
-    out = {
-        "metric": "reduced elements/sec (exact) at 1 MI355X vs plain launch; p50/p99 latency",
-        "value": rows / (ms_b * 1e-3) if exact else 0.0, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{len(ms)} independent systems, n = floor(10^U[3,6]), ER/NB/2-D/3-D mix, "
-                               "one hipGraph-replayed persistent launch",
-                   "rows": rows, "nnz": sum(m.nnz for m in ms), "per_claim": per_claim, "form": form,
-                   "schedule": "auto (GrowLocal k=65536 L=50 alpha0=1, or wavefront)"},
-        "timings": timings,
-        "exact": bool(exact),
-        "plain_sequential_ms": ms_plain, "persistent_sequential_ms": ms_pers,
-        "speedup_vs_plain": ms_plain / ms_b,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "trsv_batched_async" if form == "async" else "trsv_batched",
-                     "alg_bytes_per_launch": alg},
-    }
-    bt.close()
-    print(json.dumps(out), flush=True)
 
 
 def bench_paper(args):

@@ -109,9 +109,13 @@ typedef struct gltrsv_plan_opts {
     double growth;          /* alpha growth factor, > 1                       */
     double accept;          /* worthy iff beta >= accept * best beta          */
     int32_t schedule_kind;  /* GLTRSV_SCHED_*                                 */
-    int32_t reorder;        /* reserved; the device layout is always in the
-                               schedule order of Sec. 5 and b/x stay in the
-                               original numbering (see gltrsv_solve)          */
+    int32_t reorder;        /* 1 (default): the device stream is in the
+                               schedule order of Sec. 5; b/x always stay in
+                               the original numbering (see gltrsv_solve).
+                               0: the plan also keeps A in the caller's CSR
+                               order for gltrsv_solve_unordered (the
+                               no-reorder comparison of Sec. 5 / Table 7.3);
+                               12 nnz + 12 n more device bytes                */
     int32_t block_size;     /* device threads per workgroup (64..1024, a
                                multiple of 64); 0 = library default           */
     int32_t grid_blocks;    /* workgroups of the persistent kernel;
@@ -257,6 +261,14 @@ int gltrsv_solve(gltrsv_plan *plan, const double *b, double *x, void *stream);
 /* Baseline: one kernel launch per superstep; the kernel boundary is the
  * barrier.  Same arguments and results as gltrsv_solve. */
 int gltrsv_solve_plain(gltrsv_plan *plan, const double *b, double *x, void *stream);
+
+/* The same schedule without the reorder of Sec. 5: A stays in the caller's
+ * CSR order on the device and each lane walks its task's rows through the
+ * row pointers, one launch per superstep (compare gltrsv_solve_plain, which
+ * reads the reordered, lane-interleaved stream).  Same arguments and the
+ * same bits as gltrsv_solve.  Needs a plan created with opts.reorder = 0
+ * (GLTRSV_ENOTSUP otherwise). */
+int gltrsv_solve_unordered(gltrsv_plan *plan, const double *b, double *x, void *stream);
 
 /* As gltrsv_plan_create, but with the schedule of an earlier analysis of
  * the same pattern (gltrsv_plan_schedule or gltrsv_schedule: core[n] and

@@ -111,6 +111,7 @@ SIGNATURES = {
     "gltrsv_solve_multi": ([P, P, P, i32, P], i32),
     "gltrsv_plan_set_spin_limit": ([P, i64], i32),
     "gltrsv_solve_auto": ([P, P, P, P], i32),
+    "gltrsv_solve_unordered": ([P, P, P, P], i32),
     "gltrsv_plan_set_exec": ([P, i32], i32),
     "gltrsv_plan_tune": ([P, P, P, i32, P, P, P], i32),
     "gltrsv_plan_stream": ([P, P, P, i64], i32),
@@ -346,6 +347,15 @@ class Plan:
             x = torch.empty_like(b)
         _check(load().gltrsv_solve(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
                "gltrsv_solve")
+        return x
+
+    def solve_unordered(self, b, x=None, stream=None):
+        """The schedule without the reorder of Sec. 5 (plan built with reorder=0)."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        _check(load().gltrsv_solve_unordered(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
+               "gltrsv_solve_unordered")
         return x
 
     def solve_auto(self, b, x=None, stream=None):

@@ -297,6 +297,48 @@ __global__ __launch_bounds__(kBlock) void trsv_superstep_plain(
     run_lane(cur, b0, b1, b, x, ring);
 }
 
+// The schedule executed without the reorder of Sec. 5 (the ablation of the
+// paper's locality study): the matrix stays in the caller's CSR order and
+// each lane walks the rows of its task through the row pointers.  One launch
+// per superstep; lane t of the launch runs task t0 + t (tasks of a superstep
+// longest first, as in the packed layout).  Per row the same operations in
+// the same order as every other form: acc = b_i, then acc - a_ij x_j over
+// the stored off-diagonals in stored order, then one division.  A row of
+// the same task read from x was stored earlier by this lane (same address,
+// program order); rows of other tasks come from earlier supersteps.
+__global__ __launch_bounds__(kBlock) void trsv_superstep_unordered(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ val,
+    const int32_t *__restrict__ rows, const int64_t *__restrict__ task_off, int32_t t0, int32_t t1, int32_t upper,
+    const double *b, double *x)
+{
+    const int32_t t = t0 + int32_t(blockIdx.x * kBlock + threadIdx.x);
+    if (t >= t1) return;
+    for (int64_t k = task_off[t]; k < task_off[t + 1]; k++) {
+        const int32_t r = rows[k];
+        const int64_t beg = row_ptr[r], end = row_ptr[r + 1];
+        const int64_t d = upper ? beg : end - 1;   // the diagonal: first (upper) or last (lower) entry
+        int64_t e = upper ? beg + 1 : beg;
+        const int64_t e_end = upper ? end : end - 1;
+        double acc = load_x(b + r);
+        // four entries at a time: their loads first, then the subtractions in order
+        for (; e + 4 <= e_end; e += 4) {
+            int32_t c[4];
+            double v[4], g[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                c[j] = col[e + j];
+                v[j] = val[e + j];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) g[j] = load_x(x + c[j]);
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc = acc - v[j] * g[j];
+        }
+        for (; e < e_end; e++) acc = acc - val[e] * load_x(x + col[e]);
+        store_x(x + r, acc / val[d]);
+    }
+}
+
 // Barrier over all workgroups of the grid, in two halves so that work that
 // does not depend on other workgroups can run while waiting.  Arrivals are
 // counted in two levels: workgroups of a group of kGroup count on the group's
@@ -1040,6 +1082,7 @@ int check_opts(const gltrsv_plan_opts *o)
     if (o->exec_hint != 0 && o->exec_hint != 1) return set_error(GLTRSV_EINVAL, "exec_hint must be 0 or 1");
     if (o->triangle != GLTRSV_LOWER && o->triangle != GLTRSV_UPPER)
         return set_error(GLTRSV_EINVAL, "triangle must be GLTRSV_LOWER or GLTRSV_UPPER");
+    if (o->reorder != 0 && o->reorder != 1) return set_error(GLTRSV_EINVAL, "reorder must be 0 or 1");
     return GLTRSV_OK;
 }
 
@@ -1059,12 +1102,63 @@ SchedParams params_of(const gltrsv_plan_opts *o)
 }
 
 template <class T>
+int upload_raw(T **dst, const T *src, size_t count, int64_t *bytes)
+{
+    const size_t nb = std::max<size_t>(1, count) * sizeof(T);
+    HIP_TRY(hipMalloc(reinterpret_cast<void **>(dst), nb));
+    if (count) HIP_TRY(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+    *bytes += int64_t(nb);
+    return GLTRSV_OK;
+}
+
+template <class T>
 int upload(T **dst, const std::vector<T> &src, int64_t *bytes)
 {
-    const size_t nb = std::max<size_t>(1, src.size()) * sizeof(T);
-    HIP_TRY(hipMalloc(reinterpret_cast<void **>(dst), nb));
-    if (!src.empty()) HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
-    *bytes += int64_t(nb);
+    return upload_raw(dst, src.data(), src.size(), bytes);
+}
+
+// For plans kept in the caller's order too (opts.reorder = 0): the CSR as
+// given, and the rows of every task, tasks of a superstep longest first.
+int upload_unordered(gltrsv_plan *p, const gltrsv_csr *A, int64_t *bytes)
+{
+    const int64_t n = p->n;
+    std::vector<int32_t> rows(static_cast<size_t>(n));
+    std::vector<int64_t> off;
+    std::vector<int32_t> super_task(size_t(p->S) + 1, 0);
+    off.reserve(size_t(p->tasks) + 1);
+    off.push_back(0);
+    int64_t pos = 0;
+    for (int32_t s = 0; s < p->S; s++) {
+        // tasks of superstep s: runs of equal core in the order of Sec. 5
+        std::vector<std::pair<int64_t, int64_t>> tasks;   // (first position, length)
+        while (pos < n && p->superstep[size_t(p->perm[size_t(pos)])] == s) {
+            const int32_t c = p->core[size_t(p->perm[size_t(pos)])];
+            int64_t q = pos;
+            while (q < n && p->superstep[size_t(p->perm[size_t(q)])] == s && p->core[size_t(p->perm[size_t(q)])] == c)
+                q++;
+            tasks.emplace_back(pos, q - pos);
+            pos = q;
+        }
+        std::stable_sort(tasks.begin(), tasks.end(),
+                         [](const std::pair<int64_t, int64_t> &a, const std::pair<int64_t, int64_t> &b) {
+                             return a.second > b.second;
+                         });
+        for (const auto &tk : tasks) {
+            for (int64_t q = 0; q < tk.second; q++) {
+                const int32_t v = p->perm[size_t(tk.first + q)];
+                rows[size_t(off.back() + q)] = p->upper ? int32_t(n - 1 - v) : v;   // original row
+            }
+            off.push_back(off.back() + tk.second);
+        }
+        super_task[size_t(s) + 1] = int32_t(off.size() - 1);
+    }
+    p->super_task_host = super_task;
+    int rc;
+    if ((rc = upload_raw(&p->d_csr_rp, A->row_ptr, size_t(n) + 1, bytes)) ||
+        (rc = upload_raw(&p->d_csr_col, A->col, size_t(A->nnz), bytes)) ||
+        (rc = upload_raw(&p->d_csr_val, A->val, size_t(A->nnz), bytes)) || (rc = upload(&p->d_urows, rows, bytes)) ||
+        (rc = upload(&p->d_utask_off, off, bytes)))
+        return rc;
     return GLTRSV_OK;
 }
 
@@ -1232,6 +1326,11 @@ int gltrsv_plan_destroy(gltrsv_plan *p)
     (void)hipFree(p->d_err);
     (void)hipFree(p->d_trace);
     (void)hipFree(p->d_bcopy);
+    (void)hipFree(p->d_csr_rp);
+    (void)hipFree(p->d_csr_col);
+    (void)hipFree(p->d_csr_val);
+    (void)hipFree(p->d_urows);
+    (void)hipFree(p->d_utask_off);
     delete p;
     return GLTRSV_OK;
 }
@@ -1351,6 +1450,10 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
             gltrsv_plan_destroy(p);
             return rc;
         }
+    }
+    if (opts->reorder == 0 && (rc = upload_unordered(p, A, &bytes))) {
+        gltrsv_plan_destroy(p);
+        return rc;
     }
     p->device_bytes = bytes;
 
@@ -1634,6 +1737,23 @@ int gltrsv_plan_set_spin_limit(gltrsv_plan *p, int64_t polls)
 {
     if (!p || polls < 1) return set_error(GLTRSV_EINVAL, "polls must be >= 1");
     p->spin_limit = polls;
+    return GLTRSV_OK;
+}
+
+int gltrsv_solve_unordered(gltrsv_plan *p, const double *b, double *x, void *stream)
+{
+    if (!p || (p->n && (!b || !x))) return set_error(GLTRSV_EINVAL, "null argument");
+    if (p->n && !p->d_csr_rp) return set_error(GLTRSV_ENOTSUP, "plan was created with reorder = 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int32_t s = 0; s < p->S; s++) {
+        const int32_t t0 = p->super_task_host[size_t(s)], t1 = p->super_task_host[size_t(s) + 1];
+        const int32_t blocks = (t1 - t0 + dev::kBlock - 1) / dev::kBlock;
+        if (blocks == 0) continue;
+        hipLaunchKernelGGL(dev::trsv_superstep_unordered, dim3(blocks), dim3(dev::kBlock), 0, st, p->d_csr_rp,
+                           p->d_csr_col, p->d_csr_val, p->d_urows, p->d_utask_off, t0, t1, p->upper ? 1 : 0, b, x);
+    }
+    HIP_TRY(hipGetLastError());
+    p->last_stream = st;
     return GLTRSV_OK;
 }
 

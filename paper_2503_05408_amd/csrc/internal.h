@@ -138,6 +138,13 @@ struct gltrsv_plan {
     double *d_bcopy = nullptr;      // b when a semi-asynchronous solve runs in place
     int cooperative = 0;
     int32_t exec_form = 0;          // preferred form of gltrsv_solve_auto (GLTRSV_EXEC_*)
+    // opts.reorder = 0: the matrix in the caller's order as well, for gltrsv_solve_unordered
+    int64_t *d_csr_rp = nullptr;
+    int32_t *d_csr_col = nullptr;
+    double *d_csr_val = nullptr;
+    int32_t *d_urows = nullptr;         // original rows of every task, task after task
+    int64_t *d_utask_off = nullptr;     // [tasks + 1] offsets into d_urows
+    std::vector<int32_t> super_task_host;   // [S + 1] task range of each superstep
 };
 
 inline int64_t widest_of(const std::vector<gltrsv_plan *> &plans)
