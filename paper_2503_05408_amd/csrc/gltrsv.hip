@@ -79,29 +79,21 @@ struct Batch {
 // store has completed.  The barrier therefore needs no L2 write-back or
 // invalidation: an arrival waits for the workgroup's stores to complete, and
 // the gathers of the next superstep are issued after the new generation has
-// been observed.  Building with GLTRSV_FENCED uses plain accesses and
-// agent-scope release/acquire fences around the barrier instead (slower:
-// each fence writes back or invalidates the XCD's whole L2).
+// been observed.  (Plain accesses with agent-scope release/acquire fences
+// at the barrier are slower: each fence writes back or invalidates the XCD's
+// whole L2, and plain random gathers are no faster than coherent ones.)
 __device__ __forceinline__ double load_x(const double *p)
 {
-#ifndef GLTRSV_FENCED
     const unsigned long long u =
         __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return __longlong_as_double(static_cast<long long>(u));
-#else
-    return *p;
-#endif
 }
 
 __device__ __forceinline__ void store_x(double *p, double v)
 {
-#ifndef GLTRSV_FENCED
     __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
                        static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-#else
-    *p = v;
-#endif
 }
 
 struct LaneCursor {
@@ -358,17 +350,9 @@ struct BarrierTicket {
     bool last;
 };
 
-#ifndef GLTRSV_FENCED
-#define GLTRSV_ARRIVE_ORDER __ATOMIC_RELAXED
-#define GLTRSV_NO_FENCES 1
-#else
-#define GLTRSV_ARRIVE_ORDER __ATOMIC_RELEASE
-#endif
-
 __device__ __forceinline__ BarrierTicket barrier_arrive(uint32_t *bar)
 {
-    // Every wave waits until its own stores have completed (with fences:
-    // reached L2, which thread 0's agent-scope release then writes back).
+    // Every wave waits until its own (coherent) stores have completed.
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
@@ -384,19 +368,13 @@ __device__ __forceinline__ BarrierTicket barrier_arrive(uint32_t *bar)
         uint32_t *cnt = bar + kBarGroups + 32 * grp;
         const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         bool last = false;
-        const uint32_t old = __hip_atomic_fetch_add(cnt, 1u, GLTRSV_ARRIVE_ORDER, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == gsize - 1) {
-#ifndef GLTRSV_NO_FENCES
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-#endif
             __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t old2 = __hip_atomic_fetch_add(top, 1u, GLTRSV_ARRIVE_ORDER, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t old2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (old2 == groups - 1) {
-#ifndef GLTRSV_NO_FENCES
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-#endif
                 __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(gen, 1u, GLTRSV_ARRIVE_ORDER, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 last = true;
             }
         }
@@ -433,9 +411,6 @@ __device__ __forceinline__ bool barrier_wait(uint32_t *bar, BarrierTicket t, int
                 }
             }
         }
-#ifndef GLTRSV_NO_FENCES
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-#endif
         ok = good;
     }
     __syncthreads();

@@ -110,3 +110,28 @@ def test_async_batch_mix_small():
             assert oracle.same_bits(xd[i].cpu().numpy(), oracle.solve(m, bs[i])), (m.name, per_claim)
     for p in ps:
         p.close()
+
+
+@pytest.mark.parametrize("async_exec", [False, True])
+def test_shuffled_system_order_and_grid_sizes(plans, async_exec):
+    # the systems listed in random orders (so waves start their scans at
+    # different systems and claim chunks in different interleavings) on grids
+    # of 1, 3 and 17 workgroups and the default: every x is the same bits
+    import torch
+    ms, ps = plans
+    bs = [gen.rhs_uniform(m.n, 7 + i) for i, m in enumerate(ms)]
+    wants = [oracle.solve(m, b) for m, b in zip(ms, bs)]
+    bd = [torch.from_numpy(b).cuda() for b in bs]
+    rng = np.random.default_rng(11)
+    for trial, grid in enumerate((1, 3, 17, 0)):
+        order = rng.permutation(len(ms))
+        xd = [torch.full((ms[i].n,), float("nan"), dtype=torch.float64, device="cuda") for i in order]
+        with B.Batch([ps[i] for i in order], per_claim=1 + trial % 2, grid_blocks=grid,
+                     async_exec=async_exec) as bt:
+            if grid:
+                assert bt.info()["grid_blocks"] <= grid
+            bt.solve([bd[i] for i in order], xd)
+            torch.cuda.synchronize()
+            assert bt.status() == 0
+        for j, i in enumerate(order):
+            assert oracle.same_bits(xd[j].cpu().numpy(), wants[i]), (grid, ms[i].name)
