@@ -487,9 +487,11 @@ def bench_paper(args):
     o_gl, o_wf, o_auto = B.gpu_opts(), B.default_opts(schedule_kind=B.SCHED_WAVEFRONT), \
         B.gpu_opts(schedule_kind=B.SCHED_AUTO)
     o_auto_a = B.gpu_opts(schedule_kind=B.SCHED_AUTO, exec_hint=1)
+    o_wave = B.default_opts(schedule_kind=B.SCHED_WAVEFRONT, core_width=64)
     forms = {"GL persistent": (o_gl, "solve"), "GL async": (o_gl, "solve_async"),
              "wavefront persistent": (o_wf, "solve"), "wavefront async": (o_wf, "solve_async"),
-             "AUTO persistent": (o_auto, "solve"), "AUTO async": (o_auto_a, "solve_async")}
+             "AUTO persistent": (o_auto, "solve"), "AUTO async": (o_auto_a, "solve_async"),
+             "wavefront wave-core persistent": (o_wave, "solve")}
     report = []
     for fam, p, Bw in sets:
         logs = {f: [] for f in forms}

@@ -56,7 +56,7 @@ class PlanOpts(ctypes.Structure):
                 ("schedule_kind", i32), ("reorder", i32), ("block_size", i32), ("grid_blocks", i32),
                 ("cooperative", i32), ("analysis_threads", i32), ("pack", i32),
                 ("blocks", i32), ("triangle", i32), ("funnel_max_weight", i32),
-                ("exec_hint", i32)]
+                ("exec_hint", i32), ("core_width", i32)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -81,7 +81,7 @@ class PlanInfo(ctypes.Structure):
                 ("chunks", i64), ("stream_slots", i64), ("device_bytes", i64), ("analysis_ns", i64),
                 ("pattern_key", u64), ("grid_blocks", i32), ("block_size", i32), ("max_task_rows", i64),
                 ("schedule_kind", i32), ("predicted_us", dbl), ("device_packed", i32),
-                ("async_grid_blocks", i32), ("exec_form", i32)]
+                ("async_grid_blocks", i32), ("exec_form", i32), ("core_width", i32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -472,6 +472,99 @@ __global__ __launch_bounds__(kBlock) void trsv_persistent(
 }
 
 // ---------------------------------------------------------------------------
+// Wavefront cores (opts.core_width = 64): a BSP core is a whole wavefront.
+// The task's rows run one after another; for each row the 64 lanes load 64
+// of its off-diagonals at once, gather x and form the products, and the wave
+// subtracts them from acc = b_i in stored order (one lane's product at a
+// time, broadcast with readlane), so every row sees exactly the operations
+// of the one-lane form.  The next 64 entries are loaded and gathered while
+// the current ones are subtracted.  Columns among the task's last kWaveRing
+// rows are marked in the layout and read from a per-wave LDS ring; older
+// rows of the task were stored before the wave's last full memory wait,
+// which it takes every kWaveRing rows.
+// ---------------------------------------------------------------------------
+constexpr int kWaveRing = 64;
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u)), l));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u >> 32)), l));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// value of entry e (if e < e1) of the current row: a column from memory or
+// from the ring; the product is formed by the caller
+__device__ __forceinline__ void wave_load(const uint32_t *__restrict__ wcol, const double *__restrict__ wval,
+                                          int64_t e, int64_t e1, const double *x, const double *ring, int32_t q,
+                                          double &v, double &g)
+{
+    v = 0.0;
+    g = 0.0;
+    if (e < e1) {
+        const uint32_t c = wcol[e];
+        v = wval[e];
+        g = (c & INTL) ? ring[(q - int32_t(c & MASK)) & (kWaveRing - 1)] : load_x(x + c);
+    }
+}
+
+__device__ __forceinline__ void wave_task(const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr,
+                                          const double *__restrict__ wdiag, const uint32_t *__restrict__ wcol,
+                                          const double *__restrict__ wval, int64_t t0, int64_t t1, const double *b,
+                                          double *x, double *ring)
+{
+    const int lane = threadIdx.x & 63;
+    for (int64_t t = t0; t < t1; t++) {
+        const int32_t q = int32_t(t - t0);   // row index within the task
+        if (q > 0 && (q & (kWaveRing - 1)) == 0) __builtin_amdgcn_s_waitcnt(0);   // older rows are in memory
+        const int32_t row = wrow[t];
+        double acc = load_x(b + row);
+        const int64_t e0 = wptr[t], e1 = wptr[t + 1];
+        double v, g;
+        wave_load(wcol, wval, e0 + lane, e1, x, ring, q, v, g);
+        for (int64_t base = e0; base < e1; base += 64) {
+            double vn, gn;
+            wave_load(wcol, wval, base + 64 + lane, e1, x, ring, q, vn, gn);
+            const double p = v * g;
+            const int cnt = int(min<int64_t>(64, e1 - base));
+            for (int l = 0; l < cnt; l++) acc = acc - readlane_f64(p, l);
+            v = vn;
+            g = gn;
+        }
+        const double y = acc / wdiag[t];
+        if (lane == 0) {
+            ring[q & (kWaveRing - 1)] = y;
+            store_x(x + row, y);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Supersteps [s0, s1) of a wave-core plan.  With s1 - s0 > 1 the grid is
+// co-resident and the device-scope barrier separates the supersteps; a
+// single superstep per launch needs none.  The i-th wave of workgroup g is
+// slot i G + g (tasks of a superstep sorted longest first).
+__global__ __launch_bounds__(kBlock) void trsv_wave(
+    const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr, const double *__restrict__ wdiag,
+    const uint32_t *__restrict__ wcol, const double *__restrict__ wval, const int64_t *__restrict__ wtask,
+    const int32_t *__restrict__ wsuper, int32_t s0, int32_t s1, const double *b, double *x, uint32_t *bar,
+    int32_t *err, int64_t spin_limit)
+{
+    __shared__ double ring[kWavesPerBlock][kWaveRing];
+    const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
+    const int32_t slot = int32_t(threadIdx.x >> 6) * int32_t(gridDim.x) + int32_t(blockIdx.x);
+    double *my_ring = ring[threadIdx.x >> 6];
+    for (int32_t s = s0; s < s1; s++) {
+        for (int32_t t = wsuper[s] + slot; t < wsuper[s + 1]; t += waves)
+            wave_task(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring);
+        if (s + 1 < s1) {
+            const BarrierTicket tk = barrier_arrive(bar);
+            if (!barrier_wait(bar, tk, err, spin_limit)) return;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Semi-asynchronous solve: no barriers.  Wave w runs chunks w, w + W, w + 2W,
 // ... in order (chunks are numbered superstep by superstep), and a lane waits
 // only for the columns it reads (await_batch).  Progress: the earliest
@@ -1058,6 +1151,8 @@ int check_opts(const gltrsv_plan_opts *o)
     if (o->triangle != GLTRSV_LOWER && o->triangle != GLTRSV_UPPER)
         return set_error(GLTRSV_EINVAL, "triangle must be GLTRSV_LOWER or GLTRSV_UPPER");
     if (o->reorder != 0 && o->reorder != 1) return set_error(GLTRSV_EINVAL, "reorder must be 0 or 1");
+    if (o->core_width != 0 && o->core_width != 1 && o->core_width != 64)
+        return set_error(GLTRSV_EINVAL, "core_width must be 1 or 64");
     return GLTRSV_OK;
 }
 
@@ -1090,6 +1185,82 @@ template <class T>
 int upload(T **dst, const std::vector<T> &src, int64_t *bytes)
 {
     return upload_raw(dst, src.data(), src.size(), bytes);
+}
+
+// Wave-core layout (opts.core_width = 64): positions in the order of Sec. 5,
+// tasks of a superstep longest first; per position the original row, its
+// off-diagonals in stored order (a column among the task's last kWaveRing
+// rows as kIntBit | rows back) and its diagonal.
+int upload_wave(gltrsv_plan *p, const gltrsv_csr *A, int64_t *bytes)
+{
+    const int64_t n = p->n;
+    const bool up = p->upper;
+    std::vector<std::pair<int64_t, int64_t>> tasks;   // (first position in perm, length)
+    std::vector<int32_t> wsuper(size_t(p->S) + 1, 0);
+    int64_t pos = 0;
+    for (int32_t s = 0; s < p->S; s++) {
+        const size_t first = tasks.size();
+        while (pos < n && p->superstep[size_t(p->perm[size_t(pos)])] == s) {
+            const int32_t c = p->core[size_t(p->perm[size_t(pos)])];
+            int64_t q = pos;
+            while (q < n && p->superstep[size_t(p->perm[size_t(q)])] == s && p->core[size_t(p->perm[size_t(q)])] == c)
+                q++;
+            tasks.emplace_back(pos, q - pos);
+            pos = q;
+        }
+        std::stable_sort(tasks.begin() + std::ptrdiff_t(first), tasks.end(),
+                         [](const std::pair<int64_t, int64_t> &a, const std::pair<int64_t, int64_t> &b) {
+                             return a.second > b.second;
+                         });
+        wsuper[size_t(s) + 1] = int32_t(tasks.size());
+    }
+    // new position of every row, and the task of every new position
+    const size_t un = static_cast<size_t>(n);
+    std::vector<int32_t> wrow(un), task_of(un);
+    std::vector<int64_t> wtask(tasks.size() + 1, 0), newpos(un);
+    int64_t np = 0;
+    for (size_t t = 0; t < tasks.size(); t++) {
+        wtask[t] = np;
+        for (int64_t q = 0; q < tasks[t].second; q++, np++) {
+            const int32_t v = p->perm[size_t(tasks[t].first + q)];
+            const int32_t row = up ? int32_t(n - 1 - v) : v;
+            wrow[size_t(np)] = row;
+            task_of[size_t(np)] = int32_t(t);
+            newpos[size_t(row)] = np;
+        }
+    }
+    wtask[tasks.size()] = np;
+    const int64_t noff = A->nnz - n;
+    std::vector<int64_t> wptr(size_t(n) + 1, 0);
+    const size_t uoff = static_cast<size_t>(std::max<int64_t>(noff, 0));
+    std::vector<double> wdiag(un);
+    std::vector<uint32_t> wcol(uoff);
+    std::vector<double> wval(uoff);
+    int64_t e = 0;
+    for (int64_t t = 0; t < n; t++) {
+        const int32_t row = wrow[size_t(t)];
+        const int64_t beg = A->row_ptr[row], end = A->row_ptr[row + 1];
+        const int64_t d = up ? beg : end - 1;
+        wdiag[size_t(t)] = A->val[d];
+        wptr[size_t(t)] = e;
+        for (int64_t k = up ? beg + 1 : beg; k < (up ? end : end - 1); k++, e++) {
+            const int32_t c = A->col[k];
+            const int64_t pc = newpos[size_t(c)];
+            const int64_t back = t - pc;
+            const bool same = task_of[size_t(pc)] == task_of[size_t(t)] && back > 0 && back < dev::kWaveRing;
+            wcol[size_t(e)] = same ? (kIntBit | uint32_t(back)) : uint32_t(c);
+            wval[size_t(e)] = A->val[k];
+        }
+    }
+    wptr[size_t(n)] = e;
+    p->wsuper_host = wsuper;
+    int rc;
+    if ((rc = upload(&p->d_wrow, wrow, bytes)) || (rc = upload(&p->d_wptr, wptr, bytes)) ||
+        (rc = upload(&p->d_wdiag, wdiag, bytes)) || (rc = upload(&p->d_wcol, wcol, bytes)) ||
+        (rc = upload(&p->d_wval, wval, bytes)) || (rc = upload(&p->d_wtask, wtask, bytes)) ||
+        (rc = upload(&p->d_wsuper, wsuper, bytes)))
+        return rc;
+    return GLTRSV_OK;
 }
 
 // For plans kept in the caller's order too (opts.reorder = 0): the CSR as
@@ -1306,6 +1477,13 @@ int gltrsv_plan_destroy(gltrsv_plan *p)
     (void)hipFree(p->d_csr_val);
     (void)hipFree(p->d_urows);
     (void)hipFree(p->d_utask_off);
+    (void)hipFree(p->d_wrow);
+    (void)hipFree(p->d_wptr);
+    (void)hipFree(p->d_wdiag);
+    (void)hipFree(p->d_wcol);
+    (void)hipFree(p->d_wval);
+    (void)hipFree(p->d_wtask);
+    (void)hipFree(p->d_wsuper);
     delete p;
     return GLTRSV_OK;
 }
@@ -1430,6 +1608,11 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         gltrsv_plan_destroy(p);
         return rc;
     }
+    p->core_width = opts->core_width == 64 ? 64 : 1;
+    if (p->core_width == 64 && (rc = upload_wave(p, A, &bytes))) {
+        gltrsv_plan_destroy(p);
+        return rc;
+    }
     p->device_bytes = bytes;
 
     // persistent grid: every workgroup must be co-resident (cooperative launch)
@@ -1468,6 +1651,22 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         p->grid_async = int(std::max<int64_t>(
             1, std::min<int64_t>(ga, (p->chunks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
     }
+    if (p->core_width == 64) {
+        // wave cores: co-resident for the barrier, no more workgroups than
+        // the superstep with the most tasks can use
+        int per_cu_w = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_w, dev::trsv_wave, dev::kBlock, 0);
+        if (e != hipSuccess) {
+            gltrsv_plan_destroy(p);
+            return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
+        }
+        int64_t most = 1;
+        for (int32_t q = 0; q < p->S; q++)
+            most = std::max<int64_t>(most, p->wsuper_host[size_t(q) + 1] - p->wsuper_host[size_t(q)]);
+        int64_t gw = std::min<int64_t>(int64_t(per_cu_w) * cus, dev::kGroup * 128);
+        if (opts->grid_blocks > 0) gw = std::min<int64_t>(gw, opts->grid_blocks);
+        p->grid_wave = int(std::max<int64_t>(1, std::min<int64_t>(gw, (most + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
+    }
 #ifdef GLTRSV_TRACE
     {
         std::vector<int64_t> tr(size_t(p->S) * grid * 3, 0);
@@ -1505,6 +1704,7 @@ int gltrsv_plan_info_get(const gltrsv_plan *p, gltrsv_plan_info *o)
     o->device_packed = p->device_packed ? 1 : 0;
     o->async_grid_blocks = p->grid_async;
     o->exec_form = p->exec_form;
+    o->core_width = p->core_width;
     return GLTRSV_OK;
 }
 
@@ -1532,6 +1732,19 @@ int gltrsv_solve_plain(gltrsv_plan *p, const double *b, double *x, void *stream)
 {
     if (!p || (p->n && (!b || !x))) return set_error(GLTRSV_EINVAL, "null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->core_width == 64) {
+        for (int32_t s = 0; s < p->S; s++) {
+            const int32_t tasks = p->wsuper_host[size_t(s) + 1] - p->wsuper_host[size_t(s)];
+            const int32_t blocks = (tasks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
+            if (blocks == 0) continue;
+            hipLaunchKernelGGL(dev::trsv_wave, dim3(blocks), dim3(dev::kBlock), 0, st, p->d_wrow, p->d_wptr,
+                               p->d_wdiag, p->d_wcol, p->d_wval, p->d_wtask, p->d_wsuper, s, s + 1, b, x,
+                               p->d_bar, p->d_err, p->spin_limit);
+        }
+        HIP_TRY(hipGetLastError());
+        p->last_stream = st;
+        return GLTRSV_OK;
+    }
     for (int32_t s = 0; s < p->S; s++) {
         const int32_t c0 = p->super_chunk_host[s], c1 = p->super_chunk_host[s + 1];
         const int32_t waves = c1 - c0;
@@ -1549,6 +1762,15 @@ int gltrsv_solve(gltrsv_plan *p, const double *b, double *x, void *stream)
     if (!p || (p->n && (!b || !x))) return set_error(GLTRSV_EINVAL, "null argument");
     if (p->n == 0) return GLTRSV_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->core_width == 64) {
+        // all supersteps in one launch; the grid fits the co-resident capacity
+        hipLaunchKernelGGL(dev::trsv_wave, dim3(p->grid_wave), dim3(dev::kBlock), 0, st, p->d_wrow, p->d_wptr,
+                           p->d_wdiag, p->d_wcol, p->d_wval, p->d_wtask, p->d_wsuper, 0, p->S, b, x, p->d_bar,
+                           p->d_err, p->spin_limit);
+        HIP_TRY(hipGetLastError());
+        p->last_stream = st;
+        return GLTRSV_OK;
+    }
     const uint32_t *w = p->d_word;
     const double *v = p->d_value;
     const int64_t *cb = p->d_chunk_base;

@@ -145,6 +145,17 @@ struct gltrsv_plan {
     int32_t *d_urows = nullptr;         // original rows of every task, task after task
     int64_t *d_utask_off = nullptr;     // [tasks + 1] offsets into d_urows
     std::vector<int32_t> super_task_host;   // [S + 1] task range of each superstep
+    // opts.core_width = 64: a core is a wavefront (see trsv_wave)
+    int32_t core_width = 1;
+    int32_t *d_wrow = nullptr;          // [n] original row at each position of the wave layout
+    int64_t *d_wptr = nullptr;          // [n + 1] off-diagonal entries of each position
+    double *d_wdiag = nullptr;          // [n]
+    uint32_t *d_wcol = nullptr;         // [nnz - n] column, or kIntBit | rows back within the task
+    double *d_wval = nullptr;           // [nnz - n]
+    int64_t *d_wtask = nullptr;         // [wave tasks + 1] first position of each task
+    int32_t *d_wsuper = nullptr;        // [S + 1] task range of each superstep
+    std::vector<int32_t> wsuper_host;   // [S + 1] task range of each superstep
+    int grid_wave = 0;                  // workgroups of the persistent wave kernel
 };
 
 inline int64_t widest_of(const std::vector<gltrsv_plan *> &plans)

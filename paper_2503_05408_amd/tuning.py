@@ -84,46 +84,52 @@ def matrix_key(m, opts) -> str:
     return f"{h.hexdigest()}/{tri}/{sig}/{dev.name}/{getattr(dev, 'gcnArchName', '')}"
 
 
-def best_plan(m, opts=None, path: str | None = None, reps: int = 5):
+def best_plan(m, opts=None, path: str | None = None, reps: int = 5, core_widths=(1,)):
     """A plan for m with the measured-fastest schedule (GrowLocal or
-    wavefront) and execution form (persistent, plain, semi-asynchronous) for
+    wavefront), core width (`core_widths`: 1 = a core is a lane, 64 = a core
+    is a wavefront, which applies to the persistent and plain forms) and
+    execution form (persistent, plain, semi-asynchronous) for
     gltrsv_solve_auto.  With `path`, the choice is read from / stored in the
-    JSON table there, so a later process builds only the chosen schedule.
-    Returns (plan, entry) with entry = {"schedule", "form", "us"}."""
+    JSON table there, so a later process builds only the chosen plan.
+    Returns (plan, entry) with entry = {"schedule", "core_width", "form",
+    "us"}."""
     import ctypes
     base = opts if opts is not None else B.gpu_opts()
 
-    def with_kind(kind):
+    def variant(kind, width):
         o = B.PlanOpts()
         ctypes.memmove(ctypes.byref(o), ctypes.byref(base), ctypes.sizeof(o))
         o.schedule_kind = kind
+        o.core_width = width
         return o
 
     names = {v: k for k, v in SCHEDULES.items()}
     forms = {v: k for k, v in B.EXEC_NAMES.items()}
-    key = matrix_key(m, base) if path else None
+    key = f"{matrix_key(m, base)}/w{'-'.join(str(w) for w in core_widths)}" if path else None
     if path:
         hit = load_table(path).get(key)
         if isinstance(hit, dict) and hit.get("schedule") in names and hit.get("form") in forms:
-            plan = B.Plan(m, with_kind(names[hit["schedule"]]))
+            plan = B.Plan(m, variant(names[hit["schedule"]], int(hit.get("core_width", 1))))
             plan.set_exec(forms[hit["form"]])
             return plan, hit
     best, best_us, times = None, None, {}
-    for kind, sname in SCHEDULES.items():
-        plan = B.Plan(m, with_kind(kind))
-        res = plan.tune(reps=reps)
-        for f, us in res["us"].items():
-            times[f"{sname}/{f}"] = us
-        us = res["us"][res["form"]]
-        if best_us is None or us < best_us:
-            if best is not None:
-                best[0].close()
-            best, best_us = (plan, sname, res["form"]), us
-        else:
-            plan.close()
-    plan, sname, form = best
+    for width in core_widths:
+        for kind, sname in SCHEDULES.items():
+            plan = B.Plan(m, variant(kind, width))
+            res = plan.tune(reps=reps)
+            usable = {f: us for f, us in res["us"].items() if width == 1 or f != "async"}
+            for f, us in usable.items():
+                times[f"{sname}/w{width}/{f}"] = us
+            form = min(usable, key=usable.get)
+            if best_us is None or usable[form] < best_us:
+                if best is not None:
+                    best[0].close()
+                best, best_us = (plan, sname, width, form), usable[form]
+            else:
+                plan.close()
+    plan, sname, width, form = best
     plan.set_exec(forms[form])
-    entry = {"schedule": sname, "form": form, "us": times}
+    entry = {"schedule": sname, "core_width": width, "form": form, "us": times}
     if path:
         table = load_table(path)
         table[key] = entry

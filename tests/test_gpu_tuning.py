@@ -135,9 +135,9 @@ def test_best_plan_over_schedules_and_forms(tmp_path):
     plan, entry = tuning.best_plan(m, B.gpu_opts(), path, reps=3)
     print(entry, flush=True)
     with plan:
-        assert len(entry["us"]) == 6
+        assert len(entry["us"]) == 6 and entry["core_width"] == 1
         fastest = min(entry["us"], key=entry["us"].get)
-        assert fastest == f"{entry['schedule']}/{entry['form']}"
+        assert fastest == f"{entry['schedule']}/w1/{entry['form']}"
         kind = {"growlocal": B.SCHED_GROWLOCAL, "wavefront": B.SCHED_WAVEFRONT}[entry["schedule"]]
         assert plan.info()["schedule_kind"] == kind
         assert B.EXEC_NAMES[plan.info()["exec_form"]] == entry["form"]
@@ -158,4 +158,20 @@ def test_best_plan_over_schedules_and_forms(tmp_path):
         torch.cuda.synchronize()
         assert oracle.same_bits(x.cpu().numpy(), want)
     # other schedule parameters are another entry
-    assert tuning.matrix_key(m, B.gpu_opts(L=20.0)) != key
+    assert not key.startswith(tuning.matrix_key(m, B.gpu_opts(L=20.0)))
+
+
+def test_best_plan_with_wave_cores(tmp_path):
+    import torch
+    m = gen.erdos_renyi(4000, 0.03, gen.SEED_BASE + 46)    # rows of ~60 entries
+    want = oracle.solve(m, np.ones(m.n))
+    plan, entry = tuning.best_plan(m, B.gpu_opts(k=1024), str(tmp_path / "w.json"), reps=2, core_widths=(1, 64))
+    print(entry, flush=True)
+    with plan:
+        assert len(entry["us"]) == 10               # 2 schedules x (3 lane forms + 2 wave forms)
+        fastest = min(entry["us"], key=entry["us"].get)
+        assert fastest == f"{entry['schedule']}/w{entry['core_width']}/{entry['form']}"
+        assert plan.info()["core_width"] == entry["core_width"]
+        x = plan.solve_auto(torch.ones(m.n, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        assert oracle.same_bits(x.cpu().numpy(), want)
