@@ -491,7 +491,8 @@ def bench_paper(args):
     forms = {"GL persistent": (o_gl, "solve"), "GL async": (o_gl, "solve_async"),
              "wavefront persistent": (o_wf, "solve"), "wavefront async": (o_wf, "solve_async"),
              "AUTO persistent": (o_auto, "solve"), "AUTO async": (o_auto_a, "solve_async"),
-             "wavefront wave-core persistent": (o_wave, "solve")}
+             "wavefront wave-core persistent": (o_wave, "solve"),
+             "wavefront wave-core async": (o_wave, "solve_async")}
     report = []
     for fam, p, Bw in sets:
         logs = {f: [] for f in forms}

@@ -176,16 +176,17 @@ typedef struct gltrsv_plan_opts {
                                one after another at 0.18 us per entry, a
                                parent in another task adding 1.5 us -- and
                                all entries at 4e4 entries/us, plus 10 us)    */
-    int32_t core_width;       /* lanes per BSP core in gltrsv_solve and
-                               gltrsv_solve_plain: 1 (0 = default) = a core
-                               is one lane of a wavefront; 64 = a core is a
-                               whole wavefront: the lanes gather and multiply
-                               64 entries of a row at once and the wave
-                               subtracts the products in stored order (the
-                               same bits), for rows of many entries.  k then
-                               counts wavefronts (the device holds 1,024 at
-                               one per SIMD).  The other solve forms keep
-                               one lane per core.                           */
+    int32_t core_width;       /* lanes per BSP core in gltrsv_solve,
+                               gltrsv_solve_plain and gltrsv_solve_async:
+                               1 (0 = default) = a core is one lane of a
+                               wavefront; 64 = a core is a whole wavefront:
+                               the lanes gather and multiply 64 entries of a
+                               row at once and the wave subtracts the
+                               products in stored order (the same bits), for
+                               rows of many entries.  k then counts
+                               wavefronts (the device holds 1,024 at one per
+                               SIMD).  Several right-hand sides, batches and
+                               the server keep one lane per core.           */
 } gltrsv_plan_opts;
 
 /* Fills the paper's parameters: k = 22 (the core count of the main

@@ -494,24 +494,49 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
 }
 
 // value of entry e (if e < e1) of the current row: a column from memory or
-// from the ring; the product is formed by the caller
+// from the ring; the product is formed by the caller.  c receives the word
+// (kPadWord past the row's end).
 __device__ __forceinline__ void wave_load(const uint32_t *__restrict__ wcol, const double *__restrict__ wval,
                                           int64_t e, int64_t e1, const double *x, const double *ring, int32_t q,
-                                          double &v, double &g)
+                                          double &v, double &g, uint32_t &c)
 {
     v = 0.0;
     g = 0.0;
+    c = PAD;
     if (e < e1) {
-        const uint32_t c = wcol[e];
+        c = wcol[e];
         v = wval[e];
         g = (c & INTL) ? ring[(q - int32_t(c & MASK)) & (kWaveRing - 1)] : load_x(x + c);
     }
 }
 
-__device__ __forceinline__ void wave_task(const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr,
+// Semi-asynchronous wave cores: gathers that returned the not-yet-computed
+// mark are read again until every lane holds a computed value.  Returns
+// false once the spin limit is hit (setting *err) or another wave failed.
+__device__ __forceinline__ bool wave_await(uint32_t c, double &g, const double *x, int32_t *err, int64_t spin_limit)
+{
+    bool miss = (c & (HDR | INTL)) == 0 && static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
+    if (__ballot(miss) == 0ull) return true;
+    for (int64_t spins = 1;; spins++) {
+        __builtin_amdgcn_s_sleep(1);
+        if (miss) {
+            g = load_x(x + c);
+            miss = static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
+        }
+        if (__ballot(miss) == 0ull) return true;
+        if (spins > spin_limit) {
+            if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    }
+}
+
+template <bool kAsync>
+__device__ __forceinline__ bool wave_task(const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr,
                                           const double *__restrict__ wdiag, const uint32_t *__restrict__ wcol,
                                           const double *__restrict__ wval, int64_t t0, int64_t t1, const double *b,
-                                          double *x, double *ring)
+                                          double *x, double *ring, int32_t *err, int64_t spin_limit)
 {
     const int lane = threadIdx.x & 63;
     for (int64_t t = t0; t < t1; t++) {
@@ -521,15 +546,20 @@ __device__ __forceinline__ void wave_task(const int32_t *__restrict__ wrow, cons
         double acc = load_x(b + row);
         const int64_t e0 = wptr[t], e1 = wptr[t + 1];
         double v, g;
-        wave_load(wcol, wval, e0 + lane, e1, x, ring, q, v, g);
+        uint32_t c;
+        wave_load(wcol, wval, e0 + lane, e1, x, ring, q, v, g, c);
         for (int64_t base = e0; base < e1; base += 64) {
             double vn, gn;
-            wave_load(wcol, wval, base + 64 + lane, e1, x, ring, q, vn, gn);
+            uint32_t cn;
+            wave_load(wcol, wval, base + 64 + lane, e1, x, ring, q, vn, gn, cn);
+            if constexpr (kAsync)
+                if (!wave_await(c, g, x, err, spin_limit)) return false;
             const double p = v * g;
             const int cnt = int(min<int64_t>(64, e1 - base));
             for (int l = 0; l < cnt; l++) acc = acc - readlane_f64(p, l);
             v = vn;
             g = gn;
+            c = cn;
         }
         const double y = acc / wdiag[t];
         if (lane == 0) {
@@ -538,6 +568,7 @@ __device__ __forceinline__ void wave_task(const int32_t *__restrict__ wrow, cons
         }
         __builtin_amdgcn_wave_barrier();
     }
+    return true;
 }
 
 // Supersteps [s0, s1) of a wave-core plan.  With s1 - s0 > 1 the grid is
@@ -556,12 +587,31 @@ __global__ __launch_bounds__(kBlock) void trsv_wave(
     double *my_ring = ring[threadIdx.x >> 6];
     for (int32_t s = s0; s < s1; s++) {
         for (int32_t t = wsuper[s] + slot; t < wsuper[s + 1]; t += waves)
-            wave_task(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring);
+            wave_task<false>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring, err, spin_limit);
         if (s + 1 < s1) {
             const BarrierTicket tk = barrier_arrive(bar);
             if (!barrier_wait(bar, tk, err, spin_limit)) return;
         }
     }
+}
+
+// Semi-asynchronous wave cores: x holds the not-yet-computed mark at the
+// start; wave w runs tasks w, w + W, ... in their global order (superstep by
+// superstep) and waits only for the values it gathers.  Progress as for
+// trsv_async: the earliest unfinished task depends only on finished tasks
+// and its wave has finished its own earlier tasks (all waves co-resident).
+__global__ __launch_bounds__(kBlock) void trsv_wave_async(
+    const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr, const double *__restrict__ wdiag,
+    const uint32_t *__restrict__ wcol, const double *__restrict__ wval, const int64_t *__restrict__ wtask,
+    int32_t tasks, const double *b, double *x, int32_t *err, int64_t spin_limit)
+{
+    __shared__ double ring[kWavesPerBlock][kWaveRing];
+    const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
+    const int32_t w = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
+    double *my_ring = ring[threadIdx.x >> 6];
+    for (int32_t t = w; t < tasks; t += waves)
+        if (!wave_task<true>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring, err, spin_limit))
+            return;
 }
 
 // ---------------------------------------------------------------------------
@@ -1666,6 +1716,20 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         int64_t gw = std::min<int64_t>(int64_t(per_cu_w) * cus, dev::kGroup * 128);
         if (opts->grid_blocks > 0) gw = std::min<int64_t>(gw, opts->grid_blocks);
         p->grid_wave = int(std::max<int64_t>(1, std::min<int64_t>(gw, (most + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
+        // semi-asynchronous: about four supersteps of average width in flight
+        // (one wave per task), at most one workgroup per CU, all co-resident
+        int per_cu_wa = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_wa, dev::trsv_wave_async, dev::kBlock, 0);
+        if (e != hipSuccess) {
+            gltrsv_plan_destroy(p);
+            return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
+        }
+        const int64_t wtasks = p->wsuper_host.empty() ? 0 : p->wsuper_host.back();
+        const int64_t avg_tasks = p->S > 0 ? (wtasks + p->S - 1) / p->S : 1;
+        int64_t gwa = std::min<int64_t>({int64_t(per_cu_wa) * cus, int64_t(cus), avg_tasks});
+        if (opts->grid_blocks > 0) gwa = std::min<int64_t>(opts->grid_blocks, int64_t(per_cu_wa) * cus);
+        p->grid_wave_async = int(std::max<int64_t>(
+            1, std::min<int64_t>(gwa, (wtasks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
     }
 #ifdef GLTRSV_TRACE
     {
@@ -1812,6 +1876,15 @@ int gltrsv_solve_async(gltrsv_plan *p, const double *b, double *x, void *stream)
     const int64_t fill_blocks = std::min<int64_t>(4096, (p->n + dev::kBlock - 1) / dev::kBlock);
     hipLaunchKernelGGL(dev::fill_unready, dim3(unsigned(fill_blocks)), dim3(dev::kBlock), 0, st,
                        reinterpret_cast<unsigned long long *>(x), p->n);
+    if (p->core_width == 64) {
+        const int32_t wtasks = p->wsuper_host.back();
+        hipLaunchKernelGGL(dev::trsv_wave_async, dim3(p->grid_wave_async), dim3(dev::kBlock), 0, st, p->d_wrow,
+                           p->d_wptr, p->d_wdiag, p->d_wcol, p->d_wval, p->d_wtask, wtasks, bb, x, p->d_err,
+                           p->spin_limit);
+        HIP_TRY(hipGetLastError());
+        p->last_stream = st;
+        return GLTRSV_OK;
+    }
     const int32_t chunks = int32_t(p->chunks);
     int64_t lim = p->spin_limit;
     if (p->cooperative) {

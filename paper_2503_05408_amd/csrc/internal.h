@@ -156,6 +156,7 @@ struct gltrsv_plan {
     int32_t *d_wsuper = nullptr;        // [S + 1] task range of each superstep
     std::vector<int32_t> wsuper_host;   // [S + 1] task range of each superstep
     int grid_wave = 0;                  // workgroups of the persistent wave kernel
+    int grid_wave_async = 0;            // workgroups of the semi-asynchronous wave kernel
 };
 
 inline int64_t widest_of(const std::vector<gltrsv_plan *> &plans)

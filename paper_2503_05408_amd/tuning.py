@@ -87,7 +87,7 @@ def matrix_key(m, opts) -> str:
 def best_plan(m, opts=None, path: str | None = None, reps: int = 5, core_widths=(1,)):
     """A plan for m with the measured-fastest schedule (GrowLocal or
     wavefront), core width (`core_widths`: 1 = a core is a lane, 64 = a core
-    is a wavefront, which applies to the persistent and plain forms) and
+    is a wavefront) and
     execution form (persistent, plain, semi-asynchronous) for
     gltrsv_solve_auto.  With `path`, the choice is read from / stored in the
     JSON table there, so a later process builds only the chosen plan.
@@ -117,7 +117,7 @@ def best_plan(m, opts=None, path: str | None = None, reps: int = 5, core_widths=
         for kind, sname in SCHEDULES.items():
             plan = B.Plan(m, variant(kind, width))
             res = plan.tune(reps=reps)
-            usable = {f: us for f, us in res["us"].items() if width == 1 or f != "async"}
+            usable = res["us"]
             for f, us in usable.items():
                 times[f"{sname}/w{width}/{f}"] = us
             form = min(usable, key=usable.get)

@@ -168,7 +168,7 @@ def test_best_plan_with_wave_cores(tmp_path):
     plan, entry = tuning.best_plan(m, B.gpu_opts(k=1024), str(tmp_path / "w.json"), reps=2, core_widths=(1, 64))
     print(entry, flush=True)
     with plan:
-        assert len(entry["us"]) == 10               # 2 schedules x (3 lane forms + 2 wave forms)
+        assert len(entry["us"]) == 12               # 2 schedules x 2 widths x 3 forms
         fastest = min(entry["us"], key=entry["us"].get)
         assert fastest == f"{entry['schedule']}/w{entry['core_width']}/{entry['form']}"
         assert plan.info()["core_width"] == entry["core_width"]

@@ -1,9 +1,10 @@
 """Wavefront cores (GPU): with opts.core_width = 64 a BSP core is a whole
 wavefront that forms 64 products of a row at once and subtracts them in
-stored order.  gltrsv_solve and gltrsv_solve_plain must give the oracle's
+stored order.  gltrsv_solve, gltrsv_solve_plain and gltrsv_solve_async
+(semi-asynchronous wave cores) must give the oracle's
 bits for lower and upper systems, rows shorter and longer than 64 entries,
 same-task dependencies near (LDS ring) and far (memory) and every schedule
-kind, in place or not; the other forms of the same plan are unaffected."""
+kind, in place or not; several right-hand sides keep lane cores."""
 import numpy as np
 import pytest
 
@@ -46,7 +47,7 @@ def test_wave_cores_match_the_oracle(case, oname, upper):
     bd = torch.from_numpy(b).cuda()
     with B.Plan(m, B.default_opts(core_width=64, **over)) as plan:
         assert plan.info()["core_width"] == 64
-        for solve in (plan.solve, plan.solve_plain):
+        for solve in (plan.solve, plan.solve_plain, plan.solve_async):
             x = torch.full_like(bd, float("nan"))
             solve(bd, x)
             torch.cuda.synchronize()
@@ -56,9 +57,9 @@ def test_wave_cores_match_the_oracle(case, oname, upper):
             solve(y, y)
             torch.cuda.synchronize()
             assert oracle.same_bits(y.cpu().numpy(), want), ("in place", solve.__name__)
-        x = plan.solve_async(bd)                   # one lane per core, same schedule
+        X = plan.solve_multi(torch.stack([bd, -bd], dim=1).contiguous())   # lane cores, same schedule
         torch.cuda.synchronize()
-        assert oracle.same_bits(x.cpu().numpy(), want)
+        assert oracle.same_bits(X[:, 0].cpu().numpy(), want)
 
 
 def test_wave_cores_repeat_and_reject_bad_width():
@@ -68,11 +69,12 @@ def test_wave_cores_repeat_and_reject_bad_width():
     b = torch.ones(m.n, dtype=torch.float64, device="cuda")
     with B.Plan(m, B.default_opts(core_width=64, k=1024, L=50.0, alpha0=1.0)) as plan:
         x = torch.empty_like(b)
-        for _ in range(30):
-            x.fill_(float("nan"))
-            plan.solve(b, x)
-        torch.cuda.synchronize()
-        assert plan.device_status() == 0
-        assert oracle.same_bits(x.cpu().numpy(), want)
+        for solve in (plan.solve, plan.solve_async):
+            for _ in range(30):
+                x.fill_(float("nan"))
+                solve(b, x)
+            torch.cuda.synchronize()
+            assert plan.device_status() == 0
+            assert oracle.same_bits(x.cpu().numpy(), want)
     with pytest.raises(B.GltrsvError):
         B.Plan(m, B.default_opts(core_width=32))
