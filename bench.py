@@ -247,6 +247,27 @@ def main():
         ms_unordered = u0.elapsed_time(u1) / args.plain_steps
     del core, sup
 
+    # wavefront cores (a BSP core is a whole wave) on the wavefront schedule
+    wopts = B.PlanOpts()
+    ctypes.memmove(ctypes.byref(wopts), ctypes.byref(opts), ctypes.sizeof(wopts))
+    wopts.core_width = 64
+    wopts.schedule_kind = B.SCHED_WAVEFRONT
+    wave = {}
+    with B.Plan(m, wopts) as wplan:
+        for name, fn in (("persistent", wplan.solve), ("async", wplan.solve_async)):
+            x.fill_(float("nan"))
+            fn(b, x)
+            torch.cuda.synchronize()
+            ok = wplan.device_status() == 0 and oracle.same_bits(x.cpu().numpy(), want)
+            w0 = torch.cuda.Event(enable_timing=True)
+            w1 = torch.cuda.Event(enable_timing=True)
+            w0.record(stream)
+            for _ in range(args.plain_steps):
+                fn(b, x)
+            w1.record(stream)
+            torch.cuda.synchronize()
+            wave[name] = {"ms_per_step": w0.elapsed_time(w1) / args.plain_steps, "exact": bool(ok)}
+
     # semi-asynchronous form: no barriers, per-row readiness
     x.fill_(0.0)
     plan.solve_async(b, x)
@@ -368,6 +389,7 @@ def main():
         "plain": {"value": rows_s_plain, "ms_per_step": ms_plain, "launches_per_step": info["supersteps"],
                   "graph_ms_per_step": ms_graph},
         "speedup_vs_plain": (ms_plain / ms) if ms > 0 else None,
+        "wave_cores_wavefront": wave,
         "unordered": {"ms_per_step": ms_unordered, "exact": bool(exact_unordered),
                       "reorder_speedup": (ms_unordered / ms_plain) if ms_plain > 0 else None},
         "multi_rhs": multi,

@@ -1716,8 +1716,10 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         int64_t gw = std::min<int64_t>(int64_t(per_cu_w) * cus, dev::kGroup * 128);
         if (opts->grid_blocks > 0) gw = std::min<int64_t>(gw, opts->grid_blocks);
         p->grid_wave = int(std::max<int64_t>(1, std::min<int64_t>(gw, (most + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
-        // semi-asynchronous: about four supersteps of average width in flight
-        // (one wave per task), at most one workgroup per CU, all co-resident
+        // semi-asynchronous: at least two workgroups per CU, more for large
+        // systems (about one wave per 1,024 rows: each wave has one row in
+        // flight), all co-resident.  Measured on MI355X: 512 workgroups were
+        // best for the n = 1e5 ER and NB sets, the full 2,048 for n = 1e7.
         int per_cu_wa = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_wa, dev::trsv_wave_async, dev::kBlock, 0);
         if (e != hipSuccess) {
@@ -1725,8 +1727,8 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
             return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
         }
         const int64_t wtasks = p->wsuper_host.empty() ? 0 : p->wsuper_host.back();
-        const int64_t avg_tasks = p->S > 0 ? (wtasks + p->S - 1) / p->S : 1;
-        int64_t gwa = std::min<int64_t>({int64_t(per_cu_wa) * cus, int64_t(cus), avg_tasks});
+        int64_t gwa = std::min<int64_t>(int64_t(per_cu_wa) * cus,
+                                        std::max<int64_t>(2 * int64_t(cus), (p->n + 4095) / 4096));
         if (opts->grid_blocks > 0) gwa = std::min<int64_t>(opts->grid_blocks, int64_t(per_cu_wa) * cus);
         p->grid_wave_async = int(std::max<int64_t>(
             1, std::min<int64_t>(gwa, (wtasks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
