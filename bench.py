@@ -595,34 +595,15 @@ def bench_batch(args):
     stream = torch.cuda.Stream()
     bd = [torch.ones(m.n, dtype=torch.float64, device="cuda") for m in ms]
     xd = [torch.full((m.n,), float("nan"), dtype=torch.float64, device="cuda") for m in ms]
-    best = None
-    timings = {}
-    for async_exec, per_claim in [(False, 1), (False, 2), (False, 4), (True, 1), (True, 2), (True, 4)]:
-        # execution form and claim size picked by measurement
-        with torch.cuda.stream(stream):
-            bt = B.Batch(plans_async if async_exec else plans, per_claim=per_claim, use_graph=True,
-                         async_exec=async_exec)
-            for _ in range(max(1, args.warmup)):
-                bt.solve(bd, xd, stream)
-            stream.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(args.steps):
-                bt.solve(bd, xd, stream)
-            e1.record(stream)
-            stream.synchronize()
-            ms_b = e0.elapsed_time(e1) / args.steps
-            ok = bt.status() == 0
-        form = "async" if async_exec else "bsp"
-        log(f"{form} per_claim={per_claim}: {ms_b:.3f} ms status_ok={ok}")
-        timings[f"{form}_claim{per_claim}_ms"] = ms_b
-        if ok and (best is None or ms_b < best[1]):
-            if best is not None:
-                best[2].close()
-            best = (per_claim, ms_b, bt, form)
-        else:
-            bt.close()
-    per_claim, ms_b, bt, form = best
+    # execution form and claim size picked by the autotuner (measured)
+    from paper_2503_05408_amd import tuning
+    with torch.cuda.stream(stream):
+        bt, entry = tuning.best_batch(plans, bd, xd, plans_async=plans_async, claims=(1, 2, 4, 8),
+                                      reps=args.steps, stream=stream)
+    per_claim, form = entry["per_claim"], entry["form"]
+    timings = {f"{k.split('/')[0]}_claim{k.split('/')[1]}_ms": v for k, v in entry["ms"].items()}
+    ms_b = timings[f"{form}_claim{per_claim}_ms"]
+    log(f"autotuned: {form} per_claim={per_claim} {ms_b:.3f} ms; {timings}")
     for x in xd:
         x.fill_(float("nan"))
     with torch.cuda.stream(stream):

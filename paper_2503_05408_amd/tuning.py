@@ -135,3 +135,70 @@ def best_plan(m, opts=None, path: str | None = None, reps: int = 5, core_widths=
         table[key] = entry
         store_table(path, table)
     return plan, entry
+
+
+def _batch_key(plans, plans_async) -> str:
+    import hashlib
+
+    import torch
+    h = hashlib.blake2b(digest_size=12)
+    for group in (plans, plans_async or []):
+        for p in group:
+            h.update(tuning_key(p).encode())
+        h.update(b"|")
+    dev = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"batch/{h.hexdigest()}/{dev.name}/{getattr(dev, 'gcnArchName', '')}"
+
+
+def best_batch(plans, b, x, plans_async=None, claims=(1, 2, 4, 8), reps: int = 3, path: str | None = None,
+               stream=None):
+    """The batched launch (gltrsv_batch_*) with the measured-fastest chunk
+    claim size and execution form for this set of systems: BSP on `plans`,
+    and, when `plans_async` (the same systems, e.g. planned for
+    semi-asynchronous execution) is given, semi-asynchronous on those.  b and
+    x: lists of device tensors per system, not aliasing each other; x ends
+    holding the solutions.  With `path` the choice is read from / stored in
+    the JSON table there.  Returns (batch, entry) with entry = {"form",
+    "per_claim", "ms"}; the caller closes the batch."""
+    import torch
+    stream = stream or torch.cuda.current_stream()
+    forms = [("bsp", plans)] + ([("async", plans_async)] if plans_async is not None else [])
+    key = _batch_key(plans, plans_async) if path else None
+    if path:
+        hit = load_table(path).get(key)
+        if isinstance(hit, dict) and hit.get("form") in dict(forms) and int(hit.get("per_claim", 0)) >= 1:
+            bt = B.Batch(dict(forms)[hit["form"]], per_claim=int(hit["per_claim"]), use_graph=True,
+                         async_exec=hit["form"] == "async")
+            return bt, hit
+    best, times = None, {}
+    for form, ps in forms:
+        for pc in claims:
+            bt = B.Batch(ps, per_claim=pc, use_graph=True, async_exec=form == "async")
+            bt.solve(b, x, stream)
+            stream.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                bt.solve(b, x, stream)
+            e1.record(stream)
+            stream.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            if bt.status() != 0:
+                bt.close()
+                continue
+            times[f"{form}/{pc}"] = ms
+            if best is None or ms < best[1]:
+                if best is not None:
+                    best[0].close()
+                best = (bt, ms, form, pc)
+            else:
+                bt.close()
+    if best is None:
+        raise RuntimeError("no batch configuration completed without a device error")
+    bt, ms, form, pc = best
+    entry = {"form": form, "per_claim": pc, "ms": times}
+    if path:
+        table = load_table(path)
+        table[key] = entry
+        store_table(path, table)
+    return bt, entry

@@ -175,3 +175,38 @@ def test_best_plan_with_wave_cores(tmp_path):
         x = plan.solve_auto(torch.ones(m.n, dtype=torch.float64, device="cuda"))
         torch.cuda.synchronize()
         assert oracle.same_bits(x.cpu().numpy(), want)
+
+
+def test_best_batch_picks_the_fastest_configuration(tmp_path):
+    import torch
+    ms = [gen.erdos_renyi(3000, 0.003, gen.SEED_BASE + 47), gen.stencil_2d5(40, 30),
+          gen.narrow_band(2500, 0.05, 20, gen.SEED_BASE + 48), gen.chain(200)]
+    plans = [B.Plan(m, B.gpu_opts(schedule_kind=B.SCHED_AUTO)) for m in ms]
+    plans_a = [B.Plan(m, B.gpu_opts(schedule_kind=B.SCHED_AUTO, exec_hint=1)) for m in ms]
+    bs = [torch.from_numpy(gen.rhs_uniform(m.n, 20 + i)).cuda() for i, m in enumerate(ms)]
+    wants = [oracle.solve(m, b.cpu().numpy()) for m, b in zip(ms, bs)]
+    xs = [torch.full_like(b, float("nan")) for b in bs]
+    path = str(tmp_path / "batch.json")
+    bt, entry = tuning.best_batch(plans, bs, xs, plans_async=plans_a, claims=(1, 2), reps=2, path=path)
+    print(entry, flush=True)
+    with bt:
+        assert len(entry["ms"]) == 4
+        assert f"{entry['form']}/{entry['per_claim']}" == min(entry["ms"], key=entry["ms"].get)
+        for x in xs:
+            x.fill_(float("nan"))
+        bt.solve(bs, xs)
+        torch.cuda.synchronize()
+        assert bt.status() == 0
+        for x, w in zip(xs, wants):
+            assert oracle.same_bits(x.cpu().numpy(), w)
+    # a stored choice is used as it is
+    table = tuning.load_table(path)
+    (key,) = table
+    table[key] = {"form": "bsp", "per_claim": 2, "ms": {}}
+    tuning.store_table(path, table)
+    bt, entry = tuning.best_batch(plans, bs, xs, plans_async=plans_a, path=path)
+    with bt:
+        assert entry["form"] == "bsp" and entry["per_claim"] == 2
+        assert bt.info()["systems"] == len(ms)
+    for p in plans + plans_a:
+        p.close()
