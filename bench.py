@@ -62,15 +62,13 @@ def algorithmic_bytes(n: int, nnz: int) -> int:
 
 
 def kernel_sources_hash() -> str:
-    """Hash of what the measured kernels are built from: the device section of
-    gltrsv.hip (everything before its host runtime) and the analysis that lays
-    out the stream they read."""
+    """Hash of what the measured kernels are built from: the kernels, the
+    constants they share with the host, and the analysis that lays out the
+    stream they read."""
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2503_05408_amd/csrc/gltrsv.hip"), "rb") as fh:
-        text = fh.read()
-    h.update(text.split(b"// host runtime and C ABI")[0])
-    for f in ("paper_2503_05408_amd/csrc/analysis.cpp", "paper_2503_05408_amd/csrc/analysis.h"):
+    for f in ("paper_2503_05408_amd/csrc/kernels.hip", "paper_2503_05408_amd/csrc/internal.h",
+              "paper_2503_05408_amd/csrc/analysis.cpp", "paper_2503_05408_amd/csrc/analysis.h"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

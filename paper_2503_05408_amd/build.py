@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgltrsv.so")
 SOURCES_HOST = ["analysis.cpp"]
-SOURCES_HIP = ["gltrsv.hip", "serve.hip", "pack.hip"]
+SOURCES_HIP = ["kernels.hip", "gltrsv.hip", "serve.hip", "pack.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GLTRSV_ARCH", "gfx950")
 

@@ -1,15 +1,7 @@
-// gltrsv: GrowLocal-scheduled sparse lower-triangular solve for gfx950.
-//
-// Device side: every BSP core of the schedule (Definition 2.1) is one lane
-// of a 64-wide wavefront.  A lane walks the rows of its (superstep, core)
-// task in the order of Sec. 5, each row as the forward substitution of
-// Eq. (2.1): acc <- b_i, acc <- acc - A_ij * x_j over the stored
-// off-diagonals (no fused multiply-add), x_i <- acc / A_ii.  Tasks of one
-// superstep never read each other's results (Def. 2.1), so the only
-// synchronisation is the barrier between supersteps: the kernel boundary in
-// the plain form, a device-scope counter in the persistent form.
-//
-// Host side: the C ABI of include/gltrsv.h.
+// gltrsv host runtime and C ABI (include/gltrsv.h): option checks, plans
+// (analysis, layouts, device upload), the single-system solve forms, the
+// execution-form autotuner, batches and the measurement probes.  The kernels
+// are in kernels.hip; the server is in serve.hip, device packing in pack.hip.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -21,1129 +13,6 @@
 #include "../../include/gltrsv.h"
 #include "analysis.h"
 #include "internal.h"
-
-#pragma clang fp contract(off)
-
-namespace gltrsv {
-namespace dev {
-
-constexpr uint32_t HDR = 0x80000000u;
-constexpr uint32_t INTL = 0x40000000u;
-constexpr uint32_t MASK = 0x3FFFFFFFu;
-constexpr uint32_t PAD = 0xFFFFFFFFu;
-// Entries per batch (below).  A short batch shortens a lane's serial path,
-// since each batch waits for its own gathers; a long one keeps more gathers
-// in flight per lane.  Measured on MI355X: 4 is fastest for the single-system
-// kernels and BSP batches, 8 for semi-asynchronous batches and several
-// right-hand sides.
-#ifndef GLTRSV_UNROLL
-#define GLTRSV_UNROLL 4
-#endif
-#ifndef GLTRSV_UNROLL_WIDE
-#define GLTRSV_UNROLL_WIDE 8
-#endif
-constexpr int kUnroll = GLTRSV_UNROLL;
-constexpr int kUnrollWide = GLTRSV_UNROLL_WIDE;
-using gltrsv::kRing;
-
-// One lane processes the packed entries of its task: entry t at
-// word/value[base + 64 t + lane], t < len.  Entries are handled in batches of
-// U (kUnroll or kUnrollWide) through a two-deep pipeline:
-//   while batch i is processed, the gathers of batch i+1 and the words and
-//   values of batch i+2 are in flight;
-//   every operand that is final before batch i+1 starts (x of an earlier
-//   superstep, b of a new row, a row of this task at least kRing rows back)
-//   is gathered from memory; rows of this task fewer than kRing rows back come
-//   from an on-chip ring (a register for the previous row, LDS for older);
-//   the x values finished in a batch are stored after the batch, so no store
-//   sits in front of a wait.
-// A row read from memory by batch j finished at least kRing >= 2 U
-// entries earlier, i.e. in batch j-2 or before, whose stores precede the
-// gathers of batch j in the lane's program order.
-// Loads are issued unconditionally (padding slots re-read the chunk's first
-// slot, non-gathered operands re-read b[0]) so their count per iteration is
-// fixed and the compiler can wait for exactly the batch it needs.
-static_assert(2 * kUnroll <= gltrsv::kRing && 2 * kUnrollWide <= gltrsv::kRing,
-              "the ring must cover two batches");
-
-template <int U>
-struct Batch {
-    uint32_t w[U];
-    double v[U];
-};
-
-// Cross-workgroup data protocol.  x is the only array written during a
-// solve.  Every access to it (and to b, which may alias it) is an agent-scope
-// atomic access; on this GPU family those are the L2-coherent (sc1) loads and
-// stores, so a value stored by any XCD is what any other XCD loads once the
-// store has completed.  The barrier therefore needs no L2 write-back or
-// invalidation: an arrival waits for the workgroup's stores to complete, and
-// the gathers of the next superstep are issued after the new generation has
-// been observed.  (Plain accesses with agent-scope release/acquire fences
-// at the barrier are slower: each fence writes back or invalidates the XCD's
-// whole L2, and plain random gathers are no faster than coherent ones.)
-__device__ __forceinline__ double load_x(const double *p)
-{
-    const unsigned long long u =
-        __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double(static_cast<long long>(u));
-}
-
-__device__ __forceinline__ void store_x(double *p, double v)
-{
-    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
-                       static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-
-struct LaneCursor {
-    const uint32_t *wp;   // word + base + lane
-    const double *vp;
-    int32_t len;
-};
-
-__device__ __forceinline__ LaneCursor make_cursor(const uint32_t *__restrict__ word, const double *__restrict__ value,
-                                                  int64_t base, int32_t len, int lane)
-{
-    LaneCursor c;
-    c.wp = word + base + lane;
-    c.vp = value + base + lane;
-    c.len = len;
-    return c;
-}
-
-template <int U>
-__device__ __forceinline__ void load_batch(const LaneCursor &c, int32_t t0, Batch<U> &B)
-{
-#pragma unroll
-    for (int j = 0; j < U; j++) {
-        const bool in = t0 + j < c.len;
-        const int64_t off = in ? int64_t(t0 + j) * 64 : 0;
-        const uint32_t w = __builtin_nontemporal_load(c.wp + off);
-        const double v = __builtin_nontemporal_load(c.vp + off);
-        B.w[j] = in ? w : PAD;
-        B.v[j] = v;
-    }
-}
-
-template <int U>
-__device__ __forceinline__ void gather_batch(const Batch<U> &B, const double *b, const double *x, double (&g)[U])
-{
-#pragma unroll
-    for (int j = 0; j < U; j++) {
-        const uint32_t c = B.w[j];
-        const bool ext = (c & (HDR | INTL)) == 0;
-        const bool hdr = (c & HDR) && c != PAD;
-        const double *src = ext ? x + c : (hdr ? b + (c & MASK) : b);
-        g[j] = load_x(src);
-    }
-}
-
-struct LaneState {
-    double acc, diag, last_y;
-    int32_t cur;
-    uint32_t pos;
-};
-
-// Ring of the lane's recent rows in LDS: slot r % kRing holds row r of the
-// task; slot kRing takes the writes of entries that finish no row, so the
-// write needs no branch.
-using Ring = double (*)[kBlock];
-
-// Handles U entries in order.  Every entry runs the same instruction
-// sequence: the division that closes a row is evaluated for every entry and
-// kept only at row headers, so the wave never splits on the entry kind.
-template <int U>
-__device__ __forceinline__ void process_batch(const Batch<U> &B, const double (&g)[U], LaneState &st, double *x,
-                                              Ring ring)
-{
-    double ys[U];
-    int32_t yrow[U];
-#pragma unroll
-    for (int j = 0; j < U; j++) {
-        const uint32_t c = B.w[j];
-        const bool hdr = (c & HDR) != 0;           // row header or padding
-        const bool intl = (c >> 30) == 1u;         // same task, a few rows back
-        const bool fin = hdr && st.cur >= 0;       // closes the current row
-        const double y = st.acc / st.diag;
-        ys[j] = y;
-        yrow[j] = fin ? st.cur : -1;
-        st.last_y = fin ? y : st.last_y;
-        ring[fin ? (st.pos % kRing) : kRing][threadIdx.x] = y;
-        st.pos += fin ? 1u : 0u;
-        const uint32_t back = c & MASK;
-        double xv = g[j];
-        if (intl && back >= 2u) xv = ring[(st.pos - back) % kRing][threadIdx.x];
-        xv = (intl && back == 1u) ? st.last_y : xv;
-        const double prod = B.v[j] * xv;
-        const double nacc = st.acc - prod;
-        st.acc = hdr ? g[j] : nacc;
-        st.diag = hdr ? B.v[j] : st.diag;
-        st.cur = hdr ? (c == PAD ? -1 : int32_t(back)) : st.cur;
-    }
-#pragma unroll
-    for (int j = 0; j < U; j++)
-        if (yrow[j] >= 0) store_x(x + yrow[j], ys[j]);
-}
-
-// Semi-asynchronous execution: x starts filled with kUnready, a signalling
-// NaN.  Every value the solve stores is the result of a division, which never
-// yields a signalling NaN, so a gathered kUnready means "not computed yet":
-// the gather is repeated until the value arrives.
-constexpr unsigned long long kUnready = 0x7FF4A5A5A5A5A5A5ull;
-#ifndef GLTRSV_AWAIT_NAP_MAX
-#define GLTRSV_AWAIT_NAP_MAX 1
-#endif
-constexpr int kAwaitNapMax = GLTRSV_AWAIT_NAP_MAX;   // longest pause between re-reads, in s_sleep(1) units
-
-__device__ __forceinline__ bool unready(uint32_t c, double g)
-{
-    return (c & (HDR | INTL)) == 0 && static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
-}
-
-// Waits until every gathered column of the batch holds a computed value.
-// Gives up after spin_limit rounds (setting *err) or once another wave has
-// set *err; the solve's status then reports the failure.
-template <int U>
-__device__ __forceinline__ void await_batch(const Batch<U> &B, double (&g)[U], const double *x, int32_t *err,
-                                            int64_t spin_limit)
-{
-    bool miss = false;
-#pragma unroll
-    for (int j = 0; j < U; j++) miss |= unready(B.w[j], g[j]);
-    if (__ballot(miss) == 0ull) return;
-    int32_t nap = 1;
-    for (int64_t spins = 1;; spins++) {
-        for (int32_t k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(1);
-        nap = min(2 * nap, int32_t(kAwaitNapMax));
-#pragma unroll
-        for (int j = 0; j < U; j++)
-            if (unready(B.w[j], g[j])) g[j] = load_x(x + B.w[j]);
-        miss = false;
-#pragma unroll
-        for (int j = 0; j < U; j++) miss |= unready(B.w[j], g[j]);
-        if (__ballot(miss) == 0ull) return;
-        if (spins > spin_limit) {
-            if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
-        }
-        if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-    }
-}
-
-// One pipeline step: gathers of `nxt`, words/values of the batch after it
-// into `fut`, then the work of `now` (in the semi-asynchronous form, once
-// every operand of `now` has been computed).
-#define GLTRSV_STEP(NOW, GNOW, NXT, GNXT, FUT, T0)                                                       \
-    do {                                                                                                 \
-        gather_batch(NXT, b, x, GNXT);                                                                   \
-        load_batch(cur, (T0) + 2 * U, FUT);                                                              \
-        if constexpr (kAsync) await_batch(NOW, GNOW, x, err, spin_limit);                                \
-        process_batch(NOW, GNOW, st, x, ring);                                                           \
-    } while (0)
-
-// Runs one lane's task.  b0/b1 hold the task's first two batches (already
-// loaded by the caller, possibly before the superstep's barrier).  The loop
-// is unrolled three times so the three batch buffers change roles without
-// register copies.
-template <int U, bool kAsync = false>
-__device__ __forceinline__ void run_lane(const LaneCursor &cur, Batch<U> &b0, Batch<U> &b1, const double *b,
-                                         double *x, Ring ring, int32_t *err = nullptr, int64_t spin_limit = 0)
-{
-    LaneState st;
-    st.acc = 0.0;
-    st.diag = 1.0;
-    st.last_y = 0.0;
-    st.cur = -1;
-    st.pos = 0;
-    Batch<U> b2;
-    double g0[U], g1[U], g2[U];
-    gather_batch(b0, b, x, g0);
-    int32_t t0 = 0;
-    for (;;) {
-        GLTRSV_STEP(b0, g0, b1, g1, b2, t0);
-        t0 += U;
-        if (t0 >= cur.len) break;
-        GLTRSV_STEP(b1, g1, b2, g2, b0, t0);
-        t0 += U;
-        if (t0 >= cur.len) break;
-        GLTRSV_STEP(b2, g2, b0, g0, b1, t0);
-        t0 += U;
-        if (t0 >= cur.len) break;
-    }
-    if (st.cur >= 0) store_x(x + st.cur, st.acc / st.diag);
-}
-#undef GLTRSV_STEP
-
-__global__ __launch_bounds__(kBlock) void trsv_superstep_plain(
-    const uint32_t *__restrict__ word, const double *__restrict__ value, const int64_t *__restrict__ chunk_base,
-    const int32_t *__restrict__ chunk_len, int32_t c0, int32_t c1, const double *b, double *x)
-{
-    __shared__ double ring[kRing + 1][kBlock];
-    const int32_t c = c0 + int32_t((blockIdx.x * kBlock + threadIdx.x) >> 6);
-    if (c >= c1) return;
-    const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], threadIdx.x & 63);
-    Batch<kUnroll> b0, b1;
-    load_batch(cur, 0, b0);
-    load_batch(cur, kUnroll, b1);
-    run_lane(cur, b0, b1, b, x, ring);
-}
-
-// The schedule executed without the reorder of Sec. 5 (the ablation of the
-// paper's locality study): the matrix stays in the caller's CSR order and
-// each lane walks the rows of its task through the row pointers.  One launch
-// per superstep; lane t of the launch runs task t0 + t (tasks of a superstep
-// longest first, as in the packed layout).  Per row the same operations in
-// the same order as every other form: acc = b_i, then acc - a_ij x_j over
-// the stored off-diagonals in stored order, then one division.  A row of
-// the same task read from x was stored earlier by this lane (same address,
-// program order); rows of other tasks come from earlier supersteps.
-__global__ __launch_bounds__(kBlock) void trsv_superstep_unordered(
-    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ val,
-    const int32_t *__restrict__ rows, const int64_t *__restrict__ task_off, int32_t t0, int32_t t1, int32_t upper,
-    const double *b, double *x)
-{
-    const int32_t t = t0 + int32_t(blockIdx.x * kBlock + threadIdx.x);
-    if (t >= t1) return;
-    for (int64_t k = task_off[t]; k < task_off[t + 1]; k++) {
-        const int32_t r = rows[k];
-        const int64_t beg = row_ptr[r], end = row_ptr[r + 1];
-        const int64_t d = upper ? beg : end - 1;   // the diagonal: first (upper) or last (lower) entry
-        int64_t e = upper ? beg + 1 : beg;
-        const int64_t e_end = upper ? end : end - 1;
-        double acc = load_x(b + r);
-        // four entries at a time: their loads first, then the subtractions in order
-        for (; e + 4 <= e_end; e += 4) {
-            int32_t c[4];
-            double v[4], g[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                c[j] = col[e + j];
-                v[j] = val[e + j];
-            }
-#pragma unroll
-            for (int j = 0; j < 4; j++) g[j] = load_x(x + c[j]);
-#pragma unroll
-            for (int j = 0; j < 4; j++) acc = acc - v[j] * g[j];
-        }
-        for (; e < e_end; e++) acc = acc - val[e] * load_x(x + col[e]);
-        store_x(x + r, acc / val[d]);
-    }
-}
-
-// Barrier over all workgroups of the grid, in two halves so that work that
-// does not depend on other workgroups can run while waiting.  Arrivals are
-// counted in two levels: workgroups of a group of kGroup count on the group's
-// word; the last of each group counts on the top word; the last of those
-// advances the generation word that every workgroup waits on.  No word sees
-// more than max(kGroup, groups) arrivals, and every word sits on its own
-// 128-byte line.  Each last arrival resets the word it completed before
-// moving up, so the words are ready for the next barrier.
-constexpr int kGroup = 16;
-constexpr int kBarGen = 0;          // word index of the generation
-constexpr int kBarTop = 32;         // word index of the top count
-constexpr int kBarGroups = 64;      // group g counts at kBarGroups + 32 g
-constexpr int kBarWords = kBarGroups + 32 * 128;   // up to 128 groups
-
-struct BarrierTicket {
-    uint32_t gen;
-    bool last;
-};
-
-__device__ __forceinline__ BarrierTicket barrier_arrive(uint32_t *bar)
-{
-    // Every wave waits until its own (coherent) stores have completed.
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __syncthreads();
-    __shared__ uint32_t s_gen;
-    __shared__ int32_t s_last;
-    if (threadIdx.x == 0) {
-        const uint32_t G = gridDim.x;
-        const uint32_t grp = blockIdx.x / kGroup;
-        const uint32_t groups = (G + kGroup - 1) / kGroup;
-        const uint32_t gsize = min(uint32_t(kGroup), G - grp * kGroup);
-        uint32_t *gen = bar + kBarGen;
-        uint32_t *top = bar + kBarTop;
-        uint32_t *cnt = bar + kBarGroups + 32 * grp;
-        const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        bool last = false;
-        const uint32_t old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == gsize - 1) {
-            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t old2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (old2 == groups - 1) {
-                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                last = true;
-            }
-        }
-        s_gen = g;
-        s_last = last;
-    }
-    __syncthreads();
-    BarrierTicket t;
-    t.gen = s_gen;
-    t.last = s_last != 0;
-    return t;
-}
-
-// Returns false if the spin limit was hit or another workgroup reported an
-// error; then the whole workgroup must exit.
-__device__ __forceinline__ bool barrier_wait(uint32_t *bar, BarrierTicket t, int32_t *err, int64_t spin_limit)
-{
-    __shared__ int32_t ok;
-    if (threadIdx.x == 0) {
-        int32_t good = 1;
-        if (!t.last) {
-            const uint32_t *gen = bar + kBarGen;
-            int64_t it = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == t.gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++it > spin_limit) {
-                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    good = 0;
-                    break;
-                }
-                if ((it & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    good = 0;
-                    break;
-                }
-            }
-        }
-        ok = good;
-    }
-    __syncthreads();
-    return ok != 0;
-}
-
-__global__ __launch_bounds__(kBlock) void trsv_persistent(
-    const uint32_t *__restrict__ word, const double *__restrict__ value, const int64_t *__restrict__ chunk_base,
-    const int32_t *__restrict__ chunk_len, const int32_t *__restrict__ super_chunk, int32_t S, const double *b,
-    double *x, uint32_t *bar, int32_t *err, int64_t spin_limit, int64_t *trace)
-{
-    const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
-    // wave slot: the i-th wave of workgroup g is slot i G + g.  Chunks of a
-    // superstep are sorted longest first, so every workgroup (one per CU)
-    // takes one chunk from each quarter of that order, and a narrow
-    // superstep spreads over as many CUs as it has chunks, instead of
-    // filling the first CUs with the longest chunks four at a time.
-    const int32_t wave = int32_t(threadIdx.x >> 6) * int32_t(gridDim.x) + int32_t(blockIdx.x);
-    const int lane = threadIdx.x & 63;
-    __shared__ double ring[kRing + 1][kBlock];
-    // first chunk of this wave in superstep 0, and its first two batches
-    int32_t c = super_chunk[0] + wave;
-    int32_t c_end = super_chunk[1];
-    LaneCursor cur = make_cursor(word, value, c < c_end ? chunk_base[c] : 0, c < c_end ? chunk_len[c] : 0, lane);
-    Batch<kUnroll> b0, b1;
-    load_batch(cur, 0, b0);
-    load_batch(cur, kUnroll, b1);
-    for (int32_t s = 0; s < S; s++) {
-#ifdef GLTRSV_TRACE
-        if (threadIdx.x == 0) trace[(int64_t(s) * gridDim.x + blockIdx.x) * 3 + 0] = wall_clock64();
-#endif
-        while (c < c_end) {
-            run_lane(cur, b0, b1, b, x, ring);
-            c += waves;
-            if (c < c_end) {
-                cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
-                load_batch(cur, 0, b0);
-                load_batch(cur, kUnroll, b1);
-            }
-        }
-#ifdef GLTRSV_TRACE
-        if (threadIdx.x == 0) trace[(int64_t(s) * gridDim.x + blockIdx.x) * 3 + 1] = wall_clock64();
-#endif
-        if (s + 1 < S) {
-            const BarrierTicket t = barrier_arrive(bar);
-            // the matrix stream of the next superstep does not depend on x:
-            // fetch it while the other workgroups finish
-            c = super_chunk[s + 1] + wave;
-            c_end = super_chunk[s + 2];
-            cur = make_cursor(word, value, c < c_end ? chunk_base[c] : 0, c < c_end ? chunk_len[c] : 0, lane);
-            load_batch(cur, 0, b0);
-            load_batch(cur, kUnroll, b1);
-            if (!barrier_wait(bar, t, err, spin_limit)) return;
-        }
-#ifdef GLTRSV_TRACE
-        if (threadIdx.x == 0) trace[(int64_t(s) * gridDim.x + blockIdx.x) * 3 + 2] = wall_clock64();
-#endif
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Wavefront cores (opts.core_width = 64): a BSP core is a whole wavefront.
-// The task's rows run one after another; for each row the 64 lanes load 64
-// of its off-diagonals at once, gather x and form the products, and the wave
-// subtracts them from acc = b_i in stored order (one lane's product at a
-// time, broadcast with readlane), so every row sees exactly the operations
-// of the one-lane form.  The next 64 entries are loaded and gathered while
-// the current ones are subtracted.  Columns among the task's last kWaveRing
-// rows are marked in the layout and read from a per-wave LDS ring; older
-// rows of the task were stored before the wave's last full memory wait,
-// which it takes every kWaveRing rows.
-// ---------------------------------------------------------------------------
-constexpr int kWaveRing = 64;
-
-__device__ __forceinline__ double readlane_f64(double v, int l)
-{
-    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
-    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u)), l));
-    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u >> 32)), l));
-    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
-}
-
-// value of entry e (if e < e1) of the current row: a column from memory or
-// from the ring; the product is formed by the caller.  c receives the word
-// (kPadWord past the row's end).
-__device__ __forceinline__ void wave_load(const uint32_t *__restrict__ wcol, const double *__restrict__ wval,
-                                          int64_t e, int64_t e1, const double *x, const double *ring, int32_t q,
-                                          double &v, double &g, uint32_t &c)
-{
-    v = 0.0;
-    g = 0.0;
-    c = PAD;
-    if (e < e1) {
-        c = wcol[e];
-        v = wval[e];
-        g = (c & INTL) ? ring[(q - int32_t(c & MASK)) & (kWaveRing - 1)] : load_x(x + c);
-    }
-}
-
-// Semi-asynchronous wave cores: gathers that returned the not-yet-computed
-// mark are read again until every lane holds a computed value.  Returns
-// false once the spin limit is hit (setting *err) or another wave failed.
-__device__ __forceinline__ bool wave_await(uint32_t c, double &g, const double *x, int32_t *err, int64_t spin_limit)
-{
-    bool miss = (c & (HDR | INTL)) == 0 && static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
-    if (__ballot(miss) == 0ull) return true;
-    for (int64_t spins = 1;; spins++) {
-        __builtin_amdgcn_s_sleep(1);
-        if (miss) {
-            g = load_x(x + c);
-            miss = static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
-        }
-        if (__ballot(miss) == 0ull) return true;
-        if (spins > spin_limit) {
-            if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-    }
-}
-
-template <bool kAsync>
-__device__ __forceinline__ bool wave_task(const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr,
-                                          const double *__restrict__ wdiag, const uint32_t *__restrict__ wcol,
-                                          const double *__restrict__ wval, int64_t t0, int64_t t1, const double *b,
-                                          double *x, double *ring, int32_t *err, int64_t spin_limit)
-{
-    const int lane = threadIdx.x & 63;
-    for (int64_t t = t0; t < t1; t++) {
-        const int32_t q = int32_t(t - t0);   // row index within the task
-        if (q > 0 && (q & (kWaveRing - 1)) == 0) __builtin_amdgcn_s_waitcnt(0);   // older rows are in memory
-        const int32_t row = wrow[t];
-        double acc = load_x(b + row);
-        const int64_t e0 = wptr[t], e1 = wptr[t + 1];
-        double v, g;
-        uint32_t c;
-        wave_load(wcol, wval, e0 + lane, e1, x, ring, q, v, g, c);
-        for (int64_t base = e0; base < e1; base += 64) {
-            double vn, gn;
-            uint32_t cn;
-            wave_load(wcol, wval, base + 64 + lane, e1, x, ring, q, vn, gn, cn);
-            if constexpr (kAsync)
-                if (!wave_await(c, g, x, err, spin_limit)) return false;
-            const double p = v * g;
-            const int cnt = int(min<int64_t>(64, e1 - base));
-            for (int l = 0; l < cnt; l++) acc = acc - readlane_f64(p, l);
-            v = vn;
-            g = gn;
-            c = cn;
-        }
-        const double y = acc / wdiag[t];
-        if (lane == 0) {
-            ring[q & (kWaveRing - 1)] = y;
-            store_x(x + row, y);
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-    return true;
-}
-
-// Supersteps [s0, s1) of a wave-core plan.  With s1 - s0 > 1 the grid is
-// co-resident and the device-scope barrier separates the supersteps; a
-// single superstep per launch needs none.  The i-th wave of workgroup g is
-// slot i G + g (tasks of a superstep sorted longest first).
-__global__ __launch_bounds__(kBlock) void trsv_wave(
-    const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr, const double *__restrict__ wdiag,
-    const uint32_t *__restrict__ wcol, const double *__restrict__ wval, const int64_t *__restrict__ wtask,
-    const int32_t *__restrict__ wsuper, int32_t s0, int32_t s1, const double *b, double *x, uint32_t *bar,
-    int32_t *err, int64_t spin_limit)
-{
-    __shared__ double ring[kWavesPerBlock][kWaveRing];
-    const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
-    const int32_t slot = int32_t(threadIdx.x >> 6) * int32_t(gridDim.x) + int32_t(blockIdx.x);
-    double *my_ring = ring[threadIdx.x >> 6];
-    for (int32_t s = s0; s < s1; s++) {
-        for (int32_t t = wsuper[s] + slot; t < wsuper[s + 1]; t += waves)
-            wave_task<false>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring, err, spin_limit);
-        if (s + 1 < s1) {
-            const BarrierTicket tk = barrier_arrive(bar);
-            if (!barrier_wait(bar, tk, err, spin_limit)) return;
-        }
-    }
-}
-
-// Semi-asynchronous wave cores: x holds the not-yet-computed mark at the
-// start; wave w runs tasks w, w + W, ... in their global order (superstep by
-// superstep) and waits only for the values it gathers.  Progress as for
-// trsv_async: the earliest unfinished task depends only on finished tasks
-// and its wave has finished its own earlier tasks (all waves co-resident).
-__global__ __launch_bounds__(kBlock) void trsv_wave_async(
-    const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr, const double *__restrict__ wdiag,
-    const uint32_t *__restrict__ wcol, const double *__restrict__ wval, const int64_t *__restrict__ wtask,
-    int32_t tasks, const double *b, double *x, int32_t *err, int64_t spin_limit)
-{
-    __shared__ double ring[kWavesPerBlock][kWaveRing];
-    const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
-    const int32_t w = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
-    double *my_ring = ring[threadIdx.x >> 6];
-    for (int32_t t = w; t < tasks; t += waves)
-        if (!wave_task<true>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring, err, spin_limit))
-            return;
-}
-
-// ---------------------------------------------------------------------------
-// Semi-asynchronous solve: no barriers.  Wave w runs chunks w, w + W, w + 2W,
-// ... in order (chunks are numbered superstep by superstep), and a lane waits
-// only for the columns it reads (await_batch).  Progress: the earliest
-// unfinished chunk depends only on chunks of earlier supersteps, which are
-// finished, and its wave has finished its own earlier chunks, so it is
-// running it; hence every chunk completes provided all W waves are resident
-// (the grid is sized to the device's co-resident capacity, as for the
-// persistent kernel, and a wave kept from starting ends the solve with the
-// spin-limit error instead of a hang).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void fill_unready(unsigned long long *x, int64_t n)
-{
-    const int64_t stride = int64_t(gridDim.x) * kBlock;
-    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) x[i] = kUnready;
-}
-
-__global__ __launch_bounds__(kBlock) void trsv_async(const uint32_t *__restrict__ word,
-                                                     const double *__restrict__ value,
-                                                     const int64_t *__restrict__ chunk_base,
-                                                     const int32_t *__restrict__ chunk_len, int32_t chunks,
-                                                     const double *b, double *x, int32_t *err, int64_t spin_limit)
-{
-    __shared__ double ring[kRing + 1][kBlock];
-    const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
-    const int lane = threadIdx.x & 63;
-    for (int32_t c = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6); c < chunks; c += waves) {
-        const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
-        Batch<kUnroll> b0, b1;
-        load_batch(cur, 0, b0);
-        load_batch(cur, kUnroll, b1);
-        run_lane<kUnroll, true>(cur, b0, b1, b, x, ring, err, spin_limit);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Several right-hand sides at once (SpTRSM): B and X are row-major n x ld,
-// a launch handles R consecutive columns.  Each lane runs its task once for
-// all R columns: one pass over the stream, and the R values of a gathered
-// column lie next to each other in memory.  Per column the operations and
-// their order are exactly those of the one-column solve.  Semi-asynchronous
-// (per-row readiness, as trsv_async); one wave per workgroup keeps the
-// R-column ring of recent rows within LDS.
-// ---------------------------------------------------------------------------
-template <int R>
-struct MultiState {
-    double acc[R], last_y[R];
-    double diag;
-    int32_t cur;
-    uint32_t pos;
-};
-
-template <int R>
-using MultiRing = double (*)[R][64];
-
-template <int R>
-__device__ __forceinline__ void gather_multi(const Batch<kUnrollWide> &B, const double *b, const double *x,
-                                             int64_t ld, double (&g)[kUnrollWide][R])
-{
-#pragma unroll
-    for (int j = 0; j < kUnrollWide; j++) {
-        const uint32_t c = B.w[j];
-        const bool ext = (c & (HDR | INTL)) == 0;
-        const bool hdr = (c & HDR) && c != PAD;
-        const double *src = ext ? x + int64_t(c) * ld : (hdr ? b + int64_t(c & MASK) * ld : b);
-#pragma unroll
-        for (int r = 0; r < R; r++) g[j][r] = load_x(src + r);
-    }
-}
-
-template <int R>
-__device__ __forceinline__ void await_multi(const Batch<kUnrollWide> &B, double (&g)[kUnrollWide][R], const double *x,
-                                            int64_t ld, int32_t *err, int64_t spin_limit)
-{
-    bool miss = false;
-#pragma unroll
-    for (int j = 0; j < kUnrollWide; j++)
-#pragma unroll
-        for (int r = 0; r < R; r++) miss |= unready(B.w[j], g[j][r]);
-    if (__ballot(miss) == 0ull) return;
-    for (int64_t spins = 1;; spins++) {
-        __builtin_amdgcn_s_sleep(1);
-        miss = false;
-#pragma unroll
-        for (int j = 0; j < kUnrollWide; j++)
-#pragma unroll
-            for (int r = 0; r < R; r++) {
-                if (unready(B.w[j], g[j][r])) g[j][r] = load_x(x + int64_t(B.w[j]) * ld + r);
-                miss |= unready(B.w[j], g[j][r]);
-            }
-        if (__ballot(miss) == 0ull) return;
-        if (spins > spin_limit) {
-            if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
-        }
-        if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-    }
-}
-
-// process_batch for R columns: the same branch-free sequence per column.
-template <int R>
-__device__ __forceinline__ void process_multi(const Batch<kUnrollWide> &B, const double (&g)[kUnrollWide][R],
-                                              MultiState<R> &st, double *x, int64_t ld, MultiRing<R> ring)
-{
-    const int lane = threadIdx.x & 63;
-    double ys[kUnrollWide][R];
-    int32_t yrow[kUnrollWide];
-#pragma unroll
-    for (int j = 0; j < kUnrollWide; j++) {
-        const uint32_t c = B.w[j];
-        const bool hdr = (c & HDR) != 0;
-        const bool intl = (c >> 30) == 1u;
-        const bool fin = hdr && st.cur >= 0;
-        const uint32_t slot = fin ? (st.pos % kRing) : kRing;
-        yrow[j] = fin ? st.cur : -1;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            const double y = st.acc[r] / st.diag;
-            ys[j][r] = y;
-            st.last_y[r] = fin ? y : st.last_y[r];
-            ring[slot][r][lane] = y;
-        }
-        st.pos += fin ? 1u : 0u;
-        const uint32_t back = c & MASK;
-        const uint32_t rs = (st.pos - back) % kRing;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            double xv = g[j][r];
-            if (intl && back >= 2u) xv = ring[rs][r][lane];
-            xv = (intl && back == 1u) ? st.last_y[r] : xv;
-            const double prod = B.v[j] * xv;
-            const double nacc = st.acc[r] - prod;
-            st.acc[r] = hdr ? g[j][r] : nacc;
-        }
-        st.diag = hdr ? B.v[j] : st.diag;
-        st.cur = hdr ? (c == PAD ? -1 : int32_t(back)) : st.cur;
-    }
-#pragma unroll
-    for (int j = 0; j < kUnrollWide; j++)
-        if (yrow[j] >= 0)
-#pragma unroll
-            for (int r = 0; r < R; r++) store_x(x + int64_t(yrow[j]) * ld + r, ys[j][r]);
-}
-
-template <int R>
-__device__ __forceinline__ void run_lane_multi(const LaneCursor &cur, const double *b, double *x, int64_t ld,
-                                               MultiRing<R> ring, int32_t *err, int64_t spin_limit)
-{
-    MultiState<R> st;
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        st.acc[r] = 0.0;
-        st.last_y[r] = 0.0;
-    }
-    st.diag = 1.0;
-    st.cur = -1;
-    st.pos = 0;
-    Batch<kUnrollWide> now, nxt;
-    double gnow[kUnrollWide][R], gnxt[kUnrollWide][R];
-    load_batch(cur, 0, now);
-    gather_multi<R>(now, b, x, ld, gnow);
-    for (int32_t t0 = 0; t0 < cur.len; t0 += kUnrollWide) {
-        load_batch(cur, t0 + kUnrollWide, nxt);
-        gather_multi<R>(nxt, b, x, ld, gnxt);
-        await_multi<R>(now, gnow, x, ld, err, spin_limit);
-        process_multi<R>(now, gnow, st, x, ld, ring);
-        now = nxt;
-#pragma unroll
-        for (int j = 0; j < kUnrollWide; j++)
-#pragma unroll
-            for (int r = 0; r < R; r++) gnow[j][r] = gnxt[j][r];
-    }
-    if (st.cur >= 0)
-#pragma unroll
-        for (int r = 0; r < R; r++) store_x(x + int64_t(st.cur) * ld + r, st.acc[r] / st.diag);
-}
-
-template <int R>
-__global__ __launch_bounds__(64) void trsv_async_multi(const uint32_t *__restrict__ word,
-                                                       const double *__restrict__ value,
-                                                       const int64_t *__restrict__ chunk_base,
-                                                       const int32_t *__restrict__ chunk_len, int32_t chunks,
-                                                       const double *b, double *x, int64_t ld, int32_t *err,
-                                                       int64_t spin_limit)
-{
-    __shared__ double ring[kRing + 1][R][64];
-    const int lane = threadIdx.x & 63;
-    for (int32_t c = int32_t(blockIdx.x); c < chunks; c += int32_t(gridDim.x)) {
-        const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
-        run_lane_multi<R>(cur, b, x, ld, ring, err, spin_limit);
-    }
-}
-
-template __global__ void trsv_async_multi<1>(const uint32_t *, const double *, const int64_t *, const int32_t *,
-                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t);
-template __global__ void trsv_async_multi<2>(const uint32_t *, const double *, const int64_t *, const int32_t *,
-                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t);
-template __global__ void trsv_async_multi<4>(const uint32_t *, const double *, const int64_t *, const int32_t *,
-                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t);
-
-// ---------------------------------------------------------------------------
-// Batched solve: many independent systems in one launch.
-//
-// Every system i has a 64-bit state word: high half = its open superstep,
-// low half = chunks of that superstep claimed so far.  A wave claims chunks
-// with one atomic add on the state word; a claim whose low half is beyond the
-// superstep's chunk count finds no work.  The wave that completes the last
-// chunk of superstep s (per-superstep done counters) publishes s+1 by
-// exchanging the state word to (s+1, 0): increments that land before the
-// exchange belonged to the exhausted superstep, those after it are claims of
-// s+1.  Systems never wait for each other, and a wave only waits for chunks
-// that running waves hold, so the grid needs no co-residency.
-// ---------------------------------------------------------------------------
-
-
-__device__ __forceinline__ unsigned long long *state_word(unsigned long long *state, int32_t i)
-{
-    return state + int64_t(i) * kStateStride;
-}
-
-// One claim of up to per_claim chunks of system i: valid iff the claimed
-// index lies inside the superstep the word held at that moment (it may have
-// advanced since it was read).
-__device__ __forceinline__ int32_t try_claim(const SysDesc *__restrict__ sys, unsigned long long *state, int32_t i,
-                                             int32_t per_claim, int32_t *gs_out, int32_t *c0, int32_t *c1)
-{
-    const unsigned long long got = __hip_atomic_fetch_add(state_word(state, i), (unsigned long long)per_claim,
-                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int32_t gs = int32_t(got >> 32);
-    const int64_t gc = int64_t(got & 0xffffffffull);
-    if (gs >= sys[i].S) return 0;
-    const int32_t *sc = sys[i].super_chunk;
-    const int32_t n2 = sc[gs + 1] - sc[gs];
-    if (gc >= n2) return 0;
-    *gs_out = gs;
-    *c0 = sc[gs] + int32_t(gc);
-    *c1 = sc[gs] + int32_t(min<int64_t>(gc + per_claim, n2));
-    return 1;
-}
-
-__global__ __launch_bounds__(kBlock) void batch_reset(unsigned long long *state, uint32_t *done, int32_t count,
-                                                      int32_t ndone, uint32_t *finished, int32_t *err)
-{
-    const int32_t i = int32_t(blockIdx.x) * kBlock + int32_t(threadIdx.x);
-    if (i < count) *state_word(state, i) = 0ull;
-    for (int32_t j = i; j < ndone; j += int32_t(gridDim.x) * kBlock) done[j] = 0u;
-    if (i == 0) {
-        finished[0] = 0u;
-        finished[1] = 0u;
-        *err = 0;
-    }
-}
-
-// spin_limit: wall-clock ticks a wave may go without finding work.
-// target: the launch ends once `finished` reaches it (systems completed in
-// this launch).  quantum: wall-clock ticks after which waves stop claiming
-// (<= 0: no limit); claimed chunks are always completed, so every state word
-// is consistent when the launch ends and a later launch continues from it.
-__global__ __launch_bounds__(kBlock) void trsv_batched(const SysDesc *__restrict__ sys, int32_t count,
-                                                       unsigned long long *state, uint32_t *done,
-                                                       uint32_t *finished, int32_t *err, int64_t spin_limit,
-                                                       int32_t per_claim, int32_t target, int64_t quantum,
-                                                       int32_t keep_waves)
-{
-    __shared__ double ring[kRing + 1][kBlock];
-    __shared__ uint32_t done_mask[kMaskSystems / 32];   // systems seen finished
-    for (int q = threadIdx.x; q < kMaskSystems / 32; q += kBlock) done_mask[q] = 0u;
-    __syncthreads();
-    const int32_t total_waves = int32_t(gridDim.x) * kWavesPerBlock;
-    const int lane = threadIdx.x & 63;
-    const int32_t wave = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
-    int32_t home = count > 0 ? wave % count : 0;
-    int64_t idle_since = -1;   // wall-clock tick when this wave last found no work
-    const int64_t deadline = quantum > 0 ? int64_t(wall_clock64()) + quantum : -1;
-    int32_t nap = 1;           // idle back-off, in units of s_sleep(2)
-    int32_t idle = 0;          // consecutive scans without work
-    bool may_retire = true;
-    for (;;) {
-        // lane 0 walks the systems from `home` on and claims from the first
-        // one with an unclaimed chunk; `live` counts the unfinished ones seen
-        int32_t found = -1, fs = 0, c0 = 0, c1 = 0, live = 0;
-        const bool late = deadline >= 0 && int64_t(wall_clock64()) > deadline;
-        if (lane == 0) {
-            for (int32_t t = 0; t < count && found < 0 && !late; t++) {
-                const int32_t i = home + t < count ? home + t : home + t - count;
-                if (i < kMaskSystems && (done_mask[i >> 5] >> (i & 31)) & 1u) continue;
-                const unsigned long long st = __hip_atomic_load(state_word(state, i), __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT);
-                const int32_t s = int32_t(st >> 32);
-                if (s >= sys[i].S) {
-                    if (i < kMaskSystems) atomicOr(&done_mask[i >> 5], 1u << (i & 31));
-                    continue;
-                }
-                live++;
-                const int32_t *sc = sys[i].super_chunk;
-                if (int64_t(st & 0xffffffffull) >= int64_t(sc[s + 1] - sc[s])) continue;
-                if (try_claim(sys, state, i, per_claim, &fs, &c0, &c1)) found = i;
-            }
-        }
-        found = __shfl(found, 0);
-        if (found < 0) {
-            int32_t quit = 0;
-            idle++;
-            if (lane == 0) {
-                // every system finished (a full scan saw none open), the
-                // quantum is over, or (checked now and then) the target is
-                // met or another wave failed
-                quit = late || live == 0;
-                if (!quit && (idle & 15) == 0)
-                    quit = __hip_atomic_load(finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= uint32_t(target) ||
-                           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-            }
-            if (lane == 0 && !quit) {
-                for (int32_t k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(2);
-                nap = min(2 * nap, int32_t(kIdleNapMax));
-                const int64_t now = int64_t(wall_clock64());
-                if (idle_since < 0) {
-                    idle_since = now;
-                } else if (now - idle_since > spin_limit) {
-                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                } else if (may_retire && now - idle_since > kRetireTicks) {
-                    // retire unless that would leave keep_waves or fewer; a
-                    // wave refused once stays for the rest of the launch
-                    const uint32_t r = __hip_atomic_fetch_add(finished + 1, 1u, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT);
-                    if (int64_t(total_waves) - int64_t(r) - 1 >= int64_t(keep_waves)) {
-                        quit = 1;
-                    } else {
-                        __hip_atomic_fetch_sub(finished + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        may_retire = false;
-                    }
-                }
-            }
-            if (__shfl(quit, 0)) return;
-            continue;
-        }
-        fs = __shfl(fs, 0);
-        c0 = __shfl(c0, 0);
-        c1 = __shfl(c1, 0);
-        idle = 0;
-        nap = 1;
-        idle_since = -1;
-        home = found;
-        const SysDesc d = sys[found];
-        for (int32_t c = c0; c < c1; c++) {
-            const LaneCursor cur = make_cursor(d.word, d.value, d.chunk_base[c], d.chunk_len[c], lane);
-            Batch<kUnroll> b0, b1;
-            load_batch(cur, 0, b0);
-            load_batch(cur, kUnroll, b1);
-            run_lane(cur, b0, b1, d.b, d.x, ring);
-        }
-        // the chunks' x stores are complete before they are counted as done
-        __builtin_amdgcn_s_waitcnt(0);
-        if (lane == 0) {
-            const int32_t nch = d.super_chunk[fs + 1] - d.super_chunk[fs];
-            const uint32_t old = __hip_atomic_fetch_add(done + d.done_off + fs, uint32_t(c1 - c0),
-                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (int64_t(old) + (c1 - c0) == nch) {
-                __hip_atomic_exchange(state_word(state, found), (unsigned long long)(fs + 1) << 32, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-                if (fs + 1 == d.S)
-                    __hip_atomic_fetch_add(finished, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    }
-}
-
-// The solve's memory traffic without its dependencies: one wave per chunk
-// streams the chunk's words and values and gathers x at every column the
-// solve reads from memory; a header closes the previous row with y[row] =
-// the running sum, in stored order, of value * x (1.0 stands in for x at
-// entries the solve takes from its on-chip ring).  No barrier, no division,
-// no row waits for another: the floor one solve's bytes can reach.
-__global__ __launch_bounds__(kBlock) void gather_probe(const uint32_t *__restrict__ word,
-                                                       const double *__restrict__ value,
-                                                       const int64_t *__restrict__ chunk_base,
-                                                       const int32_t *__restrict__ chunk_len, int64_t chunks,
-                                                       const double *__restrict__ x, double *__restrict__ y)
-{
-    const int lane = threadIdx.x & 63;
-    const int64_t c = int64_t(blockIdx.x) * kWavesPerBlock + int64_t(threadIdx.x >> 6);
-    if (c >= chunks) return;
-    const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
-    double acc = 0.0;
-    int32_t row = -1;
-    Batch<kUnrollWide> now, nxt;
-    load_batch(cur, 0, now);
-    for (int32_t t0 = 0; t0 < cur.len; t0 += kUnrollWide) {
-        load_batch(cur, t0 + kUnrollWide, nxt);
-        double g[kUnrollWide];
-#pragma unroll
-        for (int j = 0; j < kUnrollWide; j++) {
-            const uint32_t w = now.w[j];
-            const bool ext = (w & (HDR | INTL)) == 0;
-            const double gx = load_x(ext ? x + w : x);
-            g[j] = ext ? gx : 1.0;
-        }
-#pragma unroll
-        for (int j = 0; j < kUnrollWide; j++) {
-            const uint32_t w = now.w[j];
-            if (w & HDR) {
-                if (row >= 0) y[row] = acc;
-                acc = 0.0;
-                row = w == PAD ? -1 : int32_t(w & MASK);
-            } else {
-                acc = acc + now.v[j] * g[j];
-            }
-        }
-        now = nxt;
-    }
-    if (row >= 0) y[row] = acc;
-}
-
-// ---------------------------------------------------------------------------
-// Semi-asynchronous batched solve.  Per system one 64-bit word: low half =
-// chunks claimed, high half = chunks completed.  Chunks are claimed in order
-// (an atomic add on the low half), at most `window` ahead of the completed
-// ones, and run with per-row readiness (await_batch) instead of barriers.
-// Progress needs no co-residency: the earliest unfinished chunk of a system
-// depends only on finished chunks and is held by a running wave, since claims
-// are made by running waves in order and a wave runs its claims in order.
-// A wave leaves when no system has an unclaimed chunk (its claimed chunks are
-// done by then), or once the quantum has passed (claimed chunks are always
-// completed, so a later launch continues from the words).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void fill_unready_sys(const SysDesc *__restrict__ sys, int32_t count)
-{
-    const int32_t i = int32_t(blockIdx.y);
-    if (i >= count) return;
-    unsigned long long *x = reinterpret_cast<unsigned long long *>(sys[i].x);
-    const int64_t n = sys[i].n;
-    const int64_t stride = int64_t(gridDim.x) * kBlock;
-    for (int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x; r < n; r += stride) x[r] = kUnready;
-}
-
-__global__ __launch_bounds__(kBlock) void trsv_batched_async(const SysDesc *__restrict__ sys, int32_t count,
-                                                             unsigned long long *state, uint32_t *finished,
-                                                             int32_t *err, int64_t spin_limit, int32_t per_claim,
-                                                             int64_t quantum)
-{
-    __shared__ double ring[kRing + 1][kBlock];
-    __shared__ uint32_t done_mask[kMaskSystems / 32];   // systems with every chunk claimed
-    for (int q = threadIdx.x; q < kMaskSystems / 32; q += kBlock) done_mask[q] = 0u;
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int32_t wave = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
-    int32_t home = count > 0 ? wave % count : 0;
-    const int64_t deadline = quantum > 0 ? int64_t(wall_clock64()) + quantum : -1;
-    int32_t nap = 1;
-    int64_t idle = 0;
-    for (;;) {
-        int32_t found = -1, c0 = 0, c1 = 0, open = 0;
-        const bool late = deadline >= 0 && int64_t(wall_clock64()) > deadline;
-        if (lane == 0) {
-            for (int32_t t = 0; t < count && found < 0 && !late; t++) {
-                const int32_t i = home + t < count ? home + t : home + t - count;
-                if (i < kMaskSystems && (done_mask[i >> 5] >> (i & 31)) & 1u) continue;
-                const int32_t nch = sys[i].nchunks;
-                const unsigned long long st = __hip_atomic_load(state_word(state, i), __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT);
-                const int64_t claimed = int64_t(st & 0xffffffffull), done = int64_t(st >> 32);
-                if (claimed >= nch) {
-                    if (i < kMaskSystems) atomicOr(&done_mask[i >> 5], 1u << (i & 31));
-                    continue;
-                }
-                open++;
-                if (claimed - done >= sys[i].window) continue;   // far enough ahead
-                const unsigned long long got = __hip_atomic_fetch_add(
-                    state_word(state, i), (unsigned long long)per_claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int64_t g = int64_t(got & 0xffffffffull);
-                if (g < nch) {
-                    found = i;
-                    c0 = int32_t(g);
-                    c1 = int32_t(min<int64_t>(g + per_claim, nch));
-                }
-            }
-        }
-        found = __shfl(found, 0);
-        if (found < 0) {
-            int32_t quit = 0;
-            if (lane == 0) {
-                quit = late || open == 0 || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-                if (!quit) {   // every open system is a window ahead: wait for completions
-                    for (int32_t k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(2);
-                    nap = min(2 * nap, int32_t(kIdleNapMax));
-                    if (++idle > spin_limit) {
-                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        quit = 1;
-                    }
-                }
-            }
-            if (__shfl(quit, 0)) return;
-            continue;
-        }
-        c0 = __shfl(c0, 0);
-        c1 = __shfl(c1, 0);
-        nap = 1;
-        idle = 0;
-        home = found;
-        const SysDesc d = sys[found];
-        for (int32_t c = c0; c < c1; c++) {
-            const LaneCursor cur = make_cursor(d.word, d.value, d.chunk_base[c], d.chunk_len[c], lane);
-            Batch<kUnrollWide> b0, b1;
-            load_batch(cur, 0, b0);
-            load_batch(cur, kUnrollWide, b1);
-            run_lane<kUnrollWide, true>(cur, b0, b1, d.b, d.x, ring, err, spin_limit);
-        }
-        // the chunks' x stores are complete before they are counted as done
-        __builtin_amdgcn_s_waitcnt(0);
-        if (lane == 0) {
-            const unsigned long long old = __hip_atomic_fetch_add(
-                state_word(state, found), (unsigned long long)(c1 - c0) << 32, __ATOMIC_RELAXED,
-                __HIP_MEMORY_SCOPE_AGENT);
-            if (int64_t(old >> 32) + (c1 - c0) == d.nchunks)
-                __hip_atomic_fetch_add(finished, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
-
-// Plain copy of 16-byte elements, grid-stride: the achievable-bandwidth
-// reference and the calibration kernel of the memory-traffic counters.
-__global__ __launch_bounds__(kBlock) void copy_probe(const double2 *__restrict__ src, double2 *__restrict__ dst,
-                                                     int64_t n16)
-{
-    const int64_t stride = int64_t(gridDim.x) * kBlock;
-    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
-}
-
-}  // namespace dev
-}  // namespace gltrsv
 
 // ===========================================================================
 // host runtime and C ABI

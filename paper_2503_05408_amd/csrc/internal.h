@@ -20,6 +20,19 @@ namespace dev {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
 
+// Persistent-kernel barrier words (one 128-byte line each): the generation,
+// the top count, and one count per group of kGroup workgroups (up to 128
+// groups, so a grid of at most 2,048 workgroups).
+constexpr int kGroup = 16;
+constexpr int kBarGen = 0;          // word index of the generation
+constexpr int kBarTop = 32;         // word index of the top count
+constexpr int kBarGroups = 64;      // group g counts at kBarGroups + 32 g
+constexpr int kBarWords = kBarGroups + 32 * 128;
+
+// Wavefront cores: rows of the same task this many back or fewer come from
+// a per-wave LDS ring (the layout marks them).
+constexpr int kWaveRing = 64;
+
 // Batched launches: the state word of system i sits at state[i * kStateStride]
 // (one per 256 bytes, so waves polling different systems do not queue on
 // one line); an idle wave sleeps 1, 2, 4, ... up to kIdleNapMax short naps
@@ -93,6 +106,39 @@ __global__ void fill_unready(unsigned long long *x, int64_t n);
 // n-1-v), as for pack_fill_upper.
 int device_pack(const CsrView &A, const std::vector<int32_t> &perm, const PackLayout &lay, bool upper,
                 uint32_t *d_word, double *d_value);
+
+// Single-system kernels (kernels.hip).  Lane cores, one launch per
+// superstep, chunks [c0, c1):
+__global__ void trsv_superstep_plain(const uint32_t *word, const double *value, const int64_t *chunk_base,
+                                     const int32_t *chunk_len, int32_t c0, int32_t c1, const double *b, double *x);
+// the same without the reorder of Sec. 5 (tasks [t0, t1) over the caller's CSR)
+__global__ void trsv_superstep_unordered(const int64_t *row_ptr, const int32_t *col, const double *val,
+                                         const int32_t *rows, const int64_t *task_off, int32_t t0, int32_t t1,
+                                         int32_t upper, const double *b, double *x);
+// lane cores, every superstep in one co-resident launch with a barrier
+__global__ void trsv_persistent(const uint32_t *word, const double *value, const int64_t *chunk_base,
+                                const int32_t *chunk_len, const int32_t *super_chunk, int32_t S, const double *b,
+                                double *x, uint32_t *bar, int32_t *err, int64_t spin_limit, int64_t *trace);
+// wavefront cores: supersteps [s0, s1) (a barrier between them), and the
+// semi-asynchronous form over all tasks
+__global__ void trsv_wave(const int32_t *wrow, const int64_t *wptr, const double *wdiag, const uint32_t *wcol,
+                          const double *wval, const int64_t *wtask, const int32_t *wsuper, int32_t s0, int32_t s1,
+                          const double *b, double *x, uint32_t *bar, int32_t *err, int64_t spin_limit);
+__global__ void trsv_wave_async(const int32_t *wrow, const int64_t *wptr, const double *wdiag, const uint32_t *wcol,
+                                const double *wval, const int64_t *wtask, int32_t tasks, const double *b, double *x,
+                                int32_t *err, int64_t spin_limit);
+// lane cores, semi-asynchronous; R right-hand sides (row-major, leading dimension ld)
+__global__ void trsv_async(const uint32_t *word, const double *value, const int64_t *chunk_base,
+                           const int32_t *chunk_len, int32_t chunks, const double *b, double *x, int32_t *err,
+                           int64_t spin_limit);
+template <int R>
+__global__ void trsv_async_multi(const uint32_t *word, const double *value, const int64_t *chunk_base,
+                                 const int32_t *chunk_len, int32_t chunks, const double *b, double *x, int64_t ld,
+                                 int32_t *err, int64_t spin_limit);
+// measurement probes
+__global__ void gather_probe(const uint32_t *word, const double *value, const int64_t *chunk_base,
+                             const int32_t *chunk_len, int64_t chunks, const double *x, double *y);
+__global__ void copy_probe(const double2 *src, double2 *dst, int64_t n16);
 
 // finished[0] = systems completed in the launch, finished[1] = waves retired
 __global__ void trsv_batched(const SysDesc *__restrict__ sys, int32_t count, unsigned long long *state,
