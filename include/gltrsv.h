@@ -247,12 +247,17 @@ typedef struct gltrsv_plan_info {
     int32_t async_grid_blocks; /* workgroups of gltrsv_solve_async            */
     int32_t exec_form;      /* preferred execution form of gltrsv_solve_auto
                                (GLTRSV_EXEC_*)                                */
-    int32_t core_width;     /* lanes per core of gltrsv_solve / _plain        */
+    int32_t core_width;     /* lanes per core of gltrsv_solve / _plain /
+                               _async                                         */
 } gltrsv_plan_info;
 
 /* Analyses A (checks, schedule, Sec. 5 order) and uploads the packed matrix
- * to the current HIP device.  The values of A are captured; a plan is
- * immutable afterwards, so solves on different streams may share it.
+ * to the current HIP device.  The values of A are captured; the matrix data
+ * of a plan never changes afterwards.  Solves on one plan must not overlap
+ * in time, whatever their streams: they share the plan's barrier and error
+ * words (and, for in-place semi-asynchronous solves, its copy of b).  Use one
+ * plan per concurrent stream, or a batch.  Batches and servers only read a
+ * plan's matrix data and may use it meanwhile.
  * *out is owned by the library until gltrsv_plan_destroy. */
 int gltrsv_plan_create(const gltrsv_csr *A, const gltrsv_plan_opts *opts, gltrsv_plan **out);
 
