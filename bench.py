@@ -587,6 +587,7 @@ def bench_batch(args):
     t = time.time()
     plans = [auto_plan(m) for m in ms]
     plans_async = [auto_plan(m, async_exec=True) for m in ms]
+    plans_wave = [B.Plan(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT, core_width=64)) for m in ms]
     log(f"plans in {time.time() - t:.1f} s; supersteps total {sum(p.info()['supersteps'] for p in plans)}, "
         f"max {max(p.info()['supersteps'] for p in plans)}; async-predicted plans: max supersteps "
         f"{max(p.info()['supersteps'] for p in plans_async)}")
@@ -596,8 +597,8 @@ def bench_batch(args):
     # execution form and claim size picked by the autotuner (measured)
     from paper_2503_05408_amd import tuning
     with torch.cuda.stream(stream):
-        bt, entry = tuning.best_batch(plans, bd, xd, plans_async=plans_async, claims=(1, 2, 4, 8),
-                                      reps=args.steps, stream=stream)
+        bt, entry = tuning.best_batch(plans, bd, xd, plans_async=plans_async, plans_wave=plans_wave,
+                                      claims=(1, 2, 4, 8), reps=args.steps, stream=stream)
     per_claim, form = entry["per_claim"], entry["form"]
     timings = {f"{k.split('/')[0]}_claim{k.split('/')[1]}_ms": v for k, v in entry["ms"].items()}
     ms_b = timings[f"{form}_claim{per_claim}_ms"]
@@ -638,14 +639,15 @@ def bench_batch(args):
         "config": {"workload": f"{len(ms)} independent systems, n = floor(10^U[3,6]), ER/NB/2-D/3-D mix, "
                                "one hipGraph-replayed persistent launch",
                    "rows": rows, "nnz": sum(m.nnz for m in ms), "per_claim": per_claim, "form": form,
-                   "schedule": "auto (GrowLocal k=65536 L=50 alpha0=1, or wavefront)"},
+                   "schedule": ("wavefront, wavefront cores" if form == "wave"
+                                else "auto (GrowLocal k=65536 L=50 alpha0=1, or wavefront)")},
         "timings": timings,
         "exact": bool(exact),
         "plain_sequential_ms": ms_plain, "persistent_sequential_ms": ms_pers,
         "speedup_vs_plain": ms_plain / ms_b,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "trsv_batched_async" if form == "async" else "trsv_batched",
+                     "kernel": {"async": "trsv_batched_async", "wave": "trsv_batched_wave_async"}.get(form, "trsv_batched"),
                      "alg_bytes_per_launch": alg},
     }
     bt.close()

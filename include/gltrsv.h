@@ -328,7 +328,13 @@ typedef struct gltrsv_batch_opts {
                               four supersteps of average width ahead of the
                               completed ones; x filled with the
                               not-yet-computed mark first, so b[i] must not
-                              alias x[i] (EINVAL)                             */
+                              alias x[i] (EINVAL).  If every plan was created
+                              with core_width = 64 the systems run on
+                              wavefront cores: their tasks in one global
+                              order (supersteps of all systems by relative
+                              depth s / S, each system's order kept), wave w
+                              taking every W-th, on a co-resident grid;
+                              per_claim is then unused                        */
 } gltrsv_batch_opts;
 
 void gltrsv_default_batch_opts(gltrsv_batch_opts *opts);

@@ -291,6 +291,10 @@ struct gltrsv_batch {
     int64_t idle_ticks = 1000000000;   // 10 s of the 100 MHz wall clock
     int32_t keep_waves = 0;            // waves that never retire (see dev::kRetireTicks)
     bool async_exec = false;           // semi-asynchronous kernel (no barriers)
+    bool wave = false;                 // ... on wavefront cores (every plan has core width 64)
+    int32_t *d_gsys = nullptr;         // wave cores: system of each global task
+    int32_t *d_gtask = nullptr;        // ... and its task index in that system
+    int64_t gtasks = 0;
 };
 
 extern "C" {
@@ -993,6 +997,8 @@ int gltrsv_batch_destroy(gltrsv_batch *bt)
     (void)hipFree(bt->d_done);
     (void)hipFree(bt->d_finished);
     (void)hipFree(bt->d_err);
+    (void)hipFree(bt->d_gsys);
+    (void)hipFree(bt->d_gtask);
     delete bt;
     return GLTRSV_OK;
 }
@@ -1031,6 +1037,8 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
         bt->ndone += plans[i]->S;
     }
     bt->count = int32_t(bt->plans.size());
+    bt->wave = bt->async_exec && bt->count > 0;
+    for (auto *pl : bt->plans) bt->wave = bt->wave && pl->core_width == 64;
     const size_t ndesc = std::max<size_t>(1, bt->plans.size());
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&bt->d_desc), ndesc * sizeof(dev::SysDesc));
     if (e == hipSuccess)
@@ -1065,18 +1073,60 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
             d.nchunks = int32_t(pl->chunks);
             d.window = dev::async_window(pl->chunks, pl->S);
             d.n = pl->n;
+            d.wrow = pl->d_wrow;
+            d.wptr = pl->d_wptr;
+            d.wdiag = pl->d_wdiag;
+            d.wcol = pl->d_wcol;
+            d.wval = pl->d_wval;
+            d.wtask = pl->d_wtask;
+            d.ntasks = pl->wsuper_host.empty() ? 0 : pl->wsuper_host.back();
+            if (bt->wave) d.window = dev::async_window(d.ntasks, pl->S);
             off += pl->S;
         }
     }
     int per_cu = 0, cus = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dev::trsv_batched, dev::kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, bt->wave ? reinterpret_cast<const void *>(dev::trsv_batched_wave_async)
+                          : reinterpret_cast<const void *>(dev::trsv_batched), dev::kBlock, 0);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
     if (e != hipSuccess) {
         gltrsv_batch_destroy(bt);
         return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
     }
-    int64_t chunks = 0;
-    for (auto *pl : bt->plans) chunks += pl->chunks;
+    int64_t chunks = 0;   // wave units of work: chunks, or tasks on wavefront cores
+    for (auto *pl : bt->plans) chunks += bt->wave ? (pl->wsuper_host.empty() ? 0 : pl->wsuper_host.back()) : pl->chunks;
+    if (bt->wave) {
+        // global task order: the supersteps of all systems by relative depth
+        // (s + 1/2) / S, so a system with many supersteps advances from the
+        // start alongside the short ones instead of running alone at the
+        // end; each system's own order is kept
+        std::vector<std::pair<double, std::pair<int32_t, int32_t>>> steps;   // (depth, (system, superstep))
+        for (int32_t i = 0; i < bt->count; i++) {
+            const gltrsv_plan *pl = bt->plans[size_t(i)];
+            for (int32_t s = 0; s < pl->S; s++) steps.push_back({(s + 0.5) / pl->S, {i, s}});
+        }
+        std::stable_sort(steps.begin(), steps.end(),
+                         [](const std::pair<double, std::pair<int32_t, int32_t>> &a,
+                            const std::pair<double, std::pair<int32_t, int32_t>> &b) { return a.first < b.first; });
+        std::vector<int32_t> gsys, gtask;
+        gsys.reserve(size_t(chunks));
+        gtask.reserve(size_t(chunks));
+        for (const auto &st : steps) {
+            const int32_t i = st.second.first, s = st.second.second;
+            const gltrsv_plan *pl = bt->plans[size_t(i)];
+            for (int32_t t = pl->wsuper_host[size_t(s)]; t < pl->wsuper_host[size_t(s) + 1]; t++) {
+                gsys.push_back(i);
+                gtask.push_back(t);
+            }
+        }
+        bt->gtasks = int64_t(gsys.size());
+        int64_t bytes = 0;
+        int rc;
+        if ((rc = upload(&bt->d_gsys, gsys, &bytes)) || (rc = upload(&bt->d_gtask, gtask, &bytes))) {
+            gltrsv_batch_destroy(bt);
+            return rc;
+        }
+    }
     int grid = std::max(1, per_cu * cus);
     if (opts->grid_blocks > 0) grid = std::min(grid, opts->grid_blocks);
     grid = int(std::max<int64_t>(1, std::min<int64_t>(grid, (chunks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
@@ -1097,9 +1147,13 @@ static int batch_enqueue(gltrsv_batch *bt, hipStream_t st)
         hipLaunchKernelGGL(dev::batch_reset, dim3(unsigned(std::max(1, (bt->count + dev::kBlock - 1) / dev::kBlock))),
                            dim3(dev::kBlock), 0, st, bt->d_state, bt->d_done, bt->count, 0, bt->d_finished,
                            bt->d_err);
-        hipLaunchKernelGGL(dev::trsv_batched_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st, bt->d_desc,
-                           bt->count, bt->d_state, bt->d_finished, bt->d_err, int64_t(5000000), bt->per_claim,
-                           int64_t(0));
+        if (bt->wave)
+            hipLaunchKernelGGL(dev::trsv_batched_wave_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st,
+                               bt->d_desc, bt->d_gsys, bt->d_gtask, bt->gtasks, bt->d_err, int64_t(5000000));
+        else
+            hipLaunchKernelGGL(dev::trsv_batched_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st,
+                               bt->d_desc, bt->count, bt->d_state, bt->d_finished, bt->d_err, int64_t(5000000),
+                               bt->per_claim, int64_t(0));
         HIP_TRY(hipGetLastError());
         return GLTRSV_OK;
     }

@@ -77,8 +77,17 @@ struct SysDesc {
     int32_t S;
     int32_t done_off;   // first per-superstep done counter of this system
     int32_t nchunks;    // chunks of all supersteps
-    int32_t window;     // semi-asynchronous launches: chunks claimed ahead of the completed ones
+    int32_t window;     // semi-asynchronous launches: chunks (or tasks) claimed ahead of the completed ones
     int64_t n;          // rows
+    // wavefront-core systems (semi-asynchronous batches of core-width-64 plans);
+    // ntasks is unused there (the launch runs a global task order)
+    const int32_t *wrow;
+    const int64_t *wptr;
+    const double *wdiag;
+    const uint32_t *wcol;
+    const double *wval;
+    const int64_t *wtask;
+    int32_t ntasks;
 };
 
 // Chunks a semi-asynchronous batched launch lets one system have in flight:
@@ -99,6 +108,12 @@ __global__ void trsv_batched_async(const SysDesc *__restrict__ sys, int32_t coun
                                    uint32_t *finished, int32_t *err, int64_t spin_limit, int32_t per_claim,
                                    int64_t quantum);
 __global__ void fill_unready(unsigned long long *x, int64_t n);
+// the same for systems planned with wavefront cores: global task g is task
+// gtask[g] of system gsys[g] (each system's tasks in their order), run in
+// order by wave g mod W of a co-resident grid
+__global__ void trsv_batched_wave_async(const SysDesc *__restrict__ sys, const int32_t *__restrict__ gsys,
+                                        const int32_t *__restrict__ gtask, int64_t ntasks, int32_t *err,
+                                        int64_t spin_limit);
 
 // Fills the plan's stream (d_word, d_value: lay.pk.slots entries) on the
 // device from A, the schedule order and the host layout; synchronous.

@@ -1127,6 +1127,32 @@ __global__ __launch_bounds__(kBlock) void trsv_batched_async(const SysDesc *__re
     }
 }
 
+// Semi-asynchronous batches of wavefront-core systems.  A task of a wave
+// core is small (a wavefront schedule's task is one row), so claiming tasks
+// with atomics would cost more than running them; instead the host merges
+// the systems' tasks into one global order (each system's own order kept)
+// and wave w runs global tasks
+// w, w + W, ... in order.  Progress as for trsv_wave_async: the earliest
+// unfinished task depends only on earlier tasks of its system, which come
+// earlier in the global order and are finished, and its wave has finished
+// its own earlier tasks (all waves co-resident).
+__global__ __launch_bounds__(kBlock) void trsv_batched_wave_async(const SysDesc *__restrict__ sys,
+                                                                  const int32_t *__restrict__ gsys,
+                                                                  const int32_t *__restrict__ gtask, int64_t ntasks,
+                                                                  int32_t *err, int64_t spin_limit)
+{
+    __shared__ double ring[kWavesPerBlock][kWaveRing];
+    const int64_t waves = int64_t(gridDim.x) * kWavesPerBlock;
+    const int64_t w = int64_t(blockIdx.x) * kWavesPerBlock + int64_t(threadIdx.x >> 6);
+    for (int64_t g = w; g < ntasks; g += waves) {
+        const SysDesc &d = sys[gsys[g]];
+        const int32_t t = gtask[g];
+        if (!wave_task<true>(d.wrow, d.wptr, d.wdiag, d.wcol, d.wval, d.wtask[t], d.wtask[t + 1], d.b, d.x,
+                             ring[threadIdx.x >> 6], err, spin_limit))
+            return;   // a wait ran out: *err is set, the other waves leave too
+    }
+}
+
 // Plain copy of 16-byte elements, grid-stride: the achievable-bandwidth
 // reference and the calibration kernel of the memory-traffic counters.
 __global__ __launch_bounds__(kBlock) void copy_probe(const double2 *__restrict__ src, double2 *__restrict__ dst,

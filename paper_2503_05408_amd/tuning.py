@@ -151,29 +151,32 @@ def _batch_key(plans, plans_async) -> str:
 
 
 def best_batch(plans, b, x, plans_async=None, claims=(1, 2, 4, 8), reps: int = 3, path: str | None = None,
-               stream=None):
+               stream=None, plans_wave=None):
     """The batched launch (gltrsv_batch_*) with the measured-fastest chunk
     claim size and execution form for this set of systems: BSP on `plans`,
     and, when `plans_async` (the same systems, e.g. planned for
-    semi-asynchronous execution) is given, semi-asynchronous on those.  b and
+    semi-asynchronous execution) is given, semi-asynchronous on those, and
+    when `plans_wave` (the same systems with core width 64) is given,
+    semi-asynchronous on wavefront cores ("wave").  b and
     x: lists of device tensors per system, not aliasing each other; x ends
     holding the solutions.  With `path` the choice is read from / stored in
     the JSON table there.  Returns (batch, entry) with entry = {"form",
     "per_claim", "ms"}; the caller closes the batch."""
     import torch
     stream = stream or torch.cuda.current_stream()
-    forms = [("bsp", plans)] + ([("async", plans_async)] if plans_async is not None else [])
-    key = _batch_key(plans, plans_async) if path else None
+    forms = [("bsp", plans)] + ([("async", plans_async)] if plans_async is not None else []) + \
+        ([("wave", plans_wave)] if plans_wave is not None else [])
+    key = _batch_key(plans, (plans_async or []) + (plans_wave or [])) if path else None
     if path:
         hit = load_table(path).get(key)
         if isinstance(hit, dict) and hit.get("form") in dict(forms) and int(hit.get("per_claim", 0)) >= 1:
             bt = B.Batch(dict(forms)[hit["form"]], per_claim=int(hit["per_claim"]), use_graph=True,
-                         async_exec=hit["form"] == "async")
+                         async_exec=hit["form"] != "bsp")
             return bt, hit
     best, times = None, {}
     for form, ps in forms:
-        for pc in claims:
-            bt = B.Batch(ps, per_claim=pc, use_graph=True, async_exec=form == "async")
+        for pc in (claims if form != "wave" else (1,)):   # wave batches run a static task order
+            bt = B.Batch(ps, per_claim=pc, use_graph=True, async_exec=form != "bsp")
             bt.solve(b, x, stream)
             stream.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -135,3 +135,38 @@ def test_shuffled_system_order_and_grid_sizes(plans, async_exec):
             assert bt.status() == 0
         for j, i in enumerate(order):
             assert oracle.same_bits(xd[j].cpu().numpy(), wants[i]), (grid, ms[i].name)
+
+
+@pytest.mark.parametrize("per_claim", [1, 3])
+@pytest.mark.parametrize("grid", [1, 5, 0])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_wave_core_async_batch(per_claim, grid, use_graph):
+    # every plan with core width 64: the batch runs on wavefront cores (tasks
+    # claimed in order per system); every x is the oracle's bits, on grids of
+    # one workgroup up to the default, with and without graph replay
+    import torch
+    ms, _ = systems()
+    ps = [B.Plan(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT if i % 2 else B.SCHED_GROWLOCAL,
+                                   core_width=64, k=256)) for i, m in enumerate(ms)]
+    bs = [gen.rhs_uniform(m.n, 300 + i) for i, m in enumerate(ms)]
+    wants = [oracle.solve(m, b) for m, b in zip(ms, bs)]
+    bd = [torch.from_numpy(b).cuda() for b in bs]
+    with B.Batch(ps, per_claim=per_claim, use_graph=use_graph, grid_blocks=grid, async_exec=True) as bt:
+        for rep in range(2):
+            xd = [torch.full((m.n,), float("nan"), dtype=torch.float64, device="cuda") for m in ms]
+            bt.solve(bd, xd)
+            torch.cuda.synchronize()
+            assert bt.status() == 0
+            for i, m in enumerate(ms):
+                assert oracle.same_bits(xd[i].cpu().numpy(), wants[i]), (rep, m.name)
+    # a mix of core widths falls back to lane cores (the stream every plan keeps)
+    mixed = ps[:3] + [B.Plan(ms[3], B.gpu_opts())]
+    xd = [torch.full((m.n,), float("nan"), dtype=torch.float64, device="cuda") for m in ms[:4]]
+    with B.Batch(mixed, async_exec=True) as bt:
+        bt.solve(bd[:4], xd)
+        torch.cuda.synchronize()
+        assert bt.status() == 0
+    for i in range(4):
+        assert oracle.same_bits(xd[i].cpu().numpy(), wants[i])
+    for p in ps + mixed[3:]:
+        p.close()
