@@ -541,14 +541,15 @@ def bench_paper(args):
                 if f == "GL persistent":
                     inf = plan.info()
                     ratios.append(inf["wavefronts"] / inf["supersteps"])
-            kept.append((m, plans.pop(id(o_auto_a)), plans.pop(id(o_auto)), want))
+            kept.append((m, plans.pop(id(o_auto_a)), plans.pop(id(o_auto)), want, plans.pop(id(o_wave))))
             for plan in plans.values():
                 plan.close()
         # every instance of the set in one launch: throughput against the serial solves one after another
         batched = {}
         bs = [torch.ones(k[0].n, dtype=torch.float64, device="cuda") for k in kept]
         xs = [torch.empty_like(v) for v in bs]
-        for label, idx, async_exec in (("AUTO async batch", 1, True), ("AUTO BSP batch", 2, False)):
+        for label, idx, async_exec in (("AUTO async batch", 1, True), ("AUTO BSP batch", 2, False),
+                                       ("wavefront wave-core async batch", 4, True)):
             with B.Batch([k[idx] for k in kept], per_claim=2, use_graph=False, async_exec=async_exec) as bt:
                 t = timed(lambda: bt.solve(bs, xs), args.steps)
                 ok = bt.status() == 0 and all(oracle.same_bits(x.cpu().numpy(), k[3]) for x, k in zip(xs, kept))
@@ -557,6 +558,7 @@ def bench_paper(args):
         for k in kept:
             k[1].close()
             k[2].close()
+            k[4].close()
         row = {"set": f"{fam} p={p}" + (f" B={Bw:g}" if Bw else ""), "instances": args.instances,
                "exact": bool(all_exact), "wavefronts_per_superstep_GL": float(np.mean(ratios)),
                "geomean_speedup_vs_serial": {f: float(np.exp(np.mean(np.log(v)))) for f, v in logs.items()},
