@@ -1,7 +1,7 @@
 """Parity at the paper's sizes: the Erdos-Renyi and narrow-band sets of
 Sec. 6.2 (Tables A.4, A.5; n = 1e5, ten seeds each) solved singly and as one
-batch, and the n = 1e7 single-system workload, every x bit-identical to the
-oracle's.  Also records supersteps against wavefronts (the quantity of
+batch (lane and wavefront cores), and the n = 1e7 workloads, every x
+bit-identical to the oracle's.  Also records supersteps against wavefronts (the quantity of
 Table 7.2) for the GPU schedules."""
 import numpy as np
 import pytest
@@ -46,6 +46,22 @@ def test_paper_set_single_and_batched(fam):
     for m, x, want in zip(ms, xd, wants):
         assert oracle.same_bits(x.cpu().numpy(), want), m.name
     for p in plans:
+        p.close()
+    # wavefront cores on the wavefront schedule: each system alone (semi-async) and all in one batch
+    wplans = [B.Plan(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT, core_width=64)) for m in ms]
+    for m, p, want, b in zip(ms, wplans, wants, bd):
+        x = p.solve_async(b)
+        torch.cuda.synchronize()
+        assert p.device_status() == 0
+        assert oracle.same_bits(x.cpu().numpy(), want), ("wave", m.name)
+    xd = [torch.full_like(b, float("nan")) for b in bd]
+    with B.Batch(wplans, async_exec=True) as bt:
+        bt.solve(bd, xd)
+        torch.cuda.synchronize()
+        assert bt.status() == 0
+    for m, x, want in zip(ms, xd, wants):
+        assert oracle.same_bits(x.cpu().numpy(), want), ("wave batch", m.name)
+    for p in wplans:
         p.close()
 
 
@@ -93,11 +109,19 @@ def test_full_size_grids(maker):
             torch.cuda.synchronize()
             assert p.device_status() == 0
             assert oracle.same_bits(x.cpu().numpy(), want), (m.name, solve.__name__)
+    with B.Plan(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT, core_width=64)) as p:
+        for solve in (p.solve, p.solve_async):   # wavefront cores at full size
+            x.fill_(float("nan"))
+            solve(b, x)
+            torch.cuda.synchronize()
+            assert p.device_status() == 0
+            assert oracle.same_bits(x.cpu().numpy(), want), (m.name, "wave", solve.__name__)
 
 
 def test_full_size_batch_mix():
-    """The 64-system batching workload (9.5e6 rows) in one launch, BSP and
-    semi-asynchronous, every system against the oracle."""
+    """The 64-system batching workload (9.5e6 rows) in one launch, BSP,
+    semi-asynchronous and semi-asynchronous on wavefront cores, every system
+    against the oracle."""
     import torch
     ms = gen.batch_mix()
     plans = [B.Plan(m, B.gpu_opts(schedule_kind=B.SCHED_AUTO)) for m in ms]
@@ -112,4 +136,14 @@ def test_full_size_batch_mix():
         for m, x, w in zip(ms, xs, wants):
             assert oracle.same_bits(x.cpu().numpy(), w), (m.name, async_exec)
     for p in plans:
+        p.close()
+    wplans = [B.Plan(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT, core_width=64)) for m in ms]
+    xs = [torch.full_like(b, float("nan")) for b in bs]
+    with B.Batch(wplans, async_exec=True) as bt:
+        bt.solve(bs, xs)
+        torch.cuda.synchronize()
+        assert bt.status() == 0
+    for m, x, w in zip(ms, xs, wants):
+        assert oracle.same_bits(x.cpu().numpy(), w), (m.name, "wave")
+    for p in wplans:
         p.close()
