@@ -170,3 +170,24 @@ def test_wave_core_async_batch(per_claim, grid, use_graph):
         assert oracle.same_bits(xd[i].cpu().numpy(), wants[i])
     for p in ps + mixed[3:]:
         p.close()
+
+
+def test_wave_core_batch_mixes_forward_and_backward_systems():
+    import torch
+    lows = [gen.erdos_renyi(2500, 0.004, gen.SEED_BASE + 70), gen.narrow_band(2000, 0.1, 12, gen.SEED_BASE + 71)]
+    ups = [gen.upper_of(m) for m in lows]
+    ms = lows + ups
+    ps = [B.Plan(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT, core_width=64,
+                                   triangle=B.UPPER if m.meta.get("upper") else B.LOWER)) for m in ms]
+    bs = [gen.rhs_uniform(m.n, 40 + i) for i, m in enumerate(ms)]
+    wants = [(oracle.solve_upper if m.meta.get("upper") else oracle.solve)(m, b) for m, b in zip(ms, bs)]
+    bd = [torch.from_numpy(b).cuda() for b in bs]
+    xd = [torch.full_like(v, float("nan")) for v in bd]
+    with B.Batch(ps, async_exec=True) as bt:
+        bt.solve(bd, xd)
+        torch.cuda.synchronize()
+        assert bt.status() == 0
+    for m, x, w in zip(ms, xd, wants):
+        assert oracle.same_bits(x.cpu().numpy(), w), m.name
+    for p in ps:
+        p.close()
