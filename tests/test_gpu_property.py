@@ -36,7 +36,7 @@ def cases(draw):
     return (gen.upper_of(m) if upper else m), opts, draw(st.integers(0, 1000))
 
 
-@settings(max_examples=400, deadline=None, suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@settings(max_examples=2000, deadline=None, suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
 @given(cases())
 def test_every_form_matches_the_oracle(case):
     import torch
