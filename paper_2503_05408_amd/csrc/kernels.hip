@@ -333,12 +333,13 @@ __global__ __launch_bounds__(kBlock) void trsv_superstep_unordered(
 
 // Barrier over all workgroups of the grid, in two halves so that work that
 // does not depend on other workgroups can run while waiting.  Arrivals are
-// counted in two levels: workgroups of a group of kGroup count on the group's
-// word; the last of each group counts on the top word; the last of those
-// advances the generation word that every workgroup waits on.  No word sees
-// more than max(kGroup, groups) arrivals, and every word sits on its own
-// 128-byte line.  Each last arrival resets the word it completed before
-// moving up, so the words are ready for the next barrier.
+// counted in up to two levels: workgroups of a group (the whole grid up to
+// kFlatMax workgroups, else kGroup) count on the group's word; with several
+// groups the last of each counts on the top word;
+// the last arrival overall advances the generation word that every
+// workgroup waits on.  Every word sits on its own 128-byte line.  Each last
+// arrival resets the word it completed before moving up, so the words are
+// ready for the next barrier.
 
 struct BarrierTicket {
     uint32_t gen;
@@ -355,9 +356,10 @@ __device__ __forceinline__ BarrierTicket barrier_arrive(uint32_t *bar)
     __shared__ int32_t s_last;
     if (threadIdx.x == 0) {
         const uint32_t G = gridDim.x;
-        const uint32_t grp = blockIdx.x / kGroup;
-        const uint32_t groups = (G + kGroup - 1) / kGroup;
-        const uint32_t gsize = min(uint32_t(kGroup), G - grp * kGroup);
+        const uint32_t gw = G <= uint32_t(kFlatMax) ? G : uint32_t(kGroup);   // group width
+        const uint32_t grp = blockIdx.x / gw;
+        const uint32_t groups = (G + gw - 1) / gw;
+        const uint32_t gsize = min(gw, G - grp * gw);
         uint32_t *gen = bar + kBarGen;
         uint32_t *top = bar + kBarTop;
         uint32_t *cnt = bar + kBarGroups + 32 * grp;
@@ -366,9 +368,13 @@ __device__ __forceinline__ BarrierTicket barrier_arrive(uint32_t *bar)
         const uint32_t old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == gsize - 1) {
             __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t old2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (old2 == groups - 1) {
-                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bool top_last = true;   // a single group needs no top level
+            if (groups > 1) {
+                const uint32_t old2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                top_last = old2 == groups - 1;
+                if (top_last) __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (top_last) {
                 __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 last = true;
             }
