@@ -58,7 +58,7 @@ int check_opts(const gltrsv_plan_opts *o)
         if (!(o->accept > 0.0)) return set_error(GLTRSV_EINVAL, "accept must be > 0");
     }
     if (o->block_size != 0 && o->block_size != dev::kBlock)
-        return set_error(GLTRSV_ENOTSUP, "block_size must be 0 or 256 in this build");
+        return set_error(GLTRSV_ENOTSUP, "block_size must be 0 or 256: the kernels are compiled for 256-thread workgroups");
     if (o->grid_blocks < 0) return set_error(GLTRSV_EINVAL, "grid_blocks must be >= 0");
     if (o->analysis_threads < 0 || o->analysis_threads > 64)
         return set_error(GLTRSV_EINVAL, "analysis_threads must be in 0..64");
