@@ -1,6 +1,8 @@
 """C ABI layout (CPU): every struct of include/gltrsv.h has the same size and
 the same field offsets in C (compiled here with gcc) as in the ctypes
-binding, so the binding cannot drift from the header."""
+binding, and every constant the binding mirrors (error codes, schedule kinds,
+triangles, packing modes, execution forms) has the header's value, so the
+binding cannot drift from the header."""
 import os
 import shutil
 import subprocess
@@ -18,6 +20,14 @@ STRUCTS = {
     "gltrsv_server_opts": B.ServerOpts,
     "gltrsv_server_stats": B.ServerStats,
 }
+# header macro -> the binding's value
+CONSTANTS = {
+    "GLTRSV_OK": B.GLTRSV_OK,
+    **{"GLTRSV_" + name: code for code, name in B.ERRORS.items()},
+    **{f"GLTRSV_{n}": getattr(B, n) for n in (
+        "SCHED_GROWLOCAL", "SCHED_WAVEFRONT", "SCHED_AUTO", "SCHED_GIVEN", "LOWER", "UPPER",
+        "PACK_AUTO", "PACK_HOST", "PACK_DEVICE", "EXEC_PERSISTENT", "EXEC_PLAIN", "EXEC_ASYNC")},
+}
 
 
 @pytest.fixture(scope="module")
@@ -29,6 +39,8 @@ def c_layout(tmp_path_factory):
         lines.append(f'    printf("{name} size %zu\\n", sizeof({name}));')
         for field, _ in cls._fields_:
             lines.append(f'    printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    for macro in CONSTANTS:
+        lines.append(f'    printf("const {macro} %d\\n", (int)({macro}));')
     lines += ["    return 0;", "}"]
     d = tmp_path_factory.mktemp("abi")
     src, exe = d / "abi.c", d / "abi"
@@ -51,3 +63,10 @@ def test_struct_matches_the_header(c_layout, name):
     assert ctypes.sizeof(cls) == c_layout[(name, "size")], name
     for field, _ in cls._fields_:
         assert getattr(cls, field).offset == c_layout[(name, field)], (name, field)
+
+
+def test_constants_match_the_header(c_layout):
+    assert len(B.ERRORS) == 11
+    for macro, value in CONSTANTS.items():
+        assert c_layout[("const", macro)] == value, macro
+    assert B.EXEC_NAMES[B.EXEC_PERSISTENT] == "persistent" and B.EXEC_NAMES[B.EXEC_ASYNC] == "async"
