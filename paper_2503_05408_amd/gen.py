@@ -107,19 +107,17 @@ def paper_values(rng: np.random.Generator, m_off: int, n: int):
 
 def _tri_index_to_rc(pos: np.ndarray):
     """Map a flat index over the strict lower triangle (row-major:
-    pos = i(i-1)/2 + j, 0 <= j < i) back to (i, j)."""
-    pos = pos.astype(np.int64)
-    i = np.floor((1.0 + np.sqrt(1.0 + 8.0 * pos.astype(np.float64))) / 2.0).astype(np.int64)
-    # exact integer correction of the floating-point estimate
-    for _ in range(3):
-        lo = i * (i - 1) // 2
-        too_big = lo > pos
-        i = np.where(too_big, i - 1, i)
-        hi = i * (i + 1) // 2
-        too_small = hi <= pos
-        i = np.where(too_small, i + 1, i)
-    lo = i * (i - 1) // 2
-    j = pos - lo
+    pos = i(i-1)/2 + j, 0 <= j < i) back to (i, j): i is the last row whose
+    first index i(i-1)/2 does not exceed pos (an exact integer search)."""
+    pos = np.asarray(pos, dtype=np.int64)
+    if pos.size == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    top = int(pos.max())
+    imax = int(math.isqrt(2 * top)) + 2          # i(i-1)/2 > top for i = imax
+    r = np.arange(imax + 1, dtype=np.int64)
+    starts = r * (r - 1) // 2
+    i = np.searchsorted(starts, pos, side="right").astype(np.int64) - 1
+    j = pos - starts[i]
     assert ((j >= 0) & (j < i)).all()
     return i, j
 

@@ -65,14 +65,31 @@ def test_paper_set_single_and_batched(fam):
         p.close()
 
 
+def _schedule_key(plan):
+    import hashlib
+    h = hashlib.sha256()
+    for a in plan.schedule():          # core, superstep, perm per row
+        h.update(np.ascontiguousarray(a, dtype="<i4").tobytes())
+    return h.hexdigest()
+
+
 def test_full_size_single_system():
-    """The n = 1e7 workload of the benchmark, persistent and plain, against
-    the full oracle solve."""
+    """The n = 1e7 workload of the benchmark: the plan's GrowLocal schedule
+    and Sec. 5 order equal the oracle's (the stored key of
+    tests/golden/schedule_keys.json), and the persistent, plain,
+    semi-asynchronous and several-column solves equal the full oracle solve."""
+    import json
+    import os
     import torch
     n = 10_000_000
     m = gen.erdos_renyi(n, 20.0 / (n - 1), gen.SEED_BASE + 200)
     want = oracle.solve(m, np.ones(n))
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "schedule_keys.json")) as f:
+        golden = json.load(f)["bench_er_n1e7"]
+    assert (golden["n"], golden["nnz"]) == (m.n, m.nnz)
     with B.Plan(m, B.gpu_opts()) as p:
+        assert p.info()["supersteps"] == golden["S"]
+        assert _schedule_key(p) == golden["key"]
         b = torch.ones(n, dtype=torch.float64, device="cuda")
         x = torch.full_like(b, float("nan"))
         p.solve(b, x)
