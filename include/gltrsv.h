@@ -120,12 +120,20 @@ typedef struct gltrsv_plan_opts {
                                multiple of 64); 0 = library default           */
     int32_t grid_blocks;    /* workgroups of the persistent kernel;
                                0 = all that can be co-resident (<= 2048)      */
-    int32_t cooperative;    /* 1: launch the persistent kernel with
-                               hipLaunchCooperativeKernel (co-residency
-                               guaranteed by the runtime); 0: plain launch of
-                               an occupancy-sized grid (lower launch cost; a
-                               workgroup kept from starting by other work on
-                               the device ends the solve with ETIMEDOUT)     */
+    int32_t cooperative;    /* 1: launch the kernels whose workgroups wait
+                               for each other (gltrsv_solve, the wave-core
+                               gltrsv_solve_async) with
+                               hipLaunchCooperativeKernel, which checks the
+                               grid against the co-resident capacity (about
+                               20-40 us more per launch).  0 (default): a
+                               plain launch of the same grid.  Neither keeps
+                               kernels on other streams from delaying some
+                               workgroups (measured on MI355X); the
+                               persistent kernels do not need that (their
+                               waves claim and steal work, see
+                               gltrsv_plan_set_steal_wait) and the
+                               lane-core semi-asynchronous kernels claim
+                               chunks in order                                */
     int32_t analysis_threads; /* host threads of the GrowLocal analysis: the
                                iterations of one superstep (Algorithm 3.1)
                                start from the same state and run
@@ -269,8 +277,12 @@ int gltrsv_plan_schedule(const gltrsv_plan *plan, int32_t *core, int32_t *supers
 int gltrsv_plan_destroy(gltrsv_plan *plan);
 
 /* ----------------------------------------------------------------- solves */
-/* Persistent solve: one cooperative launch runs every superstep; the barrier
- * between supersteps (Def. 2.1) is a device-scope counter.  b and x are
+/* Persistent solve: one launch runs every superstep; between supersteps
+ * (Def. 2.1) the waves wait for a device-scope count of the superstep's
+ * completed chunks (or wavefront-core tasks).  Each chunk is claimed once
+ * per solve; a workgroup that has waited long for a superstep runs its
+ * unclaimed chunks itself (gltrsv_plan_set_steal_wait), so the solve needs
+ * no co-residency and other work on the device only delays it.  b and x are
  * device arrays in the original numbering; b may alias x (in-place solve).
  * Reading b and writing x fuse the permutation of Sec. 5. */
 int gltrsv_solve(gltrsv_plan *plan, const double *b, double *x, void *stream);
@@ -300,13 +312,37 @@ int gltrsv_plan_create_with_schedule(const gltrsv_csr *A, const gltrsv_plan_opts
  * 1 = spin limit hit).  Synchronises the plan's last stream. */
 int gltrsv_plan_device_status(gltrsv_plan *plan, int32_t *status);
 
-/* Watchdog of the plan's device-side waits (the persistent kernel's barrier,
- * the semi-asynchronous readiness waits): the number of polls a wait may take
- * before the solve gives up and sets the error word that
- * gltrsv_plan_device_status reports (default 5,000,000, about 5 s).  A small
+/* Watchdog of the plan's device-side waits (the persistent kernel's
+ * superstep waits, the semi-asynchronous readiness waits): the number of
+ * polls a wait may take before the solve gives up and sets the error word
+ * that gltrsv_plan_device_status reports (default 5,000,000; measured on
+ * MI355X a poll takes 0.14 us or more, so at least 0.7 s).  A small
  * value forces that path from the host, e.g. to test error handling: every
  * wave still leaves the kernel normally.  polls >= 1, else EINVAL. */
 int gltrsv_plan_set_spin_limit(gltrsv_plan *plan, int64_t polls);
+
+/* How long a workgroup of the persistent solve (gltrsv_solve, lane and
+ * wavefront cores) waits for a superstep to complete before it robs the
+ * workgroups of the launch that have not started yet: it marks them robbed
+ * and claims and runs their chunks (or tasks) of that superstep, and a
+ * robbed workgroup claims its own before running them once it starts.  So
+ * the solve advances whenever any workgroup runs, and workgroups kept from
+ * starting by other work on the device cannot stall it; with every
+ * workgroup resident nothing is claimed.  Default 200 us; 0 robs at the
+ * first wait.  The result is the same bits either way.  microseconds in
+ * 0..2^40, else EINVAL. */
+int gltrsv_plan_set_steal_wait(gltrsv_plan *plan, int64_t microseconds);
+
+/* Diagnostic: every 7th workgroup (index 3 mod 7) of the persistent solve
+ * (gltrsv_solve) and of the semi-asynchronous solves (gltrsv_solve_async,
+ * gltrsv_solve_multi) waits `microseconds` before it starts, so the robbing
+ * of workgroups that have not started runs without other work on the
+ * device (for tests; 0 = off, the default).  The semi-asynchronous kernels
+ * run a static order; a wave that has waited 200 us for values while a
+ * workgroup of its launch has not started runs that workgroup's earliest
+ * unrun chunk (or task) itself, then its own again (a chunk run twice stores
+ * the same bits).  microseconds in 0..1e7, else EINVAL. */
+int gltrsv_plan_set_start_delay(gltrsv_plan *plan, int64_t microseconds);
 
 /* ---------------------------------------------------------------- batches */
 /* Many independent systems in one persistent launch (the schedules compose:
@@ -333,8 +369,11 @@ typedef struct gltrsv_batch_opts {
                               wavefront cores: their tasks in one global
                               order (supersteps of all systems by relative
                               depth s / S, each system's order kept), wave w
-                              taking every W-th, on a co-resident grid;
-                              per_claim is then unused                        */
+                              taking every W-th; a wave that waits long while
+                              a workgroup of the launch has not started runs
+                              that workgroup's earliest task in its place, so
+                              no co-residency is needed; per_claim is then
+                              unused                                          */
 } gltrsv_batch_opts;
 
 void gltrsv_default_batch_opts(gltrsv_batch_opts *opts);
@@ -395,7 +434,9 @@ int gltrsv_server_create(const gltrsv_server_opts *opts, gltrsv_server **out);
 
 /* Queues the solve b -> x with `plan` (device pointers, original numbering;
  * b must be fully written before the call and b, x and the plan must stay
- * valid until the ticket completes).  Returns GLTRSV_EAGAIN when the request
+ * valid until gltrsv_server_poll has reported the ticket or
+ * gltrsv_server_cancel has returned for it; the server reads nothing of the
+ * plan after that).  Returns GLTRSV_EAGAIN when the request
  * would exceed the in-flight budget (retry after completions), ERANGE if it
  * can never fit.  Thread-safe. */
 int gltrsv_server_submit(gltrsv_server *server, gltrsv_plan *plan, const double *b, double *x, uint64_t *ticket);
@@ -409,12 +450,15 @@ int gltrsv_server_poll(gltrsv_server *server, uint64_t *tickets, int64_t *done_n
 int gltrsv_server_get_stats(gltrsv_server *server, gltrsv_server_stats *out);
 
 /* Withdraws a request that has not completed.  A queued request is removed
- * at once; one already on the device is dropped at the next quantum boundary
- * (the worker stops scheduling its chunks; chunks already claimed finish).
- * Either way the ticket is never reported by gltrsv_server_poll, its budget
- * is released, and its x is left partly written (undefined).  GLTRSV_ENOENT
- * if no pending request has this ticket (unknown, completed or cancelled).
- * Thread-safe. */
+ * at once; for one already on the device the call blocks until the worker
+ * has dropped it at the next quantum boundary (the worker stops scheduling
+ * its chunks; chunks already claimed finish first).  Either way, when the
+ * call returns the device no longer touches the request's b, x or plan (the
+ * caller may free them), the ticket is never reported by gltrsv_server_poll,
+ * its budget is released, and its x is left partly written (undefined).
+ * GLTRSV_ENOENT if no pending request has this ticket (unknown, completed or
+ * cancelled).  Thread-safe; must not be called from a thread that the
+ * server's progress depends on. */
 int gltrsv_server_cancel(gltrsv_server *server, uint64_t ticket);
 
 /* Monotonic host clock used for completion times, in nanoseconds. */

@@ -110,6 +110,8 @@ SIGNATURES = {
     "gltrsv_solve_async": ([P, P, P, P], i32),
     "gltrsv_solve_multi": ([P, P, P, i32, P], i32),
     "gltrsv_plan_set_spin_limit": ([P, i64], i32),
+    "gltrsv_plan_set_steal_wait": ([P, i64], i32),
+    "gltrsv_plan_set_start_delay": ([P, i64], i32),
     "gltrsv_solve_auto": ([P, P, P, P], i32),
     "gltrsv_solve_unordered": ([P, P, P, P], i32),
     "gltrsv_plan_set_exec": ([P, i32], i32),
@@ -386,6 +388,17 @@ class Plan:
                                        _stream_ptr(stream), us, ctypes.byref(best)), "gltrsv_plan_tune")
         return {"form": EXEC_NAMES[best.value], "us": {EXEC_NAMES[f]: us[f] for f in range(3)}}
 
+    def set_steal_wait(self, microseconds: int):
+        """Superstep wait after which the persistent solve robs workgroups
+        that have not started (0 = at the first wait)."""
+        _check(load().gltrsv_plan_set_steal_wait(self._p, int(microseconds)), "gltrsv_plan_set_steal_wait")
+
+    def set_start_delay(self, microseconds: int):
+        """Diagnostic: every 7th workgroup of the persistent solve starts this
+        much later (exercises the robbing of workgroups that have not
+        started)."""
+        _check(load().gltrsv_plan_set_start_delay(self._p, int(microseconds)), "gltrsv_plan_set_start_delay")
+
     def set_spin_limit(self, polls: int):
         """Polls a device-side wait may take before the solve reports a time-out."""
         _check(load().gltrsv_plan_set_spin_limit(self._p, int(polls)), "gltrsv_plan_set_spin_limit")
@@ -403,14 +416,16 @@ class Plan:
         """Several right-hand sides: b and x are (n, nrhs) row-major CUDA
         float64 tensors; column r of x solves column r of b."""
         import torch
-        if b.dim() != 2 or b.shape[0] != self.n or not b.is_contiguous() or b.dtype != torch.float64:
-            raise ValueError("b must be a contiguous (n, nrhs) float64 tensor")
+        if not isinstance(b, torch.Tensor) or b.dim() != 2 or b.shape[0] != self.n:
+            raise ValueError("b must be an (n, nrhs) tensor")
         if x is None:
             x = torch.empty_like(b)
-        if x.shape != b.shape or not x.is_contiguous():
-            raise ValueError("x must match b")
-        _check(load().gltrsv_solve_multi(self._p, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
-                                         int(b.shape[1]), _stream_ptr(stream)), "gltrsv_solve_multi")
+        if not isinstance(x, torch.Tensor) or x.shape != b.shape:
+            raise ValueError("x must have b's shape")
+        nrhs = int(b.shape[1])
+        bp = _dev_ptr(b, self.n * nrhs)
+        xp = _dev_ptr(x, self.n * nrhs)
+        _check(load().gltrsv_solve_multi(self._p, bp, xp, nrhs, _stream_ptr(stream)), "gltrsv_solve_multi")
         return x
 
     def solve_plain(self, b, x=None, stream=None):
@@ -543,6 +558,9 @@ class Server:
         ptr = ctypes.c_void_p()
         _check(load().gltrsv_server_create(ctypes.byref(o), ctypes.byref(ptr)), "gltrsv_server_create")
         self._p = ptr
+        # ticket -> (plan, b, x): the device may use them until the ticket is
+        # polled or cancelled, so the binding keeps them alive until then
+        self._held = {}
 
     def submit(self, plan, b, x):
         """Returns a ticket, or None when the in-flight budget is full (EAGAIN)."""
@@ -552,6 +570,7 @@ class Server:
         if rc == GLTRSV_EAGAIN:
             return None
         _check(rc, "gltrsv_server_submit")
+        self._held[t.value] = (plan, b, x)
         return t.value
 
     def poll(self, max_items: int = 4096):
@@ -559,15 +578,20 @@ class Server:
         ns = (ctypes.c_int64 * max_items)()
         k = ctypes.c_int32(0)
         _check(load().gltrsv_server_poll(self._p, tk, ns, max_items, ctypes.byref(k)), "gltrsv_server_poll")
-        return [(tk[i], ns[i]) for i in range(k.value)]
+        out = [(tk[i], ns[i]) for i in range(k.value)]
+        for t, _ in out:
+            self._held.pop(t, None)
+        return out
 
     def cancel(self, ticket: int) -> bool:
         """Withdraws a pending request (never reported by poll afterwards);
-        False if no pending request has this ticket."""
+        returns once the device no longer uses its b, x and plan.  False if
+        no pending request has this ticket."""
         rc = load().gltrsv_server_cancel(self._p, ctypes.c_uint64(int(ticket)))
         if rc == -11:
             return False
         _check(rc, "gltrsv_server_cancel")
+        self._held.pop(int(ticket), None)
         return True
 
     def stats(self) -> dict:

@@ -33,6 +33,36 @@ int gltrsv::set_error(int code, const std::string &msg)
 
 namespace {
 
+// True if the byte ranges [a, a + na) and [b, b + nb) share a byte.
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return na && nb && pa < pb + nb && pb < pa + na;
+}
+
+// Launches a kernel whose workgroups wait for each other.  cooperative:
+// hipLaunchCooperativeKernel (the runtime checks the grid against the
+// device's co-resident capacity); otherwise a plain launch of the same
+// occupancy-sized grid.  Measured on MI355X, neither keeps ordinary kernels
+// on other streams from delaying some of the grid's workgroups, which is why
+// the persistent kernels claim and steal their work (see trsv_persistent).
+int launch_coresident(const void *kernel, dim3 grid, void **args, hipStream_t st, bool cooperative)
+{
+    if (cooperative) {
+        HIP_TRY(hipLaunchCooperativeKernel(kernel, grid, dim3(dev::kBlock), args, 0, st));
+    } else {
+        HIP_TRY(hipLaunchKernel(kernel, grid, dim3(dev::kBlock), args, 0, st));
+    }
+    return GLTRSV_OK;
+}
+
+// Start ticket of a plan's semi-asynchronous kernel `which` (0 lane cores,
+// 1 several right-hand sides, 2 wave cores).
+unsigned long long *async_ticket(gltrsv_plan *p, int which)
+{
+    return reinterpret_cast<unsigned long long *>(p->d_bar + dev::kBarAsyncTicket + 32 * which);
+}
+
 CsrView view_of(const gltrsv_csr *A)
 {
     CsrView v;
@@ -295,6 +325,11 @@ struct gltrsv_batch {
     int32_t *d_gsys = nullptr;         // wave cores: system of each global task
     int32_t *d_gtask = nullptr;        // ... and its task index in that system
     int64_t gtasks = 0;
+    // wave cores: robbing of workgroups that have not started (start ticket,
+    // kMaxGrid alive words, 4 kMaxGrid robbed-prefix words)
+    unsigned long long *d_wticket = nullptr;
+    uint32_t *d_walive = nullptr;
+    unsigned long long *d_wvnext = nullptr;
 };
 
 extern "C" {
@@ -392,6 +427,11 @@ int gltrsv_plan_destroy(gltrsv_plan *p)
     (void)hipFree(p->d_chunk_len);
     (void)hipFree(p->d_super_chunk);
     (void)hipFree(p->d_bar);
+    (void)hipFree(p->d_claim);
+    (void)hipFree(p->d_alive);
+    (void)hipFree(p->d_aalive);
+    (void)hipFree(p->d_vnext);
+    (void)hipFree(p->d_wclaim);
     (void)hipFree(p->d_err);
     (void)hipFree(p->d_trace);
     (void)hipFree(p->d_bcopy);
@@ -522,7 +562,13 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
     {
         std::vector<uint32_t> bar(dev::kBarWords, 0u);
         std::vector<int32_t> err(1, 0);
-        if ((rc = upload(&p->d_bar, bar, &bytes)) || (rc = upload(&p->d_err, err, &bytes))) {
+        std::vector<uint32_t> claim(size_t(std::max<int64_t>(1, p->chunks)), 0u);
+        std::vector<uint32_t> alive(size_t(dev::kMaxGrid), 0u);
+        std::vector<uint32_t> aalive(size_t(3 * dev::kMaxGrid), 0u);
+        std::vector<unsigned long long> vnext(size_t(3 * dev::kMaxGrid * dev::kWavesPerBlock), 0ull);
+        if ((rc = upload(&p->d_bar, bar, &bytes)) || (rc = upload(&p->d_err, err, &bytes)) ||
+            (rc = upload(&p->d_claim, claim, &bytes)) || (rc = upload(&p->d_alive, alive, &bytes)) ||
+            (rc = upload(&p->d_aalive, aalive, &bytes)) || (rc = upload(&p->d_vnext, vnext, &bytes))) {
             gltrsv_plan_destroy(p);
             return rc;
         }
@@ -532,9 +578,16 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         return rc;
     }
     p->core_width = opts->core_width == 64 ? 64 : 1;
-    if (p->core_width == 64 && (rc = upload_wave(p, A, &bytes))) {
-        gltrsv_plan_destroy(p);
-        return rc;
+    if (p->core_width == 64) {
+        if ((rc = upload_wave(p, A, &bytes))) {
+            gltrsv_plan_destroy(p);
+            return rc;
+        }
+        std::vector<uint32_t> wclaim(size_t(std::max(1, p->wsuper_host.back())), 0u);
+        if ((rc = upload(&p->d_wclaim, wclaim, &bytes))) {
+            gltrsv_plan_destroy(p);
+            return rc;
+        }
     }
     p->device_bytes = bytes;
 
@@ -546,7 +599,7 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         gltrsv_plan_destroy(p);
         return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
     }
-    int grid = std::min(per_cu * cus, dev::kGroup * 128);
+    int grid = std::min(per_cu * cus, dev::kMaxGrid);
     if (opts->grid_blocks > 0) grid = std::min(grid, opts->grid_blocks);
     p->cooperative = opts->cooperative != 0;
     // no more workgroups than the widest superstep can use
@@ -586,7 +639,7 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         int64_t most = 1;
         for (int32_t q = 0; q < p->S; q++)
             most = std::max<int64_t>(most, p->wsuper_host[size_t(q) + 1] - p->wsuper_host[size_t(q)]);
-        int64_t gw = std::min<int64_t>(int64_t(per_cu_w) * cus, dev::kGroup * 128);
+        int64_t gw = std::min<int64_t>(int64_t(per_cu_w) * cus, dev::kMaxGrid);
         if (opts->grid_blocks > 0) gw = std::min<int64_t>(gw, opts->grid_blocks);
         p->grid_wave = int(std::max<int64_t>(1, std::min<int64_t>(gw, (most + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
         // semi-asynchronous: at least two workgroups per CU, more for large
@@ -678,7 +731,8 @@ int gltrsv_solve_plain(gltrsv_plan *p, const double *b, double *x, void *stream)
             if (blocks == 0) continue;
             hipLaunchKernelGGL(dev::trsv_wave, dim3(blocks), dim3(dev::kBlock), 0, st, p->d_wrow, p->d_wptr,
                                p->d_wdiag, p->d_wcol, p->d_wval, p->d_wtask, p->d_wsuper, s, s + 1, b, x,
-                               p->d_bar, p->d_err, p->spin_limit);
+                               p->d_bar, static_cast<uint32_t *>(nullptr), static_cast<uint32_t *>(nullptr),
+                               p->d_err, p->spin_limit, int64_t(0), int64_t(0));
         }
         HIP_TRY(hipGetLastError());
         p->last_stream = st;
@@ -702,11 +756,24 @@ int gltrsv_solve(gltrsv_plan *p, const double *b, double *x, void *stream)
     if (p->n == 0) return GLTRSV_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p->core_width == 64) {
-        // all supersteps in one launch; the grid fits the co-resident capacity
-        hipLaunchKernelGGL(dev::trsv_wave, dim3(p->grid_wave), dim3(dev::kBlock), 0, st, p->d_wrow, p->d_wptr,
-                           p->d_wdiag, p->d_wcol, p->d_wval, p->d_wtask, p->d_wsuper, 0, p->S, b, x, p->d_bar,
-                           p->d_err, p->spin_limit);
-        HIP_TRY(hipGetLastError());
+        // all supersteps in one launch with the grid barrier between them
+        const int32_t *wr = p->d_wrow, *ws = p->d_wsuper;
+        const int64_t *wp = p->d_wptr, *wt = p->d_wtask;
+        const double *wd = p->d_wdiag, *wv = p->d_wval;
+        const uint32_t *wc = p->d_wcol;
+        int32_t s0 = 0, s1 = p->S;
+        uint32_t *bar = p->d_bar;
+        uint32_t *alive = p->d_alive;
+        uint32_t *claim = p->d_wclaim;
+        int32_t *err = p->d_err;
+        int64_t lim = p->spin_limit;
+        int64_t steal = p->steal_ticks;
+        int64_t delay = p->delay_ticks;
+        void *args[] = {&wr, &wp, &wd, &wc, &wv, &wt, &ws, &s0, &s1, &b, &x, &bar, &alive, &claim, &err, &lim, &steal,
+                        &delay};
+        if (int rc = launch_coresident(reinterpret_cast<const void *>(dev::trsv_wave), dim3(p->grid_wave), args, st,
+                                       p->cooperative))
+            return rc;
         p->last_stream = st;
         return GLTRSV_OK;
     }
@@ -717,22 +784,21 @@ int gltrsv_solve(gltrsv_plan *p, const double *b, double *x, void *stream)
     const int32_t *sc = p->d_super_chunk;
     int32_t S = p->S;
     uint32_t *bar = p->d_bar;
+    uint32_t *alive = p->d_alive;
+    uint32_t *claim = p->d_claim;
     int32_t *err = p->d_err;
     int64_t lim = p->spin_limit;
+    int64_t steal = p->steal_ticks;
+    int64_t delay = p->delay_ticks;
     int64_t *tr = p->d_trace;
-    void *args[] = {&w, &v, &cb, &cl, &sc, &S, &b, &x, &bar, &err, &lim, &tr};
-    if (p->cooperative) {
-        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(dev::trsv_persistent), dim3(p->grid),
-                                           dim3(dev::kBlock), args, 0, st));
-    } else {
-        // The grid fits the device's co-resident capacity (occupancy query at
-        // plan creation).  Should other work on the device keep workgroups
-        // from starting, the waiting ones reach the spin limit and the solve
-        // reports GLTRSV_ETIMEDOUT through gltrsv_plan_device_status.
-        hipLaunchKernelGGL(dev::trsv_persistent, dim3(p->grid), dim3(dev::kBlock), 0, st, w, v, cb, cl, sc, S, b, x,
-                           bar, err, lim, tr);
-        HIP_TRY(hipGetLastError());
-    }
+    void *args[] = {&w, &v, &cb, &cl, &sc, &S, &b, &x, &bar, &alive, &claim, &err, &lim, &steal, &delay, &tr};
+    // Without the cooperative launch the grid still fits the device's
+    // co-resident capacity (occupancy query at plan creation), but should
+    // other work keep workgroups from starting, the waiting ones reach the
+    // spin limit and the solve reports GLTRSV_ETIMEDOUT.
+    if (int rc = launch_coresident(reinterpret_cast<const void *>(dev::trsv_persistent), dim3(p->grid), args, st,
+                                   p->cooperative))
+        return rc;
     p->last_stream = st;
     return GLTRSV_OK;
 }
@@ -742,6 +808,8 @@ int gltrsv_solve_async(gltrsv_plan *p, const double *b, double *x, void *stream)
     if (!p || (p->n && (!b || !x))) return set_error(GLTRSV_EINVAL, "null argument");
     if (p->n == 0) return GLTRSV_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t vec = sizeof(double) * size_t(p->n);
+    if (b != x && overlap(b, vec, x, vec)) return set_error(GLTRSV_EINVAL, "b and x overlap without being equal");
     const double *bb = b;
     if (b == x) {   // x is about to be overwritten with the not-yet-computed mark
         if (!p->d_bcopy) HIP_TRY(hipMalloc(reinterpret_cast<void **>(&p->d_bcopy), sizeof(double) * size_t(p->n)));
@@ -751,31 +819,22 @@ int gltrsv_solve_async(gltrsv_plan *p, const double *b, double *x, void *stream)
     const int64_t fill_blocks = std::min<int64_t>(4096, (p->n + dev::kBlock - 1) / dev::kBlock);
     hipLaunchKernelGGL(dev::fill_unready, dim3(unsigned(fill_blocks)), dim3(dev::kBlock), 0, st,
                        reinterpret_cast<unsigned long long *>(x), p->n);
+    int64_t lim = p->spin_limit;
+    int32_t *err = p->d_err;
+    // static task orders; waves that wait long rob workgroups that have not
+    // started, so no co-residency is needed (plain launches)
     if (p->core_width == 64) {
-        const int32_t wtasks = p->wsuper_host.back();
         hipLaunchKernelGGL(dev::trsv_wave_async, dim3(p->grid_wave_async), dim3(dev::kBlock), 0, st, p->d_wrow,
-                           p->d_wptr, p->d_wdiag, p->d_wcol, p->d_wval, p->d_wtask, wtasks, bb, x, p->d_err,
-                           p->spin_limit);
+                           p->d_wptr, p->d_wdiag, p->d_wcol, p->d_wval, p->d_wtask, p->wsuper_host.back(), bb, x,
+                           err, lim, async_ticket(p, 2), p->d_aalive + 2 * dev::kMaxGrid,
+                           p->d_vnext + 2 * dev::kMaxGrid * dev::kWavesPerBlock, dev::kRobTicks, p->delay_ticks);
         HIP_TRY(hipGetLastError());
         p->last_stream = st;
         return GLTRSV_OK;
     }
-    const int32_t chunks = int32_t(p->chunks);
-    int64_t lim = p->spin_limit;
-    if (p->cooperative) {
-        const uint32_t *w = p->d_word;
-        const double *v = p->d_value;
-        const int64_t *cb = p->d_chunk_base;
-        const int32_t *cl = p->d_chunk_len;
-        int32_t *err = p->d_err;
-        int32_t nch = chunks;
-        void *args[] = {&w, &v, &cb, &cl, &nch, &bb, &x, &err, &lim};
-        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(dev::trsv_async), dim3(p->grid_async),
-                                           dim3(dev::kBlock), args, 0, st));
-    } else {
-        hipLaunchKernelGGL(dev::trsv_async, dim3(p->grid_async), dim3(dev::kBlock), 0, st, p->d_word, p->d_value,
-                           p->d_chunk_base, p->d_chunk_len, chunks, bb, x, p->d_err, lim);
-    }
+    hipLaunchKernelGGL(dev::trsv_async, dim3(p->grid_async), dim3(dev::kBlock), 0, st, p->d_word, p->d_value,
+                       p->d_chunk_base, p->d_chunk_len, int32_t(p->chunks), bb, x, err, lim, async_ticket(p, 0),
+                       p->d_aalive, p->d_vnext, dev::kRobTicks, p->delay_ticks);
     HIP_TRY(hipGetLastError());
     p->last_stream = st;
     return GLTRSV_OK;
@@ -786,7 +845,8 @@ int gltrsv_solve_multi(gltrsv_plan *p, const double *b, double *x, int32_t nrhs,
     if (!p || nrhs < 1 || (p->n && (!b || !x))) return set_error(GLTRSV_EINVAL, "bad argument");
     if (p->n == 0) return GLTRSV_OK;
     const int64_t total = p->n * int64_t(nrhs);
-    if (b < x + total && x < b + total) return set_error(GLTRSV_EINVAL, "B and X must not overlap");
+    if (overlap(b, sizeof(double) * size_t(total), x, sizeof(double) * size_t(total)))
+        return set_error(GLTRSV_EINVAL, "B and X must not overlap");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t fill_blocks = std::min<int64_t>(4096, (total + dev::kBlock - 1) / dev::kBlock);
     hipLaunchKernelGGL(dev::fill_unready, dim3(unsigned(fill_blocks)), dim3(dev::kBlock), 0, st,
@@ -794,17 +854,23 @@ int gltrsv_solve_multi(gltrsv_plan *p, const double *b, double *x, int32_t nrhs,
     const int32_t chunks = int32_t(p->chunks);
     const unsigned grid = unsigned(std::min<int64_t>(int64_t(p->grid_async) * dev::kWavesPerBlock, chunks));
     const int64_t ld = nrhs;
+    unsigned long long *tk = async_ticket(p, 1);
+    uint32_t *al = p->d_aalive + dev::kMaxGrid;
+    unsigned long long *vn = p->d_vnext + dev::kMaxGrid * dev::kWavesPerBlock;
     for (int32_t r0 = 0; r0 < nrhs;) {
         const int32_t R = nrhs - r0 >= 4 ? 4 : (nrhs - r0 >= 2 ? 2 : 1);
         if (R == 4)
             hipLaunchKernelGGL(dev::trsv_async_multi<4>, dim3(grid), dim3(64), 0, st, p->d_word, p->d_value,
-                               p->d_chunk_base, p->d_chunk_len, chunks, b + r0, x + r0, ld, p->d_err, p->spin_limit);
+                               p->d_chunk_base, p->d_chunk_len, chunks, b + r0, x + r0, ld, p->d_err, p->spin_limit,
+                               tk, al, vn, dev::kRobTicks, p->delay_ticks);
         else if (R == 2)
             hipLaunchKernelGGL(dev::trsv_async_multi<2>, dim3(grid), dim3(64), 0, st, p->d_word, p->d_value,
-                               p->d_chunk_base, p->d_chunk_len, chunks, b + r0, x + r0, ld, p->d_err, p->spin_limit);
+                               p->d_chunk_base, p->d_chunk_len, chunks, b + r0, x + r0, ld, p->d_err, p->spin_limit,
+                               tk, al, vn, dev::kRobTicks, p->delay_ticks);
         else
             hipLaunchKernelGGL(dev::trsv_async_multi<1>, dim3(grid), dim3(64), 0, st, p->d_word, p->d_value,
-                               p->d_chunk_base, p->d_chunk_len, chunks, b + r0, x + r0, ld, p->d_err, p->spin_limit);
+                               p->d_chunk_base, p->d_chunk_len, chunks, b + r0, x + r0, ld, p->d_err, p->spin_limit,
+                               tk, al, vn, dev::kRobTicks, p->delay_ticks);
         HIP_TRY(hipGetLastError());
         r0 += R;
     }
@@ -871,8 +937,9 @@ int gltrsv_plan_device_status(gltrsv_plan *p, int32_t *status)
     HIP_TRY(hipMemcpy(&e, p->d_err, sizeof(int32_t), hipMemcpyDeviceToHost));
     *status = e;
     if (e) {
-        // a workgroup left the barrier early: clear the words for the next solve
-        HIP_TRY(hipMemset(p->d_bar, 0, dev::kBarWords * sizeof(uint32_t)));
+        // a solve stopped part way: clear its partial counts for the next
+        // one (the start ticket keeps counting, so epochs stay unique)
+        HIP_TRY(hipMemset(p->d_bar, 0, dev::kBarStart * sizeof(uint32_t)));
         HIP_TRY(hipMemset(p->d_err, 0, sizeof(int32_t)));
     }
     return GLTRSV_OK;
@@ -882,6 +949,22 @@ int gltrsv_plan_set_spin_limit(gltrsv_plan *p, int64_t polls)
 {
     if (!p || polls < 1) return set_error(GLTRSV_EINVAL, "polls must be >= 1");
     p->spin_limit = polls;
+    return GLTRSV_OK;
+}
+
+int gltrsv_plan_set_steal_wait(gltrsv_plan *p, int64_t microseconds)
+{
+    if (!p || microseconds < 0 || microseconds > (int64_t(1) << 40))
+        return set_error(GLTRSV_EINVAL, "microseconds must be in 0..2^40");
+    p->steal_ticks = microseconds * 100;   // the device wall clock runs at 100 MHz
+    return GLTRSV_OK;
+}
+
+int gltrsv_plan_set_start_delay(gltrsv_plan *p, int64_t microseconds)
+{
+    if (!p || microseconds < 0 || microseconds > 10000000)
+        return set_error(GLTRSV_EINVAL, "microseconds must be in 0..1e7");
+    p->delay_ticks = microseconds * 100;
     return GLTRSV_OK;
 }
 
@@ -999,6 +1082,9 @@ int gltrsv_batch_destroy(gltrsv_batch *bt)
     (void)hipFree(bt->d_err);
     (void)hipFree(bt->d_gsys);
     (void)hipFree(bt->d_gtask);
+    (void)hipFree(bt->d_wticket);
+    (void)hipFree(bt->d_walive);
+    (void)hipFree(bt->d_wvnext);
     delete bt;
     return GLTRSV_OK;
 }
@@ -1122,7 +1208,11 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
         bt->gtasks = int64_t(gsys.size());
         int64_t bytes = 0;
         int rc;
-        if ((rc = upload(&bt->d_gsys, gsys, &bytes)) || (rc = upload(&bt->d_gtask, gtask, &bytes))) {
+        std::vector<unsigned long long> ticket(16, 0ull), vnext(size_t(dev::kMaxGrid * dev::kWavesPerBlock), 0ull);
+        std::vector<uint32_t> alive(size_t(dev::kMaxGrid), 0u);
+        if ((rc = upload(&bt->d_gsys, gsys, &bytes)) || (rc = upload(&bt->d_gtask, gtask, &bytes)) ||
+            (rc = upload(&bt->d_wticket, ticket, &bytes)) || (rc = upload(&bt->d_walive, alive, &bytes)) ||
+            (rc = upload(&bt->d_wvnext, vnext, &bytes))) {
             gltrsv_batch_destroy(bt);
             return rc;
         }
@@ -1133,6 +1223,52 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
     bt->grid = grid;
     bt->keep_waves = dev::keep_waves_for(widest_of(bt->plans), bt->per_claim, grid);
     *out = bt;
+    return GLTRSV_OK;
+}
+
+// The vectors of a batched solve: no null pointer; system i's x shares no
+// byte with any other system's b or x; b[i] may equal x[i] (BSP execution
+// only) but not overlap it partly.  Sorting the ranges keeps this
+// O(count log count).
+static int check_batch_vectors(const gltrsv_batch *bt, const double *const *b, double *const *x)
+{
+    struct Range {
+        uintptr_t lo, hi;
+        int32_t sys;
+        bool is_x;
+    };
+    std::vector<Range> r;
+    r.reserve(size_t(bt->count) * 2);
+    for (int32_t i = 0; i < bt->count; i++) {
+        const int32_t j = bt->slot[i];
+        if (!b[j] || !x[j]) return set_error(GLTRSV_EINVAL, "null vector in batch");
+        const uintptr_t len = uintptr_t(bt->plans[size_t(i)]->n) * sizeof(double);
+        const uintptr_t pb = reinterpret_cast<uintptr_t>(b[j]), px = reinterpret_cast<uintptr_t>(x[j]);
+        if (pb == px) {
+            if (bt->async_exec) return set_error(GLTRSV_EINVAL, "semi-asynchronous batches need b and x apart");
+            r.push_back({px, px + len, i, true});   // one range serves as both
+        } else {
+            r.push_back({pb, pb + len, i, false});
+            r.push_back({px, px + len, i, true});
+        }
+    }
+    std::sort(r.begin(), r.end(), [](const Range &a, const Range &c) { return a.lo < c.lo; });
+    // any two overlapping ranges overlap a neighbour in this order, unless
+    // both are b ranges (read-only, sharing is fine); track the x range that
+    // reaches furthest and the furthest range of any kind
+    uintptr_t far_any = 0, far_x = 0;
+    bool any = false, anyx = false;
+    for (const Range &q : r) {
+        if (anyx && q.lo < far_x) return set_error(GLTRSV_EINVAL, "a batch's x overlaps another vector");
+        if (q.is_x && any && q.lo < far_any)
+            return set_error(GLTRSV_EINVAL, "a batch's x overlaps another vector");
+        far_any = any ? std::max(far_any, q.hi) : q.hi;
+        any = true;
+        if (q.is_x) {
+            far_x = anyx ? std::max(far_x, q.hi) : q.hi;
+            anyx = true;
+        }
+    }
     return GLTRSV_OK;
 }
 
@@ -1147,13 +1283,18 @@ static int batch_enqueue(gltrsv_batch *bt, hipStream_t st)
         hipLaunchKernelGGL(dev::batch_reset, dim3(unsigned(std::max(1, (bt->count + dev::kBlock - 1) / dev::kBlock))),
                            dim3(dev::kBlock), 0, st, bt->d_state, bt->d_done, bt->count, 0, bt->d_finished,
                            bt->d_err);
-        if (bt->wave)
+        if (bt->wave) {
+            // static global task order; waves that wait long rob workgroups
+            // that have not started, so no co-residency is needed
             hipLaunchKernelGGL(dev::trsv_batched_wave_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st,
-                               bt->d_desc, bt->d_gsys, bt->d_gtask, bt->gtasks, bt->d_err, int64_t(5000000));
-        else
-            hipLaunchKernelGGL(dev::trsv_batched_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st,
-                               bt->d_desc, bt->count, bt->d_state, bt->d_finished, bt->d_err, int64_t(5000000),
-                               bt->per_claim, int64_t(0));
+                               bt->d_desc, bt->d_gsys, bt->d_gtask, bt->gtasks, bt->d_err, int64_t(5000000),
+                               bt->d_wticket, bt->d_walive, bt->d_wvnext, dev::kRobTicks);
+            HIP_TRY(hipGetLastError());
+            return GLTRSV_OK;
+        }
+        hipLaunchKernelGGL(dev::trsv_batched_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st, bt->d_desc,
+                           bt->count, bt->d_state, bt->d_finished, bt->d_err, int64_t(5000000), bt->per_claim,
+                           int64_t(0));
         HIP_TRY(hipGetLastError());
         return GLTRSV_OK;
     }
@@ -1176,11 +1317,9 @@ int gltrsv_batch_solve(gltrsv_batch *bt, const double *const *b, double *const *
     bt->flip ^= 1;
     // the copy issued from this staging buffer two calls ago has finished
     HIP_TRY(hipEventSynchronize(bt->staged[k]));
+    if (int rc = check_batch_vectors(bt, b, x)) return rc;
     for (int32_t i = 0; i < bt->count; i++) {
         const int32_t j = bt->slot[i];
-        if (!b[j] || !x[j]) return set_error(GLTRSV_EINVAL, "null vector in batch");
-        if (bt->async_exec && b[j] == x[j])
-            return set_error(GLTRSV_EINVAL, "semi-asynchronous batches need b and x apart");
         bt->h_desc[k][i].b = b[j];
         bt->h_desc[k][i].x = x[j];
     }
@@ -1200,7 +1339,10 @@ int gltrsv_batch_solve(gltrsv_batch *bt, const double *const *b, double *const *
             const int rc = batch_enqueue(bt, st);
             hipGraph_t g = nullptr;
             const hipError_t ce = hipStreamEndCapture(st, &g);
-            if (rc) return rc;
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
             if (ce != hipSuccess) return set_error(GLTRSV_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
             bt->graph = g;
             HIP_TRY(hipGraphInstantiate(&bt->graph_exec, bt->graph, nullptr, nullptr, 0));

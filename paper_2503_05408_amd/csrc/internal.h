@@ -20,20 +20,34 @@ namespace dev {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
 
-// Persistent-kernel barrier words (one 128-byte line each): the generation,
-// the top count, and one count per group of workgroups (up to 128 groups).
-// A grid of at most kFlatMax workgroups is one group whose last arrival
-// advances the generation directly; larger grids count in groups of kGroup
-// and then on the top word.  Measured on MI355X: one level up to 256
-// workgroups beat groups of 16 (27-point grid 11.47 against 11.96 ms, equal
-// on C2), while at 2,048 workgroups groups of 16 beat groups of 256 (15.3
-// against 11.8 ms with wavefront cores).
+// Words of the persistent kernels' superstep synchronisation, one 128-byte
+// line each: the progress word (64-bit: epoch of the solve, supersteps
+// completed), the top count, one count per group of workgroups (up to 128
+// groups), and the 64-bit start ticket.  A grid of at most kFlatMax
+// workgroups counts on group 0's word only; larger grids count per group of
+// kGroup workgroups and then on the top word.  Measured on MI355X: one level
+// up to 256 workgroups beat groups of 16 (27-point grid 11.47 against
+// 11.96 ms, equal on C2), while at 2,048 workgroups groups of 16 beat groups
+// of 256 (15.3 against 11.8 ms with wavefront cores).
 constexpr int kGroup = 16;
 constexpr int kFlatMax = 256;
-constexpr int kBarGen = 0;          // word index of the generation
+constexpr int kBarProg = 0;         // word index of the 64-bit progress word
 constexpr int kBarTop = 32;         // word index of the top count
 constexpr int kBarGroups = 64;      // group g counts at kBarGroups + 32 g
-constexpr int kBarWords = kBarGroups + 32 * 128;
+constexpr int kBarStart = kBarGroups + 32 * 128;   // 64-bit start ticket
+// 64-bit start tickets of the semi-asynchronous kernels (lane cores, several
+// right-hand sides, wavefront cores), one line each
+constexpr int kBarAsyncTicket = kBarStart + 32;
+constexpr int kBarWords = kBarAsyncTicket + 3 * 32;
+// A semi-asynchronous wave that has waited this long for values (100 MHz
+// ticks, 200 us) looks for workgroups of its launch that have not started.
+constexpr int64_t kRobTicks = 20000;
+constexpr int kMaxGrid = kGroup * 128;   // workgroups of a persistent launch at most
+// A workgroup that has waited this long for a superstep (ticks of the
+// 100 MHz wall clock, 200 us) starts claiming that superstep's unclaimed
+// items: far above the imbalance waits of normal runs, so the steals only
+// act when some workgroup cannot start or has stalled.
+constexpr int64_t kStealTicks = 20000;
 
 // Wavefront cores: rows of the same task this many back or fewer come from
 // a per-wave LDS ring (the layout marks them).
@@ -113,13 +127,15 @@ __global__ void fill_unready_sys(const SysDesc *__restrict__ sys, int32_t count)
 __global__ void trsv_batched_async(const SysDesc *__restrict__ sys, int32_t count, unsigned long long *state,
                                    uint32_t *finished, int32_t *err, int64_t spin_limit, int32_t per_claim,
                                    int64_t quantum);
+// x[0, n) = the not-yet-computed mark
 __global__ void fill_unready(unsigned long long *x, int64_t n);
 // the same for systems planned with wavefront cores: global task g is task
 // gtask[g] of system gsys[g] (each system's tasks in their order), run in
 // order by wave g mod W of a co-resident grid
 __global__ void trsv_batched_wave_async(const SysDesc *__restrict__ sys, const int32_t *__restrict__ gsys,
                                         const int32_t *__restrict__ gtask, int64_t ntasks, int32_t *err,
-                                        int64_t spin_limit);
+                                        int64_t spin_limit, unsigned long long *ticket, uint32_t *alive,
+                                        unsigned long long *vnext, int64_t rob_ticks);
 
 // Fills the plan's stream (d_word, d_value: lay.pk.slots entries) on the
 // device from A, the schedule order and the host layout; synchronous.
@@ -136,26 +152,37 @@ __global__ void trsv_superstep_plain(const uint32_t *word, const double *value, 
 __global__ void trsv_superstep_unordered(const int64_t *row_ptr, const int32_t *col, const double *val,
                                          const int32_t *rows, const int64_t *task_off, int32_t t0, int32_t t1,
                                          int32_t upper, const double *b, double *x);
-// lane cores, every superstep in one co-resident launch with a barrier
+// lane cores, every superstep in one launch; superstep completion counted
+// on `bar`, workgroups that have not started robbed (alive: one word per
+// workgroup, claim: one word per chunk)
 __global__ void trsv_persistent(const uint32_t *word, const double *value, const int64_t *chunk_base,
                                 const int32_t *chunk_len, const int32_t *super_chunk, int32_t S, const double *b,
-                                double *x, uint32_t *bar, int32_t *err, int64_t spin_limit, int64_t *trace);
-// wavefront cores: supersteps [s0, s1) (a barrier between them), and the
+                                double *x, uint32_t *bar, uint32_t *alive, uint32_t *claim, int32_t *err,
+                                int64_t spin_limit, int64_t steal_ticks, int64_t delay_ticks, int64_t *trace);
+// wavefront cores: supersteps [s0, s1) (claim = nullptr for a single
+// superstep, else one word per task as in trsv_persistent), and the
 // semi-asynchronous form over all tasks
 __global__ void trsv_wave(const int32_t *wrow, const int64_t *wptr, const double *wdiag, const uint32_t *wcol,
                           const double *wval, const int64_t *wtask, const int32_t *wsuper, int32_t s0, int32_t s1,
-                          const double *b, double *x, uint32_t *bar, int32_t *err, int64_t spin_limit);
+                          const double *b, double *x, uint32_t *bar, uint32_t *alive, uint32_t *claim,
+                          int32_t *err, int64_t spin_limit, int64_t steal_ticks, int64_t delay_ticks);
 __global__ void trsv_wave_async(const int32_t *wrow, const int64_t *wptr, const double *wdiag, const uint32_t *wcol,
                                 const double *wval, const int64_t *wtask, int32_t tasks, const double *b, double *x,
-                                int32_t *err, int64_t spin_limit);
+                                int32_t *err, int64_t spin_limit, unsigned long long *ticket, uint32_t *alive,
+                                unsigned long long *vnext, int64_t rob_ticks, int64_t delay_ticks);
 // lane cores, semi-asynchronous; R right-hand sides (row-major, leading dimension ld)
+// (static chunk order; ticket/alive/vnext: the robbing of workgroups that
+// have not started, a start ticket, kMaxGrid alive words and 4 kMaxGrid
+// robbed-prefix words per kernel)
 __global__ void trsv_async(const uint32_t *word, const double *value, const int64_t *chunk_base,
                            const int32_t *chunk_len, int32_t chunks, const double *b, double *x, int32_t *err,
-                           int64_t spin_limit);
+                           int64_t spin_limit, unsigned long long *ticket, uint32_t *alive, unsigned long long *vnext,
+                           int64_t rob_ticks, int64_t delay_ticks);
 template <int R>
 __global__ void trsv_async_multi(const uint32_t *word, const double *value, const int64_t *chunk_base,
                                  const int32_t *chunk_len, int32_t chunks, const double *b, double *x, int64_t ld,
-                                 int32_t *err, int64_t spin_limit);
+                                 int32_t *err, int64_t spin_limit, unsigned long long *ticket, uint32_t *alive,
+                                 unsigned long long *vnext, int64_t rob_ticks, int64_t delay_ticks);
 // measurement probes
 __global__ void gather_probe(const uint32_t *word, const double *value, const int64_t *chunk_base,
                              const int32_t *chunk_len, int64_t chunks, const double *x, double *y);
@@ -192,11 +219,21 @@ struct gltrsv_plan {
     int64_t *d_chunk_base = nullptr;
     int32_t *d_chunk_len = nullptr;
     int32_t *d_super_chunk = nullptr;
-    uint32_t *d_bar = nullptr;   // barrier words (dev::kBarWords)
+    uint32_t *d_bar = nullptr;   // superstep synchronisation words (dev::kBarWords)
+    uint32_t *d_alive = nullptr; // per persistent-kernel workgroup: epoch of its last start (+ robbed bit)
+    uint32_t *d_claim = nullptr; // per chunk: epoch of the solve that claimed it (persistent kernel)
+    uint32_t *d_wclaim = nullptr;// per wave-core task: the same for the wave-core persistent kernel
+    // robbing in the semi-asynchronous kernels: alive words (3 x kMaxGrid:
+    // lane cores, several right-hand sides, wave cores) and robbed-prefix
+    // words (3 x 4 kMaxGrid)
+    uint32_t *d_aalive = nullptr;
+    unsigned long long *d_vnext = nullptr;
     int32_t *d_err = nullptr;
     int64_t *d_trace = nullptr;  // per-superstep timestamps (trace builds only)
     hipStream_t last_stream = nullptr;
-    int64_t spin_limit = 5000000;   // barrier polls before ETIMEDOUT, about 5 s
+    int64_t spin_limit = 5000000;   // polls of a device-side wait before ETIMEDOUT (0.7-5 s)
+    int64_t steal_ticks = gltrsv::dev::kStealTicks;   // superstep wait before robbing (100 MHz ticks)
+    int64_t delay_ticks = 0;        // diagnostic late start of every 7th persistent workgroup
     int32_t schedule_kind = 0;      // the schedule actually built
     double predicted_us = 0.0;      // cost-model prediction of one solve
     bool device_packed = false;     // stream filled by the packing kernels

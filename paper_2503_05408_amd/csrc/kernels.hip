@@ -201,18 +201,46 @@ __device__ __forceinline__ bool unready(uint32_t c, double g)
     return (c & (HDR | INTL)) == 0 && static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
 }
 
+// Robbing in the semi-asynchronous kernels (see trsv_async): a wave that has
+// waited rob_ticks for values while some workgroup of the launch has not
+// started abandons its chunk.  alive == nullptr: never abandon.
+struct AsyncRob {
+    const uint32_t *alive;   // per workgroup: epoch of its start
+    uint32_t epoch;
+    int64_t rob_ticks;
+};
+
+// True in every lane if some workgroup of the launch has not started in
+// this epoch.
+__device__ __forceinline__ bool any_not_started(AsyncRob rob)
+{
+    const int lane = threadIdx.x & 63;
+    for (uint32_t base = 0; base < gridDim.x; base += 64) {
+        const uint32_t g = base + uint32_t(lane);
+        const bool late = g < gridDim.x &&
+                          __hip_atomic_load(rob.alive + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != rob.epoch;
+        if (__ballot(late)) return true;
+    }
+    return false;
+}
+
+enum AwaitResult { kReady = 0, kAbandon = 1, kFailed = 2 };
+
 // Waits until every gathered column of the batch holds a computed value.
 // Gives up after spin_limit rounds (setting *err) or once another wave has
-// set *err; the solve's status then reports the failure.
+// set *err (kFailed: the solve's status reports the failure), or returns
+// kAbandon once it has waited rob.rob_ticks while a workgroup has not
+// started.
 template <int U>
-__device__ __forceinline__ void await_batch(const Batch<U> &B, double (&g)[U], const double *x, int32_t *err,
-                                            int64_t spin_limit)
+__device__ __forceinline__ int await_batch(const Batch<U> &B, double (&g)[U], const double *x, int32_t *err,
+                                           int64_t spin_limit, AsyncRob rob)
 {
     bool miss = false;
 #pragma unroll
     for (int j = 0; j < U; j++) miss |= unready(B.w[j], g[j]);
-    if (__ballot(miss) == 0ull) return;
+    if (__ballot(miss) == 0ull) return kReady;
     int32_t nap = 1;
+    int64_t since = -1;   // wall clock at the first rob check
     for (int64_t spins = 1;; spins++) {
         for (int32_t k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(1);
         nap = min(2 * nap, int32_t(kAwaitNapMax));
@@ -222,13 +250,100 @@ __device__ __forceinline__ void await_batch(const Batch<U> &B, double (&g)[U], c
         miss = false;
 #pragma unroll
         for (int j = 0; j < U; j++) miss |= unready(B.w[j], g[j]);
-        if (__ballot(miss) == 0ull) return;
+        if (__ballot(miss) == 0ull) return kReady;
         if (spins > spin_limit) {
             if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
+            return kFailed;
         }
-        if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+        if ((spins & 255) == 0) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return kFailed;
+            if (rob.alive) {
+                const int64_t now = int64_t(wall_clock64());
+                if (since < 0) {
+                    since = now;
+                } else if (now - since > rob.rob_ticks) {
+                    if (any_not_started(rob)) return kAbandon;
+                    since = now;
+                }
+            }
+        }
     }
+}
+
+// Per-launch epoch from the start ticket (as bsp_start; launches of this
+// kernel on a plan take their tickets from their own word), announced in
+// the alive table.
+__device__ __forceinline__ uint32_t async_start(unsigned long long *ticket, uint32_t *alive, int64_t delay_ticks)
+{
+    __shared__ uint32_t s_epoch;
+    if (threadIdx.x == 0) {
+        if (delay_ticks > 0 && blockIdx.x % 7 == 3) {   // diagnostic: a late start
+            const int64_t until = int64_t(wall_clock64()) + delay_ticks;
+            while (int64_t(wall_clock64()) < until) __builtin_amdgcn_s_sleep(8);
+        }
+        const unsigned long long t = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t e = (uint32_t(t / gridDim.x) % 0x7FFFFFFFu) + 1u;
+        __hip_atomic_store(alive + blockIdx.x, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_epoch = e;
+    }
+    __syncthreads();
+    return s_epoch;
+}
+
+// Minimum over the wave of a 64-bit key, in every lane.
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned long long o = static_cast<unsigned long long>(__shfl_xor(static_cast<long long>(v), d, 64));
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// The earliest item (of a static order: wave slot v -- the (v mod w)-th wave
+// of workgroup v / w, w waves per workgroup -- runs items v + k W, W = w G)
+// of a not-started workgroup's waves that no thief has taken; taken
+// for the caller if it precedes `before`.  vnext[v] = (epoch << 32) | items
+// of slot v taken by thieves.  Returns the item, or -1.
+__device__ __forceinline__ int64_t rob_item(AsyncRob rob, unsigned long long *vnext, int64_t items,
+                                            int64_t before)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t G = gridDim.x;
+    const uint32_t wpg = blockDim.x >> 6;   // waves per workgroup
+    const int64_t W = int64_t(G) * wpg;
+    unsigned long long best = ~0ull;   // (item << 16) | slot
+    for (uint32_t base = 0; base < G; base += 64) {
+        const uint32_t g = base + uint32_t(lane);
+        if (g >= G) continue;
+        if (__hip_atomic_load(rob.alive + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == rob.epoch) continue;
+        for (uint32_t j = 0; j < wpg; j++) {
+            const uint32_t v = g * wpg + j;
+            const unsigned long long w = __hip_atomic_load(vnext + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int64_t k = uint32_t(w >> 32) == rob.epoch ? int64_t(uint32_t(w)) : 0;
+            const int64_t item = int64_t(v) + k * W;
+            if (item < items && item < before) {
+                const unsigned long long key = (static_cast<unsigned long long>(item) << 16) | v;
+                best = key < best ? key : best;
+            }
+        }
+    }
+    best = wave_min_u64(best);
+    if (best == ~0ull) return -1;
+    const uint32_t v = uint32_t(best & 0xFFFFu);
+    const int64_t item = int64_t(best >> 16);
+    int32_t got = 0;
+    if (lane == 0) {
+        const int64_t k = (item - int64_t(v)) / W;
+        unsigned long long expect = __hip_atomic_load(vnext + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t kk = uint32_t(expect >> 32) == rob.epoch ? int64_t(uint32_t(expect)) : 0;
+        if (kk == k)
+            got = __hip_atomic_compare_exchange_strong(
+                vnext + v, &expect, (static_cast<unsigned long long>(rob.epoch) << 32) | uint32_t(k + 1),
+                __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return __builtin_amdgcn_readfirstlane(got) ? item : -1;
 }
 
 // One pipeline step: gathers of `nxt`, words/values of the batch after it
@@ -238,17 +353,22 @@ __device__ __forceinline__ void await_batch(const Batch<U> &B, double (&g)[U], c
     do {                                                                                                 \
         gather_batch(NXT, b, x, GNXT);                                                                   \
         load_batch(cur, (T0) + 2 * U, FUT);                                                              \
-        if constexpr (kAsync) await_batch(NOW, GNOW, x, err, spin_limit);                                \
+        if constexpr (kAsync)                                                                            \
+            if (await_batch(NOW, GNOW, x, err, spin_limit, rob) == kAbandon) return false;              \
         process_batch(NOW, GNOW, st, x, ring);                                                           \
     } while (0)
 
 // Runs one lane's task.  b0/b1 hold the task's first two batches (already
 // loaded by the caller, possibly before the superstep's barrier).  The loop
 // is unrolled three times so the three batch buffers change roles without
-// register copies.
+// register copies.  Returns false if the semi-asynchronous form abandoned
+// the chunk (the whole wave does; the rows stored so far are final).
+__device__ __forceinline__ AsyncRob no_rob() { return AsyncRob{nullptr, 0u, 0}; }
+
 template <int U, bool kAsync = false>
-__device__ __forceinline__ void run_lane(const LaneCursor &cur, Batch<U> &b0, Batch<U> &b1, const double *b,
-                                         double *x, Ring ring, int32_t *err = nullptr, int64_t spin_limit = 0)
+__device__ __forceinline__ bool run_lane(const LaneCursor &cur, Batch<U> &b0, Batch<U> &b1, const double *b,
+                                         double *x, Ring ring, int32_t *err = nullptr, int64_t spin_limit = 0,
+                                         AsyncRob rob = AsyncRob{nullptr, 0u, 0})
 {
     LaneState st;
     st.acc = 0.0;
@@ -272,6 +392,7 @@ __device__ __forceinline__ void run_lane(const LaneCursor &cur, Batch<U> &b0, Ba
         if (t0 >= cur.len) break;
     }
     if (st.cur >= 0) store_x(x + st.cur, st.acc / st.diag);
+    return true;
 }
 #undef GLTRSV_STEP
 
@@ -331,97 +452,232 @@ __global__ __launch_bounds__(kBlock) void trsv_superstep_unordered(
     }
 }
 
-// Barrier over all workgroups of the grid, in two halves so that work that
-// does not depend on other workgroups can run while waiting.  Arrivals are
-// counted in up to two levels: workgroups of a group (the whole grid up to
-// kFlatMax workgroups, else kGroup) count on the group's word; with several
-// groups the last of each counts on the top word;
-// the last arrival overall advances the generation word that every
-// workgroup waits on.  Every word sits on its own 128-byte line.  Each last
-// arrival resets the word it completed before moving up, so the words are
-// ready for the next barrier.
+// ---------------------------------------------------------------------------
+// Supersteps of one system in one launch, without relying on co-residency.
+//
+// The items of superstep s (chunks of 64 lane-cores, or wavefront-core
+// tasks) are numbered k = 0 .. m_s - 1; the wave in slot v = i G + g (the
+// i-th wave of workgroup g) owns items v, v + W, v + 2W, ... (W = 4 G), so
+// item k belongs to workgroup k mod G.
+//
+// Superstep s is complete when its m_s items are counted as done.  Counts
+// go to one word for grids of up to kFlatMax workgroups; larger grids count
+// per group of kGroup workgroups (the group of an item's owner) and count
+// completed groups on a top word.  The arrival that completes a word resets
+// it, waits for the reset to land and then counts one level up; the last
+// one publishes progress = (epoch, s + 1).  Words are reused by every
+// superstep: they are zero again before the progress that allows the next
+// superstep's counts is published.
+//
+// Workgroups that cannot start (other work holds the device) would stall
+// the solve, so a workgroup whose wait for a superstep exceeds steal_ticks
+// robs the workgroups that have not started yet: it marks one robbed in the
+// alive table (a compare-and-swap that fails once the owner has started),
+// then claims and runs that owner's items of the superstep, one exchange of
+// an item's claim word each.  A workgroup announces itself at its start by
+// exchanging its alive word for the epoch; if it finds itself robbed it
+// claims its items of its first superstep (thieves may still be at work on
+// that one; later supersteps are never robbed), otherwise it runs its items
+// without claims.  It starts at the published progress.  So the solve
+// advances whenever any workgroup runs, and with every workgroup resident
+// (the normal case) nothing is claimed or scanned.
+//
+// The epoch comes from a ticket every workgroup takes at its start: solves
+// on a plan do not overlap and each launches G workgroups, so tickets
+// [j G, (j + 1) G) belong to the plan's j-th solve -- also when the launch
+// is replayed from a graph.  Epochs use 31 bits; the top bit of an alive
+// word marks "robbed in that epoch".
+// ---------------------------------------------------------------------------
 
-struct BarrierTicket {
-    uint32_t gen;
-    bool last;
+constexpr uint32_t kRobbed = 0x80000000u;
+
+struct BspStart {
+    uint32_t epoch;
+    int32_t first;   // supersteps already completed when the workgroup started
+    bool robbed;     // thieves ran (or may be running) items of superstep `first`
 };
 
-__device__ __forceinline__ BarrierTicket barrier_arrive(uint32_t *bar)
+__device__ __forceinline__ BspStart bsp_start(uint32_t *bar, uint32_t *alive, int64_t delay_ticks)
 {
-    // Every wave waits until its own (coherent) stores have completed.
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __syncthreads();
-    __shared__ uint32_t s_gen;
-    __shared__ int32_t s_last;
+    __shared__ uint32_t s_epoch;
+    __shared__ int32_t s_first;
+    __shared__ int32_t s_robbed;
     if (threadIdx.x == 0) {
-        const uint32_t G = gridDim.x;
-        const uint32_t gw = G <= uint32_t(kFlatMax) ? G : uint32_t(kGroup);   // group width
-        const uint32_t grp = blockIdx.x / gw;
-        const uint32_t groups = (G + gw - 1) / gw;
-        const uint32_t gsize = min(gw, G - grp * gw);
-        uint32_t *gen = bar + kBarGen;
-        uint32_t *top = bar + kBarTop;
-        uint32_t *cnt = bar + kBarGroups + 32 * grp;
-        const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        bool last = false;
-        const uint32_t old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == gsize - 1) {
-            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            bool top_last = true;   // a single group needs no top level
-            if (groups > 1) {
-                const uint32_t old2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                top_last = old2 == groups - 1;
-                if (top_last) __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (top_last) {
-                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                last = true;
-            }
+        if (delay_ticks > 0 && blockIdx.x % 7 == 3) {   // diagnostic: a late start
+            const int64_t until = int64_t(wall_clock64()) + delay_ticks;
+            while (int64_t(wall_clock64()) < until) __builtin_amdgcn_s_sleep(8);
         }
-        s_gen = g;
-        s_last = last;
+        const unsigned long long t = __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(bar + kBarStart),
+                                                            1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t e = (uint32_t(t / gridDim.x) % 0x7FFFFFFFu) + 1u;
+        const uint32_t old = __hip_atomic_exchange(alive + blockIdx.x, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long p = __hip_atomic_load(reinterpret_cast<unsigned long long *>(bar + kBarProg),
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_epoch = e;
+        s_first = uint32_t(p >> 32) == e ? int32_t(uint32_t(p)) : 0;
+        s_robbed = old == (e | kRobbed);
     }
     __syncthreads();
-    BarrierTicket t;
-    t.gen = s_gen;
-    t.last = s_last != 0;
-    return t;
+    BspStart st;
+    st.epoch = s_epoch;
+    st.first = s_first;
+    st.robbed = s_robbed != 0;
+    return st;
 }
 
-// Returns false if the spin limit was hit or another workgroup reported an
-// error; then the whole workgroup must exit.
-__device__ __forceinline__ bool barrier_wait(uint32_t *bar, BarrierTicket t, int32_t *err, int64_t spin_limit)
+// Supersteps completed in this solve, from a progress word.
+__device__ __forceinline__ int32_t bsp_completed(unsigned long long p, uint32_t epoch)
 {
-    __shared__ int32_t ok;
+    return uint32_t(p >> 32) == epoch ? int32_t(uint32_t(p)) : 0;
+}
+
+// One lane claims item `item` for the solve; the whole wave gets the answer.
+__device__ __forceinline__ bool claim_item(uint32_t *claim, int32_t item, uint32_t epoch)
+{
+    uint32_t got = 0;
+    if ((threadIdx.x & 63) == 0)
+        got = __hip_atomic_exchange(claim + item, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch ? 1u : 0u;
+    return __builtin_amdgcn_readfirstlane(got) != 0;
+}
+
+// Items of group q (workgroups [q kGroup, q kGroup + kGroup)) among m items
+// owned by workgroup k mod G.
+__device__ __forceinline__ uint32_t group_items(uint32_t m, uint32_t G, uint32_t q)
+{
+    const uint32_t lo = q * uint32_t(kGroup), hi = min(G, lo + uint32_t(kGroup));
+    const uint32_t full = m / G, rem = m % G;
+    return (hi - lo) * full + (rem > lo ? min(rem, hi) - lo : 0u);
+}
+
+// Counts k done items of superstep s owned by workgroup `owner`; the count
+// that completes the superstep publishes it.  Called by one lane; the
+// caller's x stores have completed.
+__device__ __forceinline__ void bsp_done(uint32_t *bar, uint32_t epoch, int32_t s, uint32_t m, uint32_t owner,
+                                         uint32_t k)
+{
+    const uint32_t G = gridDim.x;
+    const bool flat = G <= uint32_t(kFlatMax);
+    const uint32_t q = flat ? 0u : owner / uint32_t(kGroup);
+    uint32_t *cnt = bar + kBarGroups + 32 * q;
+    const uint32_t want = flat ? m : group_items(m, G, q);
+    const uint32_t old = __hip_atomic_fetch_add(cnt, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + k != want) return;
+    __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    if (!flat) {
+        uint32_t *top = bar + kBarTop;
+        const uint32_t groups = (min(m, G) + uint32_t(kGroup) - 1) / uint32_t(kGroup);
+        const uint32_t old2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old2 + 1 != groups) return;
+        __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(bar + kBarProg),
+                       (static_cast<unsigned long long>(epoch) << 32) | uint32_t(s + 1), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// End of a workgroup's own items of superstep s: every wave has waited for
+// its x stores and added its count to *s_done; one add for the workgroup.
+__device__ __forceinline__ void bsp_count_own(uint32_t *bar, uint32_t epoch, int32_t s, uint32_t m, uint32_t mine,
+                                              uint32_t *s_done)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    if ((threadIdx.x & 63) == 0 && mine) atomicAdd(s_done, mine);
+    __syncthreads();
     if (threadIdx.x == 0) {
-        int32_t good = 1;
-        if (!t.last) {
-            const uint32_t *gen = bar + kBarGen;
-            int64_t it = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == t.gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++it > spin_limit) {
+        const uint32_t k = *s_done;
+        *s_done = 0;
+        if (k) bsp_done(bar, epoch, s, m, blockIdx.x, k);
+    }
+}
+
+// Waits until superstep s is complete.  Every steal_ticks of waiting (100
+// MHz wall clock) each wave runs steal(s).  Returns false if the spin limit
+// was hit or another workgroup failed; then the whole workgroup must leave.
+template <class Steal>
+__device__ __forceinline__ bool bsp_wait(uint32_t *bar, uint32_t epoch, int32_t s, int32_t *err, int64_t spin_limit,
+                                         int64_t steal_ticks, Steal steal)
+{
+    __shared__ int32_t s_state;   // 0 waiting, 1 complete, 2 failed, 3 steal now
+    const unsigned long long *prog = reinterpret_cast<const unsigned long long *>(bar + kBarProg);
+    int64_t next_steal = int64_t(wall_clock64()) + steal_ticks;
+    for (int64_t it = 0;; it++) {
+        if (threadIdx.x == 0) {
+            int32_t st = bsp_completed(__hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), epoch) > s;
+            if (!st) {
+                if (it > spin_limit) {
                     __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    good = 0;
-                    break;
+                    st = 2;
+                } else if ((it & 1023) == 1023 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    st = 2;
+                } else if (int64_t(wall_clock64()) >= next_steal) {
+                    st = 3;
+                    next_steal = int64_t(wall_clock64()) + steal_ticks;
                 }
-                if ((it & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    good = 0;
-                    break;
+            }
+            s_state = st;
+        }
+        __syncthreads();
+        const int32_t st = s_state;
+        __syncthreads();   // s_state is written again in the next round
+        if (st == 1) return true;
+        if (st == 2) return false;
+        if (st == 3)
+            steal(s);
+        else
+            __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// A wave's steal pass over superstep s (items [i0, i0 + m)): the victims
+// are the workgroups v = r, r + 4, ... (from a start spread over the
+// thieves) that have not started; each is marked robbed (compare-and-swap
+// of its alive word), then its items of s are claimed and run (run(item))
+// and counted for it.
+template <class Run>
+__device__ __forceinline__ void steal_items(uint32_t *bar, uint32_t *alive, uint32_t *claim, uint32_t epoch,
+                                            int32_t s, int32_t i0, uint32_t m, Run run)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t G = gridDim.x;
+    const uint32_t first = (blockIdx.x * uint32_t(kWavesPerBlock) + (threadIdx.x >> 6)) % G;
+    for (uint32_t base = 0; base < G; base += 64 * kWavesPerBlock) {
+        const uint32_t r = base + uint32_t(lane) * kWavesPerBlock;   // this lane's candidate, relative to `first`
+        const uint32_t v = (first + r) % G;
+        bool victim = false;
+        if (r < G && v < m) {   // owners of no item in s need no robbing
+            uint32_t a = __hip_atomic_load(alive + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a != epoch) {
+                victim = a == (epoch | kRobbed);
+                if (!victim) {
+                    uint32_t expect = a;
+                    victim = __hip_atomic_compare_exchange_strong(alive + v, &expect, epoch | kRobbed, __ATOMIC_RELAXED,
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                             expect == (epoch | kRobbed);
                 }
             }
         }
-        ok = good;
+        unsigned long long cand = __ballot(victim);
+        while (cand) {
+            const int l = __builtin_ctzll(cand);
+            cand &= cand - 1;
+            const uint32_t vv = (first + base + uint32_t(l) * kWavesPerBlock) % G;
+            for (uint32_t k = vv; k < m; k += G) {
+                if (!claim_item(claim, i0 + int32_t(k), epoch)) continue;
+                run(i0 + int32_t(k));
+                __builtin_amdgcn_s_waitcnt(0);
+                if (lane == 0) bsp_done(bar, epoch, s, m, vv, 1u);
+            }
+        }
     }
-    __syncthreads();
-    return ok != 0;
 }
 
 __global__ __launch_bounds__(kBlock) void trsv_persistent(
     const uint32_t *__restrict__ word, const double *__restrict__ value, const int64_t *__restrict__ chunk_base,
     const int32_t *__restrict__ chunk_len, const int32_t *__restrict__ super_chunk, int32_t S, const double *b,
-    double *x, uint32_t *bar, int32_t *err, int64_t spin_limit, int64_t *trace)
+    double *x, uint32_t *bar, uint32_t *alive, uint32_t *claim, int32_t *err, int64_t spin_limit,
+    int64_t steal_ticks, int64_t delay_ticks, int64_t *trace)
 {
     const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
     // wave slot: the i-th wave of workgroup g is slot i G + g.  Chunks of a
@@ -432,40 +688,65 @@ __global__ __launch_bounds__(kBlock) void trsv_persistent(
     const int32_t wave = int32_t(threadIdx.x >> 6) * int32_t(gridDim.x) + int32_t(blockIdx.x);
     const int lane = threadIdx.x & 63;
     __shared__ double ring[kRing + 1][kBlock];
-    // first chunk of this wave in superstep 0, and its first two batches
-    int32_t c = super_chunk[0] + wave;
-    int32_t c_end = super_chunk[1];
-    LaneCursor cur = make_cursor(word, value, c < c_end ? chunk_base[c] : 0, c < c_end ? chunk_len[c] : 0, lane);
+    __shared__ uint32_t s_done;
+    if (threadIdx.x == 0) s_done = 0;
+    const BspStart bs = bsp_start(bar, alive, delay_ticks);
+    int32_t s = bs.first;
+    if (s >= S) return;
+    bool claiming = bs.robbed;   // only a robbed workgroup's first superstep is contested
+    // this wave's first chunk and its first two batches
+    int32_t c = super_chunk[s] + wave, c_end = super_chunk[s + 1];
+    bool have = c < c_end && (!claiming || claim_item(claim, c, bs.epoch));
+    LaneCursor cur = make_cursor(word, value, have ? chunk_base[c] : 0, have ? chunk_len[c] : 0, lane);
     Batch<kUnroll> b0, b1;
     load_batch(cur, 0, b0);
     load_batch(cur, kUnroll, b1);
-    for (int32_t s = 0; s < S; s++) {
+    auto run_chunk = [&](int32_t cc) {
+        const LaneCursor sc = make_cursor(word, value, chunk_base[cc], chunk_len[cc], lane);
+        Batch<kUnroll> s0, s1;
+        load_batch(sc, 0, s0);
+        load_batch(sc, kUnroll, s1);
+        run_lane(sc, s0, s1, b, x, ring);
+    };
+    for (; s < S; s++) {
 #ifdef GLTRSV_TRACE
         if (threadIdx.x == 0) trace[(int64_t(s) * gridDim.x + blockIdx.x) * 3 + 0] = wall_clock64();
 #endif
-        while (c < c_end) {
-            run_lane(cur, b0, b1, b, x, ring);
+        const int32_t c0 = super_chunk[s];
+        const uint32_t m = uint32_t(c_end - c0);
+        uint32_t mine = 0;
+        for (;;) {
+            if (have) {
+                run_lane(cur, b0, b1, b, x, ring);
+                mine++;
+            }
             c += waves;
-            if (c < c_end) {
+            if (c >= c_end) break;
+            have = !claiming || claim_item(claim, c, bs.epoch);
+            if (have) {
                 cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
                 load_batch(cur, 0, b0);
                 load_batch(cur, kUnroll, b1);
             }
         }
+        claiming = false;
 #ifdef GLTRSV_TRACE
         if (threadIdx.x == 0) trace[(int64_t(s) * gridDim.x + blockIdx.x) * 3 + 1] = wall_clock64();
 #endif
+        bsp_count_own(bar, bs.epoch, s, m, mine, &s_done);
         if (s + 1 < S) {
-            const BarrierTicket t = barrier_arrive(bar);
-            // the matrix stream of the next superstep does not depend on x:
-            // fetch it while the other workgroups finish
+            // the next superstep's stream does not depend on x: fetch its
+            // first batches while waiting
             c = super_chunk[s + 1] + wave;
             c_end = super_chunk[s + 2];
-            cur = make_cursor(word, value, c < c_end ? chunk_base[c] : 0, c < c_end ? chunk_len[c] : 0, lane);
+            have = c < c_end;
+            cur = make_cursor(word, value, have ? chunk_base[c] : 0, have ? chunk_len[c] : 0, lane);
             load_batch(cur, 0, b0);
             load_batch(cur, kUnroll, b1);
-            if (!barrier_wait(bar, t, err, spin_limit)) return;
         }
+        if (!bsp_wait(bar, bs.epoch, s, err, spin_limit, steal_ticks,
+                      [&](int32_t ss) { steal_items(bar, alive, claim, bs.epoch, ss, c0, m, run_chunk); }))
+            return;
 #ifdef GLTRSV_TRACE
         if (threadIdx.x == 0) trace[(int64_t(s) * gridDim.x + blockIdx.x) * 3 + 2] = wall_clock64();
 #endif
@@ -513,30 +794,56 @@ __device__ __forceinline__ void wave_load(const uint32_t *__restrict__ wcol, con
 // Semi-asynchronous wave cores: gathers that returned the not-yet-computed
 // mark are read again until every lane holds a computed value.  Returns
 // false once the spin limit is hit (setting *err) or another wave failed.
-__device__ __forceinline__ bool wave_await(uint32_t c, double &g, const double *x, int32_t *err, int64_t spin_limit)
+__device__ __forceinline__ int wave_await(uint32_t c, double &g, const double *x, int32_t *err, int64_t spin_limit,
+                                          const AsyncRob &rob)
 {
     bool miss = (c & (HDR | INTL)) == 0 && static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
-    if (__ballot(miss) == 0ull) return true;
+    if (__ballot(miss) == 0ull) return kReady;
+    int64_t since = -1;   // wall clock at the first rob check
     for (int64_t spins = 1;; spins++) {
         __builtin_amdgcn_s_sleep(1);
         if (miss) {
             g = load_x(x + c);
             miss = static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
         }
-        if (__ballot(miss) == 0ull) return true;
+        if (__ballot(miss) == 0ull) return kReady;
         if (spins > spin_limit) {
             if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
+            return kFailed;
         }
-        if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        if ((spins & 255) == 0) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return kFailed;
+            if (rob.alive) {
+                const int64_t now = int64_t(wall_clock64());
+                if (since < 0) {
+                    since = now;
+                } else if (now - since > rob.rob_ticks) {
+                    if (any_not_started(rob)) return kAbandon;
+                    since = now;
+                }
+            }
+        }
     }
 }
 
+// Scalar registers of the wave-core kernels.  Measured on MI355X: with 88 or
+// more only 7 of their 256-thread workgroups are resident per CU (both the
+// compiler and the occupancy query report 8), with 80 or fewer all 8 are.
+// 64 makes the wave-core semi-asynchronous solve of an n = 1e7 system 17%
+// slower than 80 (5.70 against 4.88 ms).
+#ifndef GLTRSV_WAVE_SGPRS
+#define GLTRSV_WAVE_SGPRS 80
+#endif
+constexpr int kWaveSgprs = GLTRSV_WAVE_SGPRS;
+
+// Runs one wave-core task; returns kReady when done, or (semi-asynchronous
+// form) kAbandon / kFailed from the wait (rows stored so far are final).
 template <bool kAsync>
-__device__ __forceinline__ bool wave_task(const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr,
-                                          const double *__restrict__ wdiag, const uint32_t *__restrict__ wcol,
-                                          const double *__restrict__ wval, int64_t t0, int64_t t1, const double *b,
-                                          double *x, double *ring, int32_t *err, int64_t spin_limit)
+__device__ __forceinline__ int wave_task(const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr,
+                                         const double *__restrict__ wdiag, const uint32_t *__restrict__ wcol,
+                                         const double *__restrict__ wval, int64_t t0, int64_t t1, const double *b,
+                                         double *x, double *ring, int32_t *err, int64_t spin_limit,
+                                         const AsyncRob &rob)
 {
     const int lane = threadIdx.x & 63;
     for (int64_t t = t0; t < t1; t++) {
@@ -552,8 +859,10 @@ __device__ __forceinline__ bool wave_task(const int32_t *__restrict__ wrow, cons
             double vn, gn;
             uint32_t cn;
             wave_load(wcol, wval, base + 64 + lane, e1, x, ring, q, vn, gn, cn);
-            if constexpr (kAsync)
-                if (!wave_await(c, g, x, err, spin_limit)) return false;
+            if constexpr (kAsync) {
+                const int r = wave_await(c, g, x, err, spin_limit, rob);
+                if (r != kReady) return r;
+            }
             const double p = v * g;
             const int cnt = int(min<int64_t>(64, e1 - base));
             for (int l = 0; l < cnt; l++) acc = acc - readlane_f64(p, l);
@@ -568,62 +877,100 @@ __device__ __forceinline__ bool wave_task(const int32_t *__restrict__ wrow, cons
         }
         __builtin_amdgcn_wave_barrier();
     }
-    return true;
+    return kReady;
 }
 
-// Supersteps [s0, s1) of a wave-core plan.  With s1 - s0 > 1 the grid is
-// co-resident and the device-scope barrier separates the supersteps; a
-// single superstep per launch needs none.  The i-th wave of workgroup g is
-// slot i G + g (tasks of a superstep sorted longest first).
-__global__ __launch_bounds__(kBlock) void trsv_wave(
+// Supersteps [s0, s1) of a wave-core plan.  One superstep per launch needs
+// no synchronisation (claim = nullptr); several run as in trsv_persistent
+// (counted completion, robbing of workgroups that have not started), so no
+// co-residency is needed.  The i-th wave of workgroup g is slot i G + g
+// (tasks of a superstep sorted longest first).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))) void trsv_wave(
     const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr, const double *__restrict__ wdiag,
     const uint32_t *__restrict__ wcol, const double *__restrict__ wval, const int64_t *__restrict__ wtask,
     const int32_t *__restrict__ wsuper, int32_t s0, int32_t s1, const double *b, double *x, uint32_t *bar,
-    int32_t *err, int64_t spin_limit)
+    uint32_t *alive, uint32_t *claim, int32_t *err, int64_t spin_limit, int64_t steal_ticks, int64_t delay_ticks)
 {
     __shared__ double ring[kWavesPerBlock][kWaveRing];
+    __shared__ uint32_t s_done;
     const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
     const int32_t slot = int32_t(threadIdx.x >> 6) * int32_t(gridDim.x) + int32_t(blockIdx.x);
     double *my_ring = ring[threadIdx.x >> 6];
-    for (int32_t s = s0; s < s1; s++) {
-        for (int32_t t = wsuper[s] + slot; t < wsuper[s + 1]; t += waves)
-            wave_task<false>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring, err, spin_limit);
-        if (s + 1 < s1) {
-            const BarrierTicket tk = barrier_arrive(bar);
-            if (!barrier_wait(bar, tk, err, spin_limit)) return;
-        }
+    __shared__ AsyncRob s_norob;
+    if (threadIdx.x == 0) s_norob = AsyncRob{nullptr, 0u, 0};
+    __syncthreads();
+    auto run_task = [&](int32_t t) {
+        wave_task<false>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring, err, spin_limit,
+                         s_norob);
+    };
+    if (!claim) {   // one superstep, no other workgroup to wait for
+        for (int32_t t = wsuper[s0] + slot; t < wsuper[s0 + 1]; t += waves) run_task(t);
+        return;
+    }
+    if (threadIdx.x == 0) s_done = 0;
+    const BspStart bs = bsp_start(bar, alive, delay_ticks);
+    bool claiming = bs.robbed;
+    for (int32_t s = s0 + bs.first; s < s1; s++) {
+        const int32_t t0 = wsuper[s];
+        const uint32_t m = uint32_t(wsuper[s + 1] - t0);
+        uint32_t mine = 0;
+        for (int32_t t = t0 + slot; t < wsuper[s + 1]; t += waves)
+            if (!claiming || claim_item(claim, t, bs.epoch)) {
+                run_task(t);
+                mine++;
+            }
+        claiming = false;
+        bsp_count_own(bar, bs.epoch, s - s0, m, mine, &s_done);
+        if (!bsp_wait(bar, bs.epoch, s - s0, err, spin_limit, steal_ticks,
+                      [&](int32_t ss) { steal_items(bar, alive, claim, bs.epoch, ss, t0, m, run_task); }))
+            return;
     }
 }
 
 // Semi-asynchronous wave cores: x holds the not-yet-computed mark at the
-// start; wave w runs tasks w, w + W, ... in their global order (superstep by
-// superstep) and waits only for the values it gathers.  Progress as for
-// trsv_async: the earliest unfinished task depends only on finished tasks
-// and its wave has finished its own earlier tasks (all waves co-resident).
-__global__ __launch_bounds__(kBlock) void trsv_wave_async(
+// start; wave w (the i-th wave of workgroup g is w = 4 g + i) runs tasks
+// w, w + W, ... in their global order (superstep by superstep) and waits
+// only for the values it gathers.  Progress and the robbing of workgroups
+// that have not started as for trsv_async, with tasks in place of chunks.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))) void trsv_wave_async(
     const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr, const double *__restrict__ wdiag,
     const uint32_t *__restrict__ wcol, const double *__restrict__ wval, const int64_t *__restrict__ wtask,
-    int32_t tasks, const double *b, double *x, int32_t *err, int64_t spin_limit)
+    int32_t tasks, const double *b, double *x, int32_t *err, int64_t spin_limit, unsigned long long *ticket,
+    uint32_t *alive, unsigned long long *vnext, int64_t rob_ticks, int64_t delay_ticks)
 {
     __shared__ double ring[kWavesPerBlock][kWaveRing];
+    // the robbing context lives in LDS: it is only read on the rare slow
+    // path, and keeping it in scalar registers across the subtraction loop
+    // costs residency (see kWaveSgprs)
+    __shared__ AsyncRob s_rob, s_norob;
+    const uint32_t epoch = async_start(ticket, alive, delay_ticks);
+    if (threadIdx.x == 0) {
+        s_rob = AsyncRob{alive, epoch, rob_ticks};
+        s_norob = AsyncRob{nullptr, 0u, 0};
+    }
+    __syncthreads();
     const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
-    const int32_t w = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
     double *my_ring = ring[threadIdx.x >> 6];
-    for (int32_t t = w; t < tasks; t += waves)
-        if (!wave_task<true>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring, err, spin_limit))
-            return;
+    auto run = [&](int32_t t, const AsyncRob &r) {
+        return wave_task<true>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring, err, spin_limit,
+                               r);
+    };
+    for (int32_t t = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6); t < tasks;) {
+        const int r = run(t, s_rob);
+        if (r == kFailed) return;
+        if (r == kReady) {
+            t += waves;
+            continue;
+        }
+        const int64_t o = rob_item(s_rob, vnext, tasks, t);
+        if (o >= 0 && run(int32_t(o), s_norob) == kFailed) return;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Semi-asynchronous solve: no barriers.  Wave w runs chunks w, w + W, w + 2W,
-// ... in order (chunks are numbered superstep by superstep), and a lane waits
-// only for the columns it reads (await_batch).  Progress: the earliest
-// unfinished chunk depends only on chunks of earlier supersteps, which are
-// finished, and its wave has finished its own earlier chunks, so it is
-// running it; hence every chunk completes provided all W waves are resident
-// (the grid is sized to the device's co-resident capacity, as for the
-// persistent kernel, and a wave kept from starting ends the solve with the
-// spin-limit error instead of a hang).
+// Semi-asynchronous solve: no barriers.  Chunks are numbered superstep by
+// superstep and run with per-row readiness (await_batch): a lane gathering
+// a column that still holds the not-computed mark reads it again.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void fill_unready(unsigned long long *x, int64_t n)
 {
@@ -631,21 +978,49 @@ __global__ __launch_bounds__(kBlock) void fill_unready(unsigned long long *x, in
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) x[i] = kUnready;
 }
 
+// Static order with robbing.  Wave w (w = 4 g + i for the i-th wave of
+// workgroup g: neighbouring chunks on one CU, as their gathers overlap) runs
+// chunks w, w + W, w + 2W, ... in order (W waves), so every wave is only a
+// little ahead of the others and no claims are made.  The earliest
+// unfinished chunk depends only on finished chunks and its wave has finished
+// its earlier ones, so the solve advances as long as that wave runs -- which
+// needs every workgroup to have started.  Other work on the device can keep
+// workgroups from starting, so a wave that has waited rob_ticks for values
+// while some workgroup has not started abandons its chunk (the rows it
+// stored are final: every x_i has one value, so running a chunk again
+// stores the same bits), runs the earliest chunk of a not-started workgroup
+// that no one has taken yet if that chunk comes before its own (taking it
+// by advancing that wave's robbed-prefix word), and then runs its own chunk
+// again.  A robbed chunk depends only on chunks before it, which are done or
+// running, so it completes; the solve therefore advances whenever any
+// workgroup runs.  A late workgroup runs all of its chunks (robbed ones a
+// second time, with the same bits).
 __global__ __launch_bounds__(kBlock) void trsv_async(const uint32_t *__restrict__ word,
                                                      const double *__restrict__ value,
                                                      const int64_t *__restrict__ chunk_base,
                                                      const int32_t *__restrict__ chunk_len, int32_t chunks,
-                                                     const double *b, double *x, int32_t *err, int64_t spin_limit)
+                                                     const double *b, double *x, int32_t *err, int64_t spin_limit,
+                                                     unsigned long long *ticket, uint32_t *alive,
+                                                     unsigned long long *vnext, int64_t rob_ticks, int64_t delay_ticks)
 {
     __shared__ double ring[kRing + 1][kBlock];
-    const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
     const int lane = threadIdx.x & 63;
-    for (int32_t c = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6); c < chunks; c += waves) {
+    const AsyncRob rob = {alive, async_start(ticket, alive, delay_ticks), rob_ticks};
+    const int32_t W = int32_t(gridDim.x) * kWavesPerBlock;
+    auto run_chunk = [&](int32_t c, AsyncRob r) {
         const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
         Batch<kUnroll> b0, b1;
         load_batch(cur, 0, b0);
         load_batch(cur, kUnroll, b1);
-        run_lane<kUnroll, true>(cur, b0, b1, b, x, ring, err, spin_limit);
+        return run_lane<kUnroll, true>(cur, b0, b1, b, x, ring, err, spin_limit, r);
+    };
+    for (int32_t c = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6); c < chunks;) {
+        if (run_chunk(c, rob)) {
+            c += W;
+            continue;
+        }
+        const int64_t r = rob_item(rob, vnext, chunks, c);
+        if (r >= 0) run_chunk(int32_t(r), no_rob());
     }
 }
 
@@ -685,15 +1060,16 @@ __device__ __forceinline__ void gather_multi(const Batch<kUnrollWide> &B, const 
 }
 
 template <int R>
-__device__ __forceinline__ void await_multi(const Batch<kUnrollWide> &B, double (&g)[kUnrollWide][R], const double *x,
-                                            int64_t ld, int32_t *err, int64_t spin_limit)
+__device__ __forceinline__ int await_multi(const Batch<kUnrollWide> &B, double (&g)[kUnrollWide][R], const double *x,
+                                           int64_t ld, int32_t *err, int64_t spin_limit, AsyncRob rob)
 {
     bool miss = false;
 #pragma unroll
     for (int j = 0; j < kUnrollWide; j++)
 #pragma unroll
         for (int r = 0; r < R; r++) miss |= unready(B.w[j], g[j][r]);
-    if (__ballot(miss) == 0ull) return;
+    if (__ballot(miss) == 0ull) return kReady;
+    int64_t since = -1;   // wall clock at the first rob check
     for (int64_t spins = 1;; spins++) {
         __builtin_amdgcn_s_sleep(1);
         miss = false;
@@ -704,12 +1080,23 @@ __device__ __forceinline__ void await_multi(const Batch<kUnrollWide> &B, double 
                 if (unready(B.w[j], g[j][r])) g[j][r] = load_x(x + int64_t(B.w[j]) * ld + r);
                 miss |= unready(B.w[j], g[j][r]);
             }
-        if (__ballot(miss) == 0ull) return;
+        if (__ballot(miss) == 0ull) return kReady;
         if (spins > spin_limit) {
             if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
+            return kFailed;
         }
-        if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+        if ((spins & 255) == 0) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return kFailed;
+            if (rob.alive) {
+                const int64_t now = int64_t(wall_clock64());
+                if (since < 0) {
+                    since = now;
+                } else if (now - since > rob.rob_ticks) {
+                    if (any_not_started(rob)) return kAbandon;
+                    since = now;
+                }
+            }
+        }
     }
 }
 
@@ -759,8 +1146,8 @@ __device__ __forceinline__ void process_multi(const Batch<kUnrollWide> &B, const
 }
 
 template <int R>
-__device__ __forceinline__ void run_lane_multi(const LaneCursor &cur, const double *b, double *x, int64_t ld,
-                                               MultiRing<R> ring, int32_t *err, int64_t spin_limit)
+__device__ __forceinline__ bool run_lane_multi(const LaneCursor &cur, const double *b, double *x, int64_t ld,
+                                               MultiRing<R> ring, int32_t *err, int64_t spin_limit, AsyncRob rob)
 {
     MultiState<R> st;
 #pragma unroll
@@ -778,7 +1165,7 @@ __device__ __forceinline__ void run_lane_multi(const LaneCursor &cur, const doub
     for (int32_t t0 = 0; t0 < cur.len; t0 += kUnrollWide) {
         load_batch(cur, t0 + kUnrollWide, nxt);
         gather_multi<R>(nxt, b, x, ld, gnxt);
-        await_multi<R>(now, gnow, x, ld, err, spin_limit);
+        if (await_multi<R>(now, gnow, x, ld, err, spin_limit, rob) == kAbandon) return false;
         process_multi<R>(now, gnow, st, x, ld, ring);
         now = nxt;
 #pragma unroll
@@ -789,30 +1176,49 @@ __device__ __forceinline__ void run_lane_multi(const LaneCursor &cur, const doub
     if (st.cur >= 0)
 #pragma unroll
         for (int r = 0; r < R; r++) store_x(x + int64_t(st.cur) * ld + r, st.acc[r] / st.diag);
+    return true;
 }
 
+// Static order with robbing, as trsv_async; one wave per workgroup (wave g
+// runs chunks g, g + G, ...), whose R-column ring fills a quarter of the
+// LDS at R = 4.
 template <int R>
 __global__ __launch_bounds__(64) void trsv_async_multi(const uint32_t *__restrict__ word,
-                                                       const double *__restrict__ value,
-                                                       const int64_t *__restrict__ chunk_base,
-                                                       const int32_t *__restrict__ chunk_len, int32_t chunks,
-                                                       const double *b, double *x, int64_t ld, int32_t *err,
-                                                       int64_t spin_limit)
+                                                           const double *__restrict__ value,
+                                                           const int64_t *__restrict__ chunk_base,
+                                                           const int32_t *__restrict__ chunk_len, int32_t chunks,
+                                                           const double *b, double *x, int64_t ld, int32_t *err,
+                                                           int64_t spin_limit, unsigned long long *ticket,
+                                                           uint32_t *alive, unsigned long long *vnext,
+                                                           int64_t rob_ticks, int64_t delay_ticks)
 {
     __shared__ double ring[kRing + 1][R][64];
     const int lane = threadIdx.x & 63;
-    for (int32_t c = int32_t(blockIdx.x); c < chunks; c += int32_t(gridDim.x)) {
+    const AsyncRob rob = {alive, async_start(ticket, alive, delay_ticks), rob_ticks};
+    const int32_t W = int32_t(gridDim.x);
+    auto run_chunk = [&](int32_t c, AsyncRob r) {
         const LaneCursor cur = make_cursor(word, value, chunk_base[c], chunk_len[c], lane);
-        run_lane_multi<R>(cur, b, x, ld, ring, err, spin_limit);
+        return run_lane_multi<R>(cur, b, x, ld, ring, err, spin_limit, r);
+    };
+    for (int32_t c = int32_t(blockIdx.x); c < chunks;) {
+        if (run_chunk(c, rob)) {
+            c += W;
+            continue;
+        }
+        const int64_t r = rob_item(rob, vnext, chunks, c);
+        if (r >= 0) run_chunk(int32_t(r), no_rob());
     }
 }
 
 template __global__ void trsv_async_multi<1>(const uint32_t *, const double *, const int64_t *, const int32_t *,
-                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t);
+                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t,
+                                             unsigned long long *, uint32_t *, unsigned long long *, int64_t, int64_t);
 template __global__ void trsv_async_multi<2>(const uint32_t *, const double *, const int64_t *, const int32_t *,
-                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t);
+                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t,
+                                             unsigned long long *, uint32_t *, unsigned long long *, int64_t, int64_t);
 template __global__ void trsv_async_multi<4>(const uint32_t *, const double *, const int64_t *, const int32_t *,
-                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t);
+                                             int32_t, const double *, double *, int64_t, int32_t *, int64_t,
+                                             unsigned long long *, uint32_t *, unsigned long long *, int64_t, int64_t);
 
 // ---------------------------------------------------------------------------
 // Batched solve: many independent systems in one launch.
@@ -1137,25 +1543,42 @@ __global__ __launch_bounds__(kBlock) void trsv_batched_async(const SysDesc *__re
 // core is small (a wavefront schedule's task is one row), so claiming tasks
 // with atomics would cost more than running them; instead the host merges
 // the systems' tasks into one global order (each system's own order kept)
-// and wave w runs global tasks
-// w, w + W, ... in order.  Progress as for trsv_wave_async: the earliest
-// unfinished task depends only on earlier tasks of its system, which come
-// earlier in the global order and are finished, and its wave has finished
-// its own earlier tasks (all waves co-resident).
-__global__ __launch_bounds__(kBlock) void trsv_batched_wave_async(const SysDesc *__restrict__ sys,
+// and wave w runs global tasks w, w + W, ... in order.  Progress as for
+// trsv_wave_async: the earliest unfinished task depends only on earlier
+// tasks of its system, which come earlier in the global order and are
+// finished, and its wave has finished its own earlier tasks; waves blocked
+// for long while some workgroup has not started rob it (see trsv_async).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))) void trsv_batched_wave_async(const SysDesc *__restrict__ sys,
                                                                   const int32_t *__restrict__ gsys,
                                                                   const int32_t *__restrict__ gtask, int64_t ntasks,
-                                                                  int32_t *err, int64_t spin_limit)
+                                                                  int32_t *err, int64_t spin_limit,
+                                                                  unsigned long long *ticket, uint32_t *alive,
+                                                                  unsigned long long *vnext, int64_t rob_ticks)
 {
     __shared__ double ring[kWavesPerBlock][kWaveRing];
+    __shared__ AsyncRob s_rob, s_norob;   // in LDS, as in trsv_wave_async
+    const uint32_t epoch = async_start(ticket, alive, 0);
+    if (threadIdx.x == 0) {
+        s_rob = AsyncRob{alive, epoch, rob_ticks};
+        s_norob = AsyncRob{nullptr, 0u, 0};
+    }
+    __syncthreads();
     const int64_t waves = int64_t(gridDim.x) * kWavesPerBlock;
-    const int64_t w = int64_t(blockIdx.x) * kWavesPerBlock + int64_t(threadIdx.x >> 6);
-    for (int64_t g = w; g < ntasks; g += waves) {
+    auto run = [&](int64_t g, const AsyncRob &r) {
         const SysDesc &d = sys[gsys[g]];
         const int32_t t = gtask[g];
-        if (!wave_task<true>(d.wrow, d.wptr, d.wdiag, d.wcol, d.wval, d.wtask[t], d.wtask[t + 1], d.b, d.x,
-                             ring[threadIdx.x >> 6], err, spin_limit))
-            return;   // a wait ran out: *err is set, the other waves leave too
+        return wave_task<true>(d.wrow, d.wptr, d.wdiag, d.wcol, d.wval, d.wtask[t], d.wtask[t + 1], d.b, d.x,
+                               ring[threadIdx.x >> 6], err, spin_limit, r);
+    };
+    for (int64_t g = int64_t(blockIdx.x) * kWavesPerBlock + int64_t(threadIdx.x >> 6); g < ntasks;) {
+        const int r = run(g, s_rob);
+        if (r == kFailed) return;   // a wait ran out: *err is set, the other waves leave too
+        if (r == kReady) {
+            g += waves;
+            continue;
+        }
+        const int64_t o = rob_item(s_rob, vnext, ntasks, g);
+        if (o >= 0 && run(o, s_norob) == kFailed) return;
     }
 }
 

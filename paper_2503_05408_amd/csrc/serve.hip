@@ -41,10 +41,16 @@ struct Request {
 
 struct Slot {
     bool busy = false;
-    bool fresh = false;     // admitted since the last launch
+    bool fresh = false;     // descriptor changed since the last launch
     bool cancel = false;    // withdrawn: dropped at the next quantum boundary
-    Request req;
+    Request req;            // valid while busy only
     int32_t done_off = 0;
+    // copied from the plan at admission, so a slot never reads a plan after
+    // its request has left it (the caller may destroy the plan then)
+    int32_t S = 0;          // supersteps = done counters held in the arena
+    int64_t n = 0;
+    int64_t chunks = 0;
+    int64_t widest = 0;     // chunks of the plan's widest superstep
 };
 
 // First-fit allocator of per-superstep done counters inside one device array.
@@ -101,7 +107,8 @@ struct gltrsv_server {
     CounterArena *arena = nullptr;
 
     std::mutex mu;
-    std::condition_variable cv;
+    std::condition_variable cv;        // wakes the worker (new request, stop)
+    std::condition_variable cv_done;   // wakes cancel callers (a slot was released)
     std::deque<Request> queue;
     std::vector<Slot> slots;
     std::vector<std::pair<uint64_t, int64_t>> completed;
@@ -140,21 +147,22 @@ int run_quantum(gltrsv_server *sv, int32_t used, int32_t busy)
         sl.fresh = false;
         HIP_TRY(hipMemcpyAsync(sv->d_desc + i, sv->h_desc + i, sizeof(dev::SysDesc), hipMemcpyHostToDevice,
                                sv->stream));
+        if (!sl.busy) continue;   // an emptied descriptor (S = 0) reads as finished
         HIP_TRY(hipMemsetAsync(sv->d_state + size_t(i) * dev::kStateStride, 0, sizeof(unsigned long long),
                                sv->stream));
-        HIP_TRY(hipMemsetAsync(sv->d_done + sl.done_off, 0, sizeof(uint32_t) * size_t(sl.req.plan->S), sv->stream));
-        if (sv->opts.async_exec && sl.busy && sl.req.plan->n > 0) {
+        HIP_TRY(hipMemsetAsync(sv->d_done + sl.done_off, 0, sizeof(uint32_t) * size_t(std::max(1, sl.S)),
+                               sv->stream));
+        if (sv->opts.async_exec && sl.n > 0) {
             // semi-asynchronous: x starts as the not-yet-computed mark
-            const int64_t n = sl.req.plan->n;
-            const unsigned blocks = unsigned(std::min<int64_t>(1024, (n + dev::kBlock - 1) / dev::kBlock));
+            const unsigned blocks = unsigned(std::min<int64_t>(1024, (sl.n + dev::kBlock - 1) / dev::kBlock));
             hipLaunchKernelGGL(dev::fill_unready, dim3(blocks), dim3(dev::kBlock), 0, sv->stream,
-                               reinterpret_cast<unsigned long long *>(sl.req.x), n);
+                               reinterpret_cast<unsigned long long *>(sl.req.x), sl.n);
         }
     }
     HIP_TRY(hipMemsetAsync(sv->d_finished, 0, 2 * sizeof(uint32_t), sv->stream));
     int64_t widest = 0;
     for (int32_t i = 0; i < used; i++)
-        if (sv->slots[i].busy) widest = std::max(widest, sv->slots[i].req.plan->widest);
+        if (sv->slots[i].busy) widest = std::max(widest, sv->slots[i].widest);
     const int64_t quantum = int64_t(sv->opts.quantum_us * 100.0);   // 100 MHz wall clock
     if (sv->opts.async_exec)
         hipLaunchKernelGGL(dev::trsv_batched_async, dim3(unsigned(sv->grid)), dim3(dev::kBlock), 0, sv->stream,
@@ -176,19 +184,27 @@ int run_quantum(gltrsv_server *sv, int32_t used, int32_t busy)
     return GLTRSV_OK;
 }
 
-// Frees slot i of a withdrawn request (caller holds the lock, no launch in
-// flight): its descriptor is emptied, so the next launch sees it finished.
-void release_slot(gltrsv_server *sv, int32_t i)
+// Frees slot i (caller holds the lock, no launch in flight): its budget and
+// counters return, its descriptor is emptied (the next launch sees it
+// finished) and its request is forgotten; the plan is not touched.
+void free_slot(gltrsv_server *sv, int32_t i)
 {
     Slot &sl = sv->slots[i];
-    sv->stats.cancelled++;
     sv->inflight_bytes -= sl.req.bytes;
-    sv->arena->give(sl.done_off, std::max(1, sl.req.plan->S));
+    sv->arena->give(sl.done_off, std::max(1, sl.S));
     sl.busy = false;
     sl.cancel = false;
-    sv->h_desc[i].S = 0;
-    sv->h_desc[i].nchunks = 0;
+    sl.req = Request();
+    std::memset(&sv->h_desc[i], 0, sizeof(dev::SysDesc));
     sl.fresh = true;
+}
+
+// A withdrawn request leaves its slot; cancel callers waiting for it wake up.
+void release_slot(gltrsv_server *sv, int32_t i)
+{
+    sv->stats.cancelled++;
+    free_slot(sv, i);
+    sv->cv_done.notify_all();
 }
 
 void worker_main(gltrsv_server *sv)
@@ -224,6 +240,10 @@ void worker_main(gltrsv_server *sv)
                 sl.cancel = false;
                 sl.req = r;
                 sl.done_off = off;
+                sl.S = r.plan->S;
+                sl.n = r.plan->n;
+                sl.chunks = r.plan->chunks;
+                sl.widest = r.plan->widest;
                 dev::SysDesc &d = sv->h_desc[free_slot];
                 d.word = r.plan->d_word;
                 d.value = r.plan->d_value;
@@ -261,11 +281,13 @@ void worker_main(gltrsv_server *sv)
             for (auto &sl : sv->slots)
                 if (sl.busy) {
                     sl.busy = false;
+                    sl.req = Request();
                     sv->stats.failed++;
                 }
             sv->stats.failed += int64_t(sv->queue.size());
             sv->queue.clear();
             sv->inflight_bytes = 0;
+            sv->cv_done.notify_all();
             return;
         }
         for (int32_t i = 0; i < used; i++) {
@@ -275,16 +297,11 @@ void worker_main(gltrsv_server *sv)
             const int64_t hi = int64_t(sv->h_state[i] >> 32);
             if (sl.cancel) {
                 release_slot(sv, i);   // withdrawn during the quantum: never reported
-            } else if (sv->opts.async_exec ? hi >= sl.req.plan->chunks : hi >= sl.req.plan->S) {
+            } else if (sv->opts.async_exec ? hi >= sl.chunks : hi >= sl.S) {
                 sv->completed.emplace_back(sl.req.ticket, t);
                 sv->stats.completed++;
-                sv->stats.rows_completed += sl.req.plan->n;
-                sv->inflight_bytes -= sl.req.bytes;
-                sv->arena->give(sl.done_off, std::max(1, sl.req.plan->S));
-                sl.busy = false;
-                sv->h_desc[i].S = 0;
-                sv->h_desc[i].nchunks = 0;
-                sl.fresh = true;   // upload the emptied descriptor with the next launch
+                sv->stats.rows_completed += sl.n;
+                free_slot(sv, i);   // the emptied descriptor goes up with the next launch
             }
         }
     }
@@ -413,7 +430,7 @@ int gltrsv_server_get_stats(gltrsv_server *sv, gltrsv_server_stats *out)
 int gltrsv_server_cancel(gltrsv_server *sv, uint64_t ticket)
 {
     if (!sv) return set_error(GLTRSV_EINVAL, "null server");
-    std::lock_guard<std::mutex> g(sv->mu);
+    std::unique_lock<std::mutex> lk(sv->mu);
     for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
         if (it->ticket == ticket) {
             sv->inflight_bytes -= it->bytes;
@@ -421,11 +438,17 @@ int gltrsv_server_cancel(gltrsv_server *sv, uint64_t ticket)
             sv->queue.erase(it);
             return GLTRSV_OK;
         }
-    for (Slot &sl : sv->slots)
+    for (size_t i = 0; i < sv->slots.size(); i++) {
+        Slot &sl = sv->slots[i];
         if (sl.busy && !sl.cancel && sl.req.ticket == ticket) {
+            // on the device: the worker drops it at the next quantum boundary;
+            // wait for that, so b, x and the plan are free to go on return
             sl.cancel = true;
+            sv->cv.notify_one();
+            sv->cv_done.wait(lk, [&] { return !sl.busy || sl.req.ticket != ticket || sv->failure != 0; });
             return GLTRSV_OK;
         }
+    }
     return set_error(GLTRSV_ENOENT, "no pending request with this ticket");
 }
 

@@ -140,3 +140,57 @@ def test_cancel_queued_and_running_requests(async_exec):
         assert oracle.same_bits(xs[0].cpu().numpy(), want_s)
         assert oracle.same_bits(xs[2].cpu().numpy(), want_s)
         assert oracle.same_bits(xl[1].cpu().numpy(), want_l)
+
+
+@pytest.mark.parametrize("async_exec", [0, 1])
+def test_plans_and_vectors_freed_as_their_tickets_complete(async_exec):
+    # the server reads nothing of a request after its ticket is polled (or its
+    # cancel returned): each plan is destroyed, and its b and x released,
+    # the moment its last ticket comes back, while the other requests keep
+    # running; their results stay exact
+    import torch
+    ms = gen.batch_mix(12, seed=gen.SEED_BASE + 1300, lo_exp=2.0, hi_exp=4.5)
+    plans = [B.Plan(m, B.gpu_opts() if i % 2 else B.default_opts(schedule_kind=B.SCHED_WAVEFRONT))
+             for i, m in enumerate(ms)]
+    want = {}
+    owner = {}
+    left = {i: 0 for i in range(len(ms))}
+    with B.Server(quantum_us=60.0, max_slots=8, async_exec=async_exec) as sv:
+        for r in range(48):
+            i = r % len(ms)
+            b = gen.rhs_uniform(ms[i].n, 3000 + r)
+            bd = torch.from_numpy(b).cuda()
+            xd = torch.full((ms[i].n,), float("nan"), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            tk = sv.submit(plans[i], bd, xd)
+            assert tk is not None
+            want[tk] = (oracle.solve(ms[i], b), xd)
+            owner[tk] = i
+            left[i] += 1
+        del bd, xd
+        # withdraw one request on the device, then free its x at once
+        victim = next(iter(want))
+        if sv.cancel(victim):
+            left[owner[victim]] -= 1
+            del want[victim]
+        t0 = time.time()
+        checked = 0
+        while want and time.time() - t0 < 60:
+            for tk, _ in sv.poll():
+                w, xd = want.pop(tk)
+                assert oracle.same_bits(xd.cpu().numpy(), w), tk
+                checked += 1
+                i = owner[tk]
+                left[i] -= 1
+                if left[i] == 0 and plans[i] is not None:
+                    plans[i].close()           # destroyed while the others run
+                    plans[i] = None
+                del xd
+            time.sleep(0.0002)
+        assert not want, sv.stats()
+        st = sv.stats()
+        assert st["failed"] == 0 and st["inflight_bytes"] == 0, st
+    for p in plans:
+        if p is not None:
+            p.close()
+    assert checked >= 40
