@@ -400,6 +400,26 @@ int gltrsv_batch_destroy(gltrsv_batch *batch);
 int gltrsv_solve_batched(gltrsv_plan *const *plans, const double *const *b, double *const *x, int32_t count,
                          void *stream);
 
+/* gltrsv_solve_batched for callers that cannot allocate (code that must not
+ * call hipMalloc, serving loops that allocate nothing per request): the same
+ * kernels, launch configuration and results, with the batch's device state
+ * (system descriptors, superstep state words, per-superstep done counters,
+ * finished and error words) in a fixed device array that the library holds
+ * for each GPU it runs on until the process ends, instead of buffers it
+ * allocates per call.  The call allocates no memory on the device or the
+ * host (no hipMalloc, hipFree or hipHostMalloc).  Limits: at most 1,024
+ * systems with n > 0 and at most 4 MiB of state (256 bytes per system plus
+ * 4 bytes per superstep of every system, about 9.4e5 supersteps in all);
+ * a larger batch returns GLTRSV_ERANGE.  Arguments, vector rules (b[i] may
+ * equal x[i]; no other overlap), synchronisation of `stream` and error codes
+ * as gltrsv_solve_batched.  All calls on one GPU share that GPU's array:
+ * calls from several host threads of a process are serialised by the
+ * library (each holds the array until its solve has finished); the array
+ * keeps the last call's contents, which the next call clears on the device
+ * before use. */
+int gltrsv_solve_batched_noalloc(gltrsv_plan *const *plans, const double *const *b, double *const *x,
+                                 int32_t count, void *stream);
+
 /* ---------------------------------------------------------------- serving */
 /* Continuous batching of solve requests against resident plans.  A worker
  * thread owned by the server runs the batched kernel in time quanta; every

@@ -124,6 +124,7 @@ SIGNATURES = {
     "gltrsv_batch_info": ([P, P, P], i32),
     "gltrsv_batch_destroy": ([P], i32),
     "gltrsv_solve_batched": ([P, P, P, i32, P], i32),
+    "gltrsv_solve_batched_noalloc": ([P, P, P, i32, P], i32),
     "gltrsv_default_server_opts": ([P], None),
     "gltrsv_server_create": ([P, P], i32),
     "gltrsv_server_submit": ([P, P, P, P, P], i32),
@@ -534,6 +535,17 @@ def solve_batched(plans, bs, xs, stream=None):
     bp = _ptr_array(bs, lambda i: plans[i].n)
     xp = _ptr_array(xs, lambda i: plans[i].n)
     _check(load().gltrsv_solve_batched(handles, bp, xp, len(plans), _stream_ptr(stream)), "gltrsv_solve_batched")
+    return xs
+
+
+def solve_batched_noalloc(plans, bs, xs, stream=None):
+    """As solve_batched, with the batch state in the library's fixed device
+    array instead of per-call allocations (synchronises the stream)."""
+    handles = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    bp = _ptr_array(bs, lambda i: plans[i].n)
+    xp = _ptr_array(xs, lambda i: plans[i].n)
+    _check(load().gltrsv_solve_batched_noalloc(handles, bp, xp, len(plans), _stream_ptr(stream)),
+           "gltrsv_solve_batched_noalloc")
     return xs
 
 

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1394,6 +1395,161 @@ int gltrsv_solve_batched(gltrsv_plan *const *plans, const double *const *b, doub
         rc = set_error(GLTRSV_ETIMEDOUT, "batched solve: a wave found no work for longer than the idle limit");
     gltrsv_batch_destroy(bt);
     return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched solve without allocation (gltrsv_solve_batched_noalloc): the device
+// state of gltrsv_solve_batched -- system descriptors, superstep state words,
+// per-superstep done counters, the finished and error words -- lives in one
+// fixed file-scope device array instead of buffers the library allocates.
+// Host code never uses the array's name as an address: the address is taken
+// once per device with hipGetSymbolAddress and kept.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = size_t(4) << 20;
+constexpr int32_t kScratchSystems = 1024;   // descriptors staged in host memory
+constexpr int kScratchDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchSlot {
+    std::mutex mu;                          // one call at a time per device
+    unsigned char *ptr = nullptr;           // device address of `scratch`
+    dev::SysDesc desc[kScratchSystems];     // host staging of the descriptors
+};
+
+std::mutex g_scratch_setup;
+ScratchSlot g_scratch[kScratchDevices];
+
+// The device's scratch slot; its address is looked up on the first call on
+// that device (with the device current).
+int scratch_slot(int device, ScratchSlot **out)
+{
+    if (device < 0 || device >= kScratchDevices)
+        return set_error(GLTRSV_ENOTSUP, "device index beyond the no-allocation table");
+    ScratchSlot &sl = g_scratch[device];
+    std::lock_guard<std::mutex> g(g_scratch_setup);
+    if (!sl.ptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(GLTRSV_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        sl.ptr = static_cast<unsigned char *>(p);
+    }
+    *out = &sl;
+    return GLTRSV_OK;
+}
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// The rule of check_batch_vectors for BSP batches, pairwise, without
+// allocating: x of one system shares no byte with another system's b or x,
+// and b may equal x but not overlap it partly.
+int check_vectors_noalloc(gltrsv_plan *const *plans, const double *const *b, double *const *x, int32_t count)
+{
+    for (int32_t i = 0; i < count; i++) {
+        if (!plans[i] || plans[i]->n == 0) continue;
+        const size_t li = sizeof(double) * size_t(plans[i]->n);
+        if (!b[i] || !x[i]) return set_error(GLTRSV_EINVAL, "null vector in batch");
+        if (b[i] != x[i] && overlap(b[i], li, x[i], li))
+            return set_error(GLTRSV_EINVAL, "b and x of a system overlap without being equal");
+        for (int32_t j = 0; j < count; j++) {
+            if (j == i || !plans[j] || plans[j]->n == 0 || !b[j] || !x[j]) continue;
+            const size_t lj = sizeof(double) * size_t(plans[j]->n);
+            if (overlap(x[i], li, b[j], lj) || overlap(x[i], li, x[j], lj))
+                return set_error(GLTRSV_EINVAL, "a batch's x overlaps another vector");
+        }
+    }
+    return GLTRSV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gltrsv_solve_batched_noalloc(gltrsv_plan *const *plans, const double *const *b, double *const *x, int32_t count,
+                                 void *stream)
+{
+    if (!plans || count < 0 || (count > 0 && (!b || !x))) return set_error(GLTRSV_EINVAL, "bad batch arguments");
+    int dev_id = 0;
+    HIP_TRY(hipGetDevice(&dev_id));
+    int32_t systems = 0, ndone = 0;
+    int64_t chunks = 0, widest = 0;
+    for (int32_t i = 0; i < count; i++) {
+        if (!plans[i]) return set_error(GLTRSV_EINVAL, "null plan in batch");
+        if (plans[i]->device != dev_id) return set_error(GLTRSV_EINVAL, "plans of a batch must live on the current device");
+        if (plans[i]->n == 0) continue;
+        systems++;
+        if (int64_t(ndone) + plans[i]->S > INT32_MAX) return set_error(GLTRSV_ERANGE, "too many supersteps");
+        ndone += plans[i]->S;
+        chunks += plans[i]->chunks;
+        widest = std::max(widest, plans[i]->widest);
+    }
+    if (int rc = check_vectors_noalloc(plans, b, x, count)) return rc;
+    if (systems == 0) return GLTRSV_OK;
+    // scratch layout: descriptors | state words | done counters | finished[2] | error word
+    const size_t off_state = round_up(sizeof(dev::SysDesc) * size_t(systems), 256);
+    const size_t off_done = off_state + round_up(sizeof(unsigned long long) * dev::kStateStride * size_t(systems), 256);
+    const size_t off_fin = off_done + round_up(sizeof(uint32_t) * size_t(ndone), 256);
+    const size_t off_err = off_fin + 256;
+    const size_t need = off_err + 256;
+    if (systems > kScratchSystems || need > kScratchBytes)
+        return set_error(GLTRSV_ERANGE, "batch too large for the no-allocation scratch (" + std::to_string(systems) +
+                                            " systems, " + std::to_string(need) + " bytes; at most " +
+                                            std::to_string(kScratchSystems) + " systems and " +
+                                            std::to_string(kScratchBytes) + " bytes)");
+    ScratchSlot *sl = nullptr;
+    if (int rc = scratch_slot(dev_id, &sl)) return rc;
+    std::lock_guard<std::mutex> g(sl->mu);
+    int per_cu = 0, cus = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dev::trsv_batched, dev::kBlock, 0));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
+    int32_t off = 0, k = 0;
+    for (int32_t i = 0; i < count; i++) {
+        const gltrsv_plan *pl = plans[i];
+        if (pl->n == 0) continue;
+        dev::SysDesc &d = sl->desc[k++];
+        std::memset(&d, 0, sizeof(d));
+        d.word = pl->d_word;
+        d.value = pl->d_value;
+        d.chunk_base = pl->d_chunk_base;
+        d.chunk_len = pl->d_chunk_len;
+        d.super_chunk = pl->d_super_chunk;
+        d.b = b[i];
+        d.x = x[i];
+        d.S = pl->S;
+        d.done_off = off;
+        d.nchunks = int32_t(pl->chunks);
+        d.window = dev::async_window(pl->chunks, pl->S);
+        d.n = pl->n;
+        off += pl->S;
+    }
+    unsigned char *base = sl->ptr;
+    auto *d_desc = reinterpret_cast<dev::SysDesc *>(base);
+    auto *d_state = reinterpret_cast<unsigned long long *>(base + off_state);
+    auto *d_done = reinterpret_cast<uint32_t *>(base + off_done);
+    auto *d_fin = reinterpret_cast<uint32_t *>(base + off_fin);
+    auto *d_err = reinterpret_cast<int32_t *>(base + off_err);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(d_desc, sl->desc, sizeof(dev::SysDesc) * size_t(systems), hipMemcpyHostToDevice, st));
+    // the array keeps the previous call's contents: the reset kernel clears
+    // the state words, the done counters and the finished and error words
+    hipLaunchKernelGGL(dev::batch_reset, dim3(unsigned(std::max(1, (systems + dev::kBlock - 1) / dev::kBlock))),
+                       dim3(dev::kBlock), 0, st, d_state, d_done, systems, ndone, d_fin, d_err);
+    int grid = std::max(1, per_cu * cus);
+    grid = int(std::max<int64_t>(1, std::min<int64_t>(grid, (chunks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
+    const int32_t keep = dev::keep_waves_for(widest, 1, grid);
+    hipLaunchKernelGGL(dev::trsv_batched, dim3(unsigned(grid)), dim3(dev::kBlock), 0, st, d_desc, systems, d_state,
+                       d_done, d_fin, d_err, int64_t(1000000000), int32_t(1), systems, int64_t(0), keep);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    int32_t e = 0;
+    HIP_TRY(hipMemcpy(&e, d_err, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (e) return set_error(GLTRSV_ETIMEDOUT, "batched solve: a wave found no work for longer than the idle limit");
+    return GLTRSV_OK;
 }
 
 }  // extern "C"
