@@ -116,8 +116,9 @@ typedef struct gltrsv_plan_opts {
                                order for gltrsv_solve_unordered (the
                                no-reorder comparison of Sec. 5 / Table 7.3);
                                12 nnz + 12 n more device bytes                */
-    int32_t block_size;     /* device threads per workgroup (64..1024, a
-                               multiple of 64); 0 = library default           */
+    int32_t block_size;     /* device threads per workgroup: 0 or 256 (the
+                               kernels are compiled for 256-thread
+                               workgroups; any other value is ENOTSUP)       */
     int32_t grid_blocks;    /* workgroups of the persistent kernel;
                                0 = all that can be co-resident (<= 2048)      */
     int32_t cooperative;    /* 1: launch the kernels whose workgroups wait
@@ -183,7 +184,16 @@ typedef struct gltrsv_plan_opts {
                                larger of the critical path -- rows of a task
                                one after another at 0.18 us per entry, a
                                parent in another task adding 1.5 us -- and
-                               all entries at 4e4 entries/us, plus 10 us)    */
+                               all entries at 4e4 entries/us, plus 10 us),
+                               2 = one workgroup (gltrsv_solve_local): the
+                               plan also builds that form's layout and
+                               prefers it; AUTO predicts 0.1 us per group
+                               (four entries of every lane, see
+                               gltrsv_solve_local).  2 needs core_width 1
+                               and, unless schedule_kind is WAVEFRONT,
+                               k <= 64 (EINVAL otherwise); a WAVEFRONT
+                               schedule is then dealt onto 64 cores, row r
+                               of a level going to core r mod 64           */
     int32_t core_width;       /* lanes per BSP core in gltrsv_solve,
                                gltrsv_solve_plain and gltrsv_solve_async:
                                1 (0 = default) = a core is one lane of a
@@ -257,6 +267,12 @@ typedef struct gltrsv_plan_info {
                                (GLTRSV_EXEC_*)                                */
     int32_t core_width;     /* lanes per core of gltrsv_solve / _plain /
                                _async                                         */
+    int64_t local_groups;   /* plans built with exec_hint 2: the groups one
+                               lane of gltrsv_solve_local steps through (its
+                               serial path); else 0                           */
+    int64_t local_records;  /* ... and the records they are cut into          */
+    int64_t local_far;      /* ... and the operands read from x in global
+                               memory rather than from LDS                    */
 } gltrsv_plan_info;
 
 /* Analyses A (checks, schedule, Sec. 5 order) and uploads the packed matrix
@@ -510,32 +526,84 @@ int gltrsv_solve_async(gltrsv_plan *plan, const double *b, double *x, void *stre
  * gltrsv_plan_device_status. */
 int gltrsv_solve_multi(gltrsv_plan *plan, const double *b, double *x, int32_t nrhs, void *stream);
 
+/* One-workgroup solve, for plans created with opts.exec_hint = 2: the BSP
+ * machine of Definition 2.1 is one wavefront of one workgroup, lane c being
+ * core c (k <= 64), and the wave's program order is the barrier between
+ * supersteps (a value one lane writes to LDS is seen by every later LDS read
+ * of the wave), so a superstep costs no device-wide synchronisation at all.
+ * Every lane's rows of a superstep run in the order of Sec. 5, in groups of
+ * four stream entries (a row starts a new group: b_i and the diagonal, then
+ * the off-diagonals in stored order as a running subtraction, Eq. (2.1), and
+ * the division where the row ends); a superstep takes as many groups as its
+ * busiest lane.  The results of the last 128 groups stay in LDS; older
+ * operands, b and the copy of every result to x are handled by a second wave
+ * that streams the plan's records through an LDS FIFO.  One launch of one
+ * 128-thread workgroup with about 160 KB of LDS.  For the narrow,
+ * dependency-bound systems where the device-wide forms wait on memory round
+ * trips between waves.  Same arguments and the same bits as gltrsv_solve (b
+ * may alias x); GLTRSV_ENOTSUP for a plan without the layout.  Errors are
+ * reported by gltrsv_plan_device_status. */
+int gltrsv_solve_local(gltrsv_plan *plan, const double *b, double *x, void *stream);
+
+/* Copies a plan's one-workgroup layout to host memory for inspection:
+ * rec (rec_bytes bytes) receives the records one after another, info
+ * (records x 4 uint32: bytes copied, FIFO byte offset, records that must be
+ * computed before the copy, 0) the per-record copy data.  rec_bytes and
+ * records must equal the layout's (see gltrsv_plan_local_size), else
+ * EINVAL; ENOTSUP without a layout.  Record format: a 32-byte header
+ * (uint32 groups, fills, drains, records drained before compute,
+ * FIFO offset of the next record, records drained before the fills, 0, 0);
+ * per group 64 lanes x 4 doubles as [2][64][2] (entries 2h, 2h+1 of lane l
+ * at byte 1024 h + 16 l) and 64 lanes x 4 uint16 LDS slots (bit 15: row
+ * header on entry 0, row end on entry 1); fills {uint32 slot | bit 31 for
+ * x, int32 row} (slot <- b[row] or x[row]); drains {uint32 slot, int32 row}
+ * (x[row] <- slot once computed).  LDS slots (8 bytes each, in blocks of
+ * 64): 0..8191 the ring (the row ending in group g on lane c at
+ * (g mod 128) * 64 + c), 8192 holds +0.0, the FIFO of 96,768 bytes from
+ * slot 8256; records start at multiples of 512 FIFO bytes and their fill
+ * i goes to the i-th slot after the copied bytes, rounded up to 512.
+ * Synchronous. */
+int gltrsv_plan_local_size(const gltrsv_plan *plan, int64_t *rec_bytes, int64_t *records);
+/* The same layout built on the host from a schedule (core[n] < 64 and
+ * superstep[n] per row, host arrays, checked against Definition 2.1) in the
+ * order of Sec. 5, without a plan or a device: with rec or info NULL it
+ * stores the sizes in *rec_bytes and *records; otherwise those must hold
+ * them and rec/info receive the layout.  triangle: GLTRSV_LOWER or
+ * GLTRSV_UPPER (as opts.triangle).  Host only. */
+int gltrsv_local_layout(const gltrsv_csr *A, int32_t triangle, const int32_t *core, const int32_t *superstep,
+                        void *rec, int64_t *rec_bytes, uint32_t *info, int64_t *records);
+int gltrsv_plan_local_records(const gltrsv_plan *plan, void *rec, int64_t rec_bytes, uint32_t *info, int64_t records);
+
 /* ------------------------------------------------------- execution forms */
-/* The three single-system forms give the same bits; which is fastest depends
- * on the matrix and its schedule (many short supersteps favour the
- * semi-asynchronous form, a few wide ones the persistent form). */
+/* The single-system forms give the same bits; which is fastest depends on
+ * the matrix and its schedule (many short supersteps favour the
+ * semi-asynchronous form, a few wide ones the persistent form, a narrow
+ * system with a k <= 64 schedule the one-workgroup form). */
 #define GLTRSV_EXEC_PERSISTENT 0   /* gltrsv_solve       */
 #define GLTRSV_EXEC_PLAIN      1   /* gltrsv_solve_plain */
 #define GLTRSV_EXEC_ASYNC      2   /* gltrsv_solve_async */
+#define GLTRSV_EXEC_LOCAL      3   /* gltrsv_solve_local (plans with exec_hint 2) */
+#define GLTRSV_EXEC_FORMS      4
 
 /* Solves with the plan's preferred form: the one given to
  * gltrsv_plan_set_exec or found by gltrsv_plan_tune, initially the form that
- * opts.exec_hint names (persistent, or semi-asynchronous).  Arguments as for
- * gltrsv_solve (b may alias x). */
+ * opts.exec_hint names (persistent, semi-asynchronous or one workgroup).
+ * Arguments as for gltrsv_solve (b may alias x). */
 int gltrsv_solve_auto(gltrsv_plan *plan, const double *b, double *x, void *stream);
 
-/* Sets the preferred form (GLTRSV_EXEC_*, else EINVAL), e.g. from a stored
- * tuning result. */
+/* Sets the preferred form (GLTRSV_EXEC_*, else EINVAL; LOCAL only for a
+ * plan with that layout, else ENOTSUP), e.g. from a stored tuning result. */
 int gltrsv_plan_set_exec(gltrsv_plan *plan, int32_t form);
 
-/* Times the three forms on this plan and makes the fastest the preferred
- * one (an autotuner; the cost-model choice of opts.exec_hint is a
- * prediction, this is a measurement).  Each form solves b -> x once untimed,
- * then `reps` times (>= 1) between two HIP events on `stream`.  b and x:
- * device, n values each, caller-owned, not overlapping (EINVAL); x ends
- * holding the solution.  us_out (host, 3 doubles, may be NULL) receives the
- * mean microseconds per solve in GLTRSV_EXEC_* order, *best (may be NULL)
- * the chosen form.  Synchronises `stream`.  If a device-side wait ran out
+/* Times the plan's forms and makes the fastest the preferred one (an
+ * autotuner; the cost-model choice of opts.exec_hint is a prediction, this
+ * is a measurement).  Each form solves b -> x once untimed, then `reps`
+ * times (>= 1) between two HIP events on `stream`.  b and x: device, n
+ * values each, caller-owned, not overlapping (EINVAL); x ends holding the
+ * solution.  us_out (host, GLTRSV_EXEC_FORMS doubles, may be NULL) receives
+ * the mean microseconds per solve in GLTRSV_EXEC_* order (-1 for the
+ * one-workgroup form of a plan without its layout), *best (may be NULL) the
+ * chosen form.  Synchronises `stream`.  If a device-side wait ran out
  * during the measurement the preference is left unchanged and the call
  * returns GLTRSV_ETIMEDOUT. */
 int gltrsv_plan_tune(gltrsv_plan *plan, const double *b, double *x, int32_t reps, void *stream, double *us_out,

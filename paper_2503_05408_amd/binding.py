@@ -38,7 +38,9 @@ PACK_DEVICE = 2
 EXEC_PERSISTENT = 0
 EXEC_PLAIN = 1
 EXEC_ASYNC = 2
-EXEC_NAMES = {EXEC_PERSISTENT: "persistent", EXEC_PLAIN: "plain", EXEC_ASYNC: "async"}
+EXEC_LOCAL = 3
+EXEC_FORMS = 4
+EXEC_NAMES = {EXEC_PERSISTENT: "persistent", EXEC_PLAIN: "plain", EXEC_ASYNC: "async", EXEC_LOCAL: "local"}
 
 
 class GltrsvError(RuntimeError):
@@ -81,7 +83,8 @@ class PlanInfo(ctypes.Structure):
                 ("chunks", i64), ("stream_slots", i64), ("device_bytes", i64), ("analysis_ns", i64),
                 ("pattern_key", u64), ("grid_blocks", i32), ("block_size", i32), ("max_task_rows", i64),
                 ("schedule_kind", i32), ("predicted_us", dbl), ("device_packed", i32),
-                ("async_grid_blocks", i32), ("exec_form", i32), ("core_width", i32)]
+                ("async_grid_blocks", i32), ("exec_form", i32), ("core_width", i32),
+                ("local_groups", i64), ("local_records", i64), ("local_far", i64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -108,6 +111,10 @@ SIGNATURES = {
     "gltrsv_copy_probe": ([P, P, i64, P], i32),
     "gltrsv_plan_gather_probe": ([P, P, P, P], i32),
     "gltrsv_solve_async": ([P, P, P, P], i32),
+    "gltrsv_solve_local": ([P, P, P, P], i32),
+    "gltrsv_plan_local_size": ([P, P, P], i32),
+    "gltrsv_plan_local_records": ([P, P, i64, P, i64], i32),
+    "gltrsv_local_layout": ([P, i32, P, P, P, P, P, P], i32),
     "gltrsv_solve_multi": ([P, P, P, i32, P], i32),
     "gltrsv_plan_set_spin_limit": ([P, i64], i32),
     "gltrsv_plan_set_steal_wait": ([P, i64], i32),
@@ -228,6 +235,22 @@ def schedule(m, opts: PlanOpts | None = None):
     _check(load().gltrsv_schedule(h.ref, ctypes.byref(opts), _np_ptr(core), _np_ptr(sup), ctypes.byref(S)),
            "gltrsv_schedule")
     return core, sup, S.value
+
+
+def local_layout(m, core, superstep, triangle: int = 0):
+    """Host-built one-workgroup layout of the schedule (core, superstep) per
+    row: (records as uint8, info as uint32 [records, 4])."""
+    h = _HostCsr(m)
+    core = np.ascontiguousarray(core, dtype=np.int32)
+    superstep = np.ascontiguousarray(superstep, dtype=np.int32)
+    nb, nr = i64(0), i64(0)
+    _check(load().gltrsv_local_layout(h.ref, int(triangle), _np_ptr(core), _np_ptr(superstep), None,
+                                      ctypes.byref(nb), None, ctypes.byref(nr)), "gltrsv_local_layout")
+    rec = np.empty(max(1, nb.value), dtype=np.uint8)
+    info = np.empty((max(1, nr.value), 4), dtype=np.uint32)
+    _check(load().gltrsv_local_layout(h.ref, int(triangle), _np_ptr(core), _np_ptr(superstep), _np_ptr(rec),
+                                      ctypes.byref(nb), _np_ptr(info), ctypes.byref(nr)), "gltrsv_local_layout")
+    return rec[:nb.value], info[:nr.value]
 
 
 def reorder(core, superstep):
@@ -375,19 +398,21 @@ class Plan:
         _check(load().gltrsv_plan_set_exec(self._p, int(form)), "gltrsv_plan_set_exec")
 
     def tune(self, b=None, x=None, reps: int = 5, stream=None) -> dict:
-        """Times the three execution forms and makes the fastest the
-        preferred one; returns {"form": name, "us": {name: microseconds}}.
+        """Times the plan's execution forms and makes the fastest the
+        preferred one; returns {"form": name, "us": {name: microseconds}}
+        (the one-workgroup form only for plans built with exec_hint 2).
         b defaults to ones; b and x must not overlap."""
         import torch
         if b is None:
             b = torch.ones(self.n, dtype=torch.float64, device="cuda")
         if x is None:
             x = torch.empty_like(b)
-        us = (ctypes.c_double * 3)()
+        us = (ctypes.c_double * EXEC_FORMS)()
         best = i32(0)
         _check(load().gltrsv_plan_tune(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), int(reps),
                                        _stream_ptr(stream), us, ctypes.byref(best)), "gltrsv_plan_tune")
-        return {"form": EXEC_NAMES[best.value], "us": {EXEC_NAMES[f]: us[f] for f in range(3)}}
+        return {"form": EXEC_NAMES[best.value],
+                "us": {EXEC_NAMES[f]: us[f] for f in range(EXEC_FORMS) if us[f] >= 0.0}}
 
     def set_steal_wait(self, microseconds: int):
         """Superstep wait after which the persistent solve robs workgroups
@@ -412,6 +437,25 @@ class Plan:
         _check(load().gltrsv_solve_async(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
                "gltrsv_solve_async")
         return x
+
+    def solve_local(self, b, x=None, stream=None):
+        """One-workgroup solve (plans built with exec_hint=2)."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        _check(load().gltrsv_solve_local(self._p, _dev_ptr(b, self.n), _dev_ptr(x, self.n), _stream_ptr(stream)),
+               "gltrsv_solve_local")
+        return x
+
+    def local_records(self):
+        """The one-workgroup layout: (records as uint8, info as uint32 [records, 4])."""
+        nb, nr = i64(0), i64(0)
+        _check(load().gltrsv_plan_local_size(self._p, ctypes.byref(nb), ctypes.byref(nr)), "gltrsv_plan_local_size")
+        rec = np.empty(max(1, nb.value), dtype=np.uint8)
+        info = np.empty((max(1, nr.value), 4), dtype=np.uint32)
+        _check(load().gltrsv_plan_local_records(self._p, _np_ptr(rec), nb.value, _np_ptr(info), nr.value),
+               "gltrsv_plan_local_records")
+        return rec[:nb.value], info[:nr.value]
 
     def solve_multi(self, b, x=None, stream=None):
         """Several right-hand sides: b and x are (n, nrhs) row-major CUDA

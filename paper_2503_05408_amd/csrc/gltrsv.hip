@@ -97,7 +97,12 @@ int check_opts(const gltrsv_plan_opts *o)
         return set_error(GLTRSV_EINVAL, "unknown pack mode");
     if (o->blocks < 0) return set_error(GLTRSV_EINVAL, "blocks must be >= 0");
     if (o->funnel_max_weight < 0) return set_error(GLTRSV_EINVAL, "funnel_max_weight must be >= 0");
-    if (o->exec_hint != 0 && o->exec_hint != 1) return set_error(GLTRSV_EINVAL, "exec_hint must be 0 or 1");
+    if (o->exec_hint < 0 || o->exec_hint > 2) return set_error(GLTRSV_EINVAL, "exec_hint must be 0, 1 or 2");
+    if (o->exec_hint == 2) {
+        if (o->core_width == 64) return set_error(GLTRSV_EINVAL, "exec_hint 2 (one workgroup) needs core_width 1");
+        if (o->schedule_kind != GLTRSV_SCHED_WAVEFRONT && o->k > 64)
+            return set_error(GLTRSV_EINVAL, "exec_hint 2 (one workgroup) needs k <= 64");
+    }
     if (o->triangle != GLTRSV_LOWER && o->triangle != GLTRSV_UPPER)
         return set_error(GLTRSV_EINVAL, "triangle must be GLTRSV_LOWER or GLTRSV_UPPER");
     if (o->reorder != 0 && o->reorder != 1) return set_error(GLTRSV_EINVAL, "reorder must be 0 or 1");
@@ -266,10 +271,17 @@ Schedule build_schedule(const CsrView &V, const gltrsv_plan_opts *o, std::vector
 {
     const CostModel cm;
     auto predict = [&](const Schedule &sc, const std::vector<int32_t> &pm) {
+        if (o->exec_hint == 2) return double(local_group_count(V, sc, pm)) * kLocalGroupUs;
         return o->exec_hint == 1 ? predict_async_us(V, sc, pm, cm) : predict_cost_us(V, sc, pm, cm);
     };
-    if (o->schedule_kind == GLTRSV_SCHED_WAVEFRONT) {
+    // one workgroup: the levels dealt onto its 64 lanes
+    auto wavefront = [&]() {
         Schedule w = schedule_wavefront(V);
+        if (o->exec_hint == 2) fold_cores(w, 64);
+        return w;
+    };
+    if (o->schedule_kind == GLTRSV_SCHED_WAVEFRONT) {
+        Schedule w = wavefront();
         *perm = schedule_order(V.n, w.core.data(), w.superstep.data(), w.S);
         *cost_us = predict(w, *perm);
         *chosen = GLTRSV_SCHED_WAVEFRONT;
@@ -279,7 +291,7 @@ Schedule build_schedule(const CsrView &V, const gltrsv_plan_opts *o, std::vector
     std::vector<int32_t> pg = schedule_order(V.n, g.core.data(), g.superstep.data(), g.S);
     const double cg = predict(g, pg);
     if (o->schedule_kind == GLTRSV_SCHED_AUTO) {
-        Schedule w = schedule_wavefront(V);
+        Schedule w = wavefront();
         std::vector<int32_t> pw = schedule_order(V.n, w.core.data(), w.superstep.data(), w.S);
         const double cw = predict(w, pw);
         if (cw < cg) {
@@ -419,6 +431,46 @@ int gltrsv_reorder(int64_t n, const int32_t *core, const int32_t *superstep, int
     return GLTRSV_OK;
 }
 
+int gltrsv_local_layout(const gltrsv_csr *A, int32_t triangle, const int32_t *core, const int32_t *superstep,
+                        void *rec, int64_t *rec_bytes, uint32_t *info, int64_t *records)
+{
+    if (!A || !rec_bytes || !records || (A->n > 0 && (!core || !superstep)))
+        return set_error(GLTRSV_EINVAL, "null argument");
+    if (triangle != GLTRSV_LOWER && triangle != GLTRSV_UPPER) return set_error(GLTRSV_EINVAL, "bad triangle");
+    const bool upper = triangle == GLTRSV_UPPER;
+    const CsrView V = view_of(A);
+    std::string msg;
+    int rc = upper ? check_csr_upper(V, true, &msg) : check_csr(V, true, &msg);
+    if (rc) return set_error(rc, msg);
+    Mirror mir;
+    if (upper) mir = mirror_upper(V);
+    const CsrView D = upper ? mir.view() : V;
+    const int64_t n = A->n;
+    Schedule s;
+    s.core.resize(size_t(n));
+    s.superstep.resize(size_t(n));
+    for (int64_t v = 0; v < n; v++) {
+        const int64_t row = upper ? n - 1 - v : v;
+        s.core[size_t(v)] = core[row];
+        s.superstep[size_t(v)] = superstep[row];
+        s.S = std::max(s.S, superstep[row] + 1);
+    }
+    if ((rc = validate_schedule(D, s, &msg))) return set_error(rc, "schedule: " + msg);
+    const std::vector<int32_t> perm = schedule_order(n, s.core.data(), s.superstep.data(), s.S);
+    LocalLayout lay;
+    if ((rc = build_local_layout(V, upper, s, perm, &lay, &msg))) return set_error(rc, msg);
+    if (!rec || !info) {
+        *rec_bytes = int64_t(lay.rec.size());
+        *records = int64_t(lay.info.size());
+        return GLTRSV_OK;
+    }
+    if (*rec_bytes != int64_t(lay.rec.size()) || *records != int64_t(lay.info.size()))
+        return set_error(GLTRSV_EINVAL, "buffer sizes differ from the layout's (query them with null buffers)");
+    if (!lay.rec.empty()) std::memcpy(rec, lay.rec.data(), lay.rec.size());
+    if (!lay.info.empty()) std::memcpy(info, lay.info.data(), lay.info.size() * sizeof(LocalRec));
+    return GLTRSV_OK;
+}
+
 int gltrsv_plan_destroy(gltrsv_plan *p)
 {
     if (!p) return GLTRSV_OK;
@@ -448,6 +500,8 @@ int gltrsv_plan_destroy(gltrsv_plan *p)
     (void)hipFree(p->d_wval);
     (void)hipFree(p->d_wtask);
     (void)hipFree(p->d_wsuper);
+    (void)hipFree(p->d_lrec);
+    (void)hipFree(p->d_linfo);
     delete p;
     return GLTRSV_OK;
 }
@@ -509,13 +563,28 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         }
         p->perm = schedule_order(n, s.core.data(), s.superstep.data(), s.S);
         const CostModel cm;
-        p->predicted_us = opts->exec_hint == 1 ? predict_async_us(D, s, p->perm, cm) : predict_cost_us(D, s, p->perm, cm);
+        if (opts->exec_hint == 2) {
+            for (int64_t v = 0; v < n; v++)
+                if (s.core[size_t(v)] >= 64) {
+                    delete p;
+                    return set_error(GLTRSV_EINVAL, "given schedule: exec_hint 2 (one workgroup) needs cores 0..63");
+                }
+            p->predicted_us = double(local_group_count(D, s, p->perm)) * kLocalGroupUs;
+        } else {
+            p->predicted_us =
+                opts->exec_hint == 1 ? predict_async_us(D, s, p->perm, cm) : predict_cost_us(D, s, p->perm, cm);
+        }
         p->schedule_kind = GLTRSV_SCHED_GIVEN;
     } else {
         s = build_schedule(D, opts, &p->perm, &p->predicted_us, &p->schedule_kind);
     }
     std::vector<int32_t> lv;
     p->wavefronts = wavefront_levels(D, lv);
+    LocalLayout local;
+    if (opts->exec_hint == 2 && (rc = build_local_layout(V, upper, s, p->perm, &local, &msg))) {
+        delete p;
+        return set_error(rc, msg);
+    }
     const bool on_device =
         opts->pack == GLTRSV_PACK_DEVICE || (opts->pack == GLTRSV_PACK_AUTO && V.nnz >= (int64_t(1) << 20));
     PackLayout lay = pack_layout(D, s, p->perm);
@@ -555,6 +624,17 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
     }
     p->device_packed = on_device;
     p->exec_form = opts->exec_hint == 1 ? GLTRSV_EXEC_ASYNC : GLTRSV_EXEC_PERSISTENT;
+    if (opts->exec_hint == 2) {
+        if ((rc = upload(&p->d_lrec, local.rec, &bytes)) || (rc = upload(&p->d_linfo, local.info, &bytes))) {
+            gltrsv_plan_destroy(p);
+            return rc;
+        }
+        p->l_nrec = int32_t(local.info.size());
+        p->l_bytes = int64_t(local.rec.size());
+        p->l_groups = local.groups;
+        p->l_far = local.far;
+        p->exec_form = GLTRSV_EXEC_LOCAL;
+    }
     if ((rc = upload(&p->d_chunk_base, pk.chunk_base, &bytes)) || (rc = upload(&p->d_chunk_len, pk.chunk_len, &bytes)) ||
         (rc = upload(&p->d_super_chunk, pk.super_chunk, &bytes))) {
         gltrsv_plan_destroy(p);
@@ -698,6 +778,9 @@ int gltrsv_plan_info_get(const gltrsv_plan *p, gltrsv_plan_info *o)
     o->async_grid_blocks = p->grid_async;
     o->exec_form = p->exec_form;
     o->core_width = p->core_width;
+    o->local_groups = p->l_groups;
+    o->local_records = p->l_nrec;
+    o->local_far = p->l_far;
     return GLTRSV_OK;
 }
 
@@ -992,6 +1075,7 @@ int gltrsv_solve_auto(gltrsv_plan *p, const double *b, double *x, void *stream)
     switch (p->exec_form) {
     case GLTRSV_EXEC_PLAIN: return gltrsv_solve_plain(p, b, x, stream);
     case GLTRSV_EXEC_ASYNC: return gltrsv_solve_async(p, b, x, stream);
+    case GLTRSV_EXEC_LOCAL: return gltrsv_solve_local(p, b, x, stream);
     default: return gltrsv_solve(p, b, x, stream);
     }
 }
@@ -999,8 +1083,9 @@ int gltrsv_solve_auto(gltrsv_plan *p, const double *b, double *x, void *stream)
 int gltrsv_plan_set_exec(gltrsv_plan *p, int32_t form)
 {
     if (!p) return set_error(GLTRSV_EINVAL, "null plan");
-    if (form != GLTRSV_EXEC_PERSISTENT && form != GLTRSV_EXEC_PLAIN && form != GLTRSV_EXEC_ASYNC)
-        return set_error(GLTRSV_EINVAL, "unknown execution form");
+    if (form < 0 || form >= GLTRSV_EXEC_FORMS) return set_error(GLTRSV_EINVAL, "unknown execution form");
+    if (form == GLTRSV_EXEC_LOCAL && !p->d_lrec)
+        return set_error(GLTRSV_ENOTSUP, "the plan has no one-workgroup layout (create it with exec_hint 2)");
     p->exec_form = form;
     return GLTRSV_OK;
 }
@@ -1027,12 +1112,13 @@ int gltrsv_plan_tune(gltrsv_plan *p, const double *b, double *x, int32_t reps, v
     if (p->n && b0 < x0 + len && x0 < b0 + len) return set_error(GLTRSV_EINVAL, "b and x overlap");
     hipStream_t st = static_cast<hipStream_t>(stream);
     using SolveFn = int (*)(gltrsv_plan *, const double *, double *, void *);
-    const SolveFn forms[3] = {gltrsv_solve, gltrsv_solve_plain, gltrsv_solve_async};
-    double us[3] = {0.0, 0.0, 0.0};
+    const SolveFn forms[GLTRSV_EXEC_FORMS] = {gltrsv_solve, gltrsv_solve_plain, gltrsv_solve_async, gltrsv_solve_local};
+    double us[GLTRSV_EXEC_FORMS] = {0.0, 0.0, 0.0, -1.0};
+    const int nforms = p->d_lrec ? GLTRSV_EXEC_FORMS : GLTRSV_EXEC_FORMS - 1;
     EventPair ev;
     HIP_TRY(hipEventCreate(&ev.a));
     HIP_TRY(hipEventCreate(&ev.b));
-    for (int f = 0; f < 3; f++) {
+    for (int f = 0; f < nforms; f++) {
         int rc = forms[f](p, b, x, stream);
         if (rc) return rc;
         HIP_TRY(hipEventRecord(ev.a, st));
@@ -1049,11 +1135,11 @@ int gltrsv_plan_tune(gltrsv_plan *p, const double *b, double *x, int32_t reps, v
     if (rc) return rc;
     if (status) return set_error(GLTRSV_ETIMEDOUT, "a device-side wait ran out during tuning");
     int32_t f_best = 0;
-    for (int32_t f = 1; f < 3; f++)
+    for (int32_t f = 1; f < nforms; f++)
         if (us[f] < us[f_best]) f_best = f;
     p->exec_form = f_best;
     if (us_out)
-        for (int f = 0; f < 3; f++) us_out[f] = us[f];
+        for (int f = 0; f < GLTRSV_EXEC_FORMS; f++) us_out[f] = us[f];
     if (best) *best = f_best;
     return GLTRSV_OK;
 }

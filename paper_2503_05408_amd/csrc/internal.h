@@ -9,6 +9,7 @@
 
 #include "../../include/gltrsv.h"
 #include "analysis.h"
+#include "local.h"
 
 namespace gltrsv {
 
@@ -183,6 +184,19 @@ __global__ void trsv_async_multi(const uint32_t *word, const double *value, cons
                                  const int32_t *chunk_len, int32_t chunks, const double *b, double *x, int64_t ld,
                                  int32_t *err, int64_t spin_limit, unsigned long long *ticket, uint32_t *alive,
                                  unsigned long long *vnext, int64_t rob_ticks, int64_t delay_ticks);
+// single-workgroup execution (local.h): one workgroup of 128 threads per
+// system; sys[blockIdx.x] in the batched form
+struct LocalSys {
+    const uint8_t *rec;
+    const LocalRec *info;
+    const double *b;
+    double *x;
+    int64_t n;
+    int32_t nrec;
+};
+__global__ void trsv_local(const uint8_t *rec, const LocalRec *info, int32_t nrec, int64_t n, const double *b,
+                           double *x, int32_t *err, int64_t spin_limit);
+__global__ void trsv_local_batched(const LocalSys *sys, int32_t count, int32_t *err, int64_t spin_limit);
 // measurement probes
 __global__ void gather_probe(const uint32_t *word, const double *value, const int64_t *chunk_base,
                              const int32_t *chunk_len, int64_t chunks, const double *x, double *y);
@@ -261,6 +275,11 @@ struct gltrsv_plan {
     std::vector<int32_t> wsuper_host;   // [S + 1] task range of each superstep
     int grid_wave = 0;                  // workgroups of the persistent wave kernel
     int grid_wave_async = 0;            // workgroups of the semi-asynchronous wave kernel
+    // one-workgroup layout (opts.exec_hint = 2, local.h)
+    uint8_t *d_lrec = nullptr;          // the records
+    gltrsv::LocalRec *d_linfo = nullptr;   // [l_nrec]
+    int32_t l_nrec = 0;
+    int64_t l_bytes = 0, l_groups = 0, l_far = 0;
 };
 
 inline int64_t widest_of(const std::vector<gltrsv_plan *> &plans)

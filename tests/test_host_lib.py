@@ -58,7 +58,8 @@ def test_bad_options_rejected():
     m = gen.fig_1_1()
     for bad in (dict(k=0), dict(alpha0=0.5), dict(growth=1.0), dict(L=-1.0), dict(schedule_kind=7),
                 dict(analysis_threads=-1), dict(pack=9), dict(blocks=-2), dict(funnel_max_weight=-1),
-                dict(exec_hint=2), dict(reorder=2), dict(reorder=-1), dict(triangle=5), dict(core_width=32)):
+                dict(exec_hint=3), dict(exec_hint=-1), dict(exec_hint=2, k=65), dict(exec_hint=2, core_width=64),
+                dict(reorder=2), dict(reorder=-1), dict(triangle=5), dict(core_width=32)):
         with pytest.raises(B.GltrsvError):
             B.schedule(m, B.default_opts(**bad))
 
