@@ -748,10 +748,14 @@ PackLayout pack_layout(const CsrView &A, const Schedule &sch, const std::vector<
     pk.slots = slots;
     lay.pos_slot.assign(n, 0);
     lay.pos_task0.assign(n, 0);
+    lay.lane_first.assign(size_t(C) * kLanes, 0);
+    lay.lane_rows.assign(size_t(C) * kLanes, 0);
     for (int64_t c = 0; c < C; c++) {
         for (int l = 0; l < kLanes; l++) {
             const int64_t task = lane_task[c * kLanes + l];
             if (task < 0) continue;
+            lay.lane_first[size_t(c * kLanes + l)] = int32_t(task_begin[task]);
+            lay.lane_rows[size_t(c * kLanes + l)] = int32_t(task_begin[task + 1] - task_begin[task]);
             for (int64_t t = task_begin[task]; t < task_begin[task + 1]; t++) {
                 lay.pos_slot[t] = pk.chunk_base[c] + l;
                 lay.pos_task0[t] = int32_t(task_begin[task]);

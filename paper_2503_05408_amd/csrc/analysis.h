@@ -136,6 +136,9 @@ struct PackLayout {
     Packed pk;                         // everything but word/value
     std::vector<int64_t> pos_slot;     // [n]
     std::vector<int32_t> pos_task0;    // [n]
+    // per (chunk, lane), chunk-major: the task's first position in the order
+    // and its row count (0 for a lane without a task)
+    std::vector<int32_t> lane_first, lane_rows;
 };
 PackLayout pack_layout(const CsrView &A, const Schedule &sch, const std::vector<int32_t> &perm);
 

@@ -1,18 +1,15 @@
 // Device packing of the lane-interleaved stream (the reorder of Sec. 5 and
 // the packed layout the solve kernels read), after the host has laid out
 // tasks, chunks and lanes:
-//   1. per position t of the schedule order: the row perm[t], its inverse,
-//      and its stream length (stored entries of the row);
-//   2. an exclusive prefix sum of the lengths: each workgroup stages 2048
-//      lengths through LDS, every thread sums 8 consecutive ones, the
-//      64-lane wavefronts scan those sums with lane shuffles, and the four
-//      wave totals are combined through LDS; one more workgroup scans the
-//      workgroup totals;
-//   3. the scatter: a row's entries start at (its prefix - the prefix of its
-//      task's first row) entries into its lane, so entry j lands at
-//      slot(lane) + 64 * (that offset + j).  Words are encoded as the host
-//      packer does: header, a column of the same task fewer than kRing rows
-//      back as "rows back", any other column as itself.
+//   1. per position t of the schedule order: the inverse of the order,
+//      inv[perm[t]] = t;
+//   2. the fill: a wavefront per chunk, lane l walking the rows of the
+//      chunk's l-th task in order, all lanes on the same entry index at
+//      each step, so every step stores 64 consecutive words and values;
+//      each lane reads its own rows' columns and values one after another.
+//      Words are encoded as the host packer does: header, a column of the
+//      same task fewer than kRing rows back as "rows back", any other column
+//      as itself.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -26,125 +23,77 @@ namespace gltrsv {
 namespace dev {
 namespace {
 
-constexpr int kScanItems = 8;                      // per thread
-constexpr int kScanTile = kBlock * kScanItems;     // per workgroup
+// Waves of the fill kernel per compute unit.  Every wave keeps about two
+// lines per lane in use (its lanes' current rows), so more waves hide more
+// latency but push those lines out of L2 before the lanes' next steps reuse
+// them.  Measured on MI355X for the n = 1e7 ER stream (1.2e8 slots): 1, 2,
+// 4 and 8 waves per CU took 13.5, 7.0, 3.9 and 5.6 ms and read 1.31e8,
+// 1.38e8, 1.69e8 and 2.98e8 128-byte requests beyond L2.
+#ifndef GLTRSV_PACK_WAVES_PER_CU
+#define GLTRSV_PACK_WAVES_PER_CU 4
+#endif
+constexpr int kPackWavesPerCU = GLTRSV_PACK_WAVES_PER_CU;
 
 // perm lists vertices; for an upper-triangular matrix vertex v is row n-1-v.
-__global__ __launch_bounds__(kBlock) void pack_rows(const int32_t *__restrict__ perm,
-                                                    const int64_t *__restrict__ row_ptr, int64_t n, int32_t upper,
-                                                    int32_t *__restrict__ inv, int64_t *__restrict__ len)
+__global__ __launch_bounds__(kBlock) void pack_inverse(const int32_t *__restrict__ perm, int64_t n,
+                                                       int32_t *__restrict__ inv)
 {
     const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (t >= n) return;
-    const int32_t v = perm[t];
-    const int64_t row = upper ? n - 1 - v : v;
-    inv[v] = int32_t(t);
-    len[t] = row_ptr[row + 1] - row_ptr[row];
+    if (t < n) inv[perm[t]] = int32_t(t);
 }
 
-__device__ __forceinline__ int64_t wave_inclusive_scan(int64_t v, int lane)
-{
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int64_t u = __shfl_up(v, d, 64);
-        if (lane >= d) v += u;
-    }
-    return v;
-}
-
-// Exclusive scan of one tile of `data` in place; returns the tile's total
-// (valid in every thread).
-__device__ __forceinline__ int64_t scan_tile(int64_t *data, int64_t n, int64_t base, int64_t *tile, int64_t *wsum)
-{
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        const int64_t i = base + int64_t(k) * kBlock + tid;
-        tile[k * kBlock + tid] = i < n ? data[i] : 0;
-    }
-    __syncthreads();
-    int64_t own[kScanItems], sum = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        own[k] = sum;
-        sum += tile[tid * kScanItems + k];
-    }
-    const int64_t incl = wave_inclusive_scan(sum, lane);
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    int64_t before = 0, total = 0;
-#pragma unroll
-    for (int w = 0; w < kWavesPerBlock; w++) {
-        before += w < wave ? wsum[w] : 0;
-        total += wsum[w];
-    }
-    const int64_t first = before + incl - sum;
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) tile[tid * kScanItems + k] = first + own[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        const int64_t i = base + int64_t(k) * kBlock + tid;
-        if (i < n) data[i] = tile[k * kBlock + tid];
-    }
-    __syncthreads();   // tile and wsum are reused by the caller's next tile
-    return total;
-}
-
-__global__ __launch_bounds__(kBlock) void scan_tiles(int64_t *__restrict__ data, int64_t n, int64_t *__restrict__ tops)
-{
-    __shared__ int64_t tile[kScanTile];
-    __shared__ int64_t wsum[kWavesPerBlock];
-    const int64_t total = scan_tile(data, n, int64_t(blockIdx.x) * kScanTile, tile, wsum);
-    if (threadIdx.x == 0) tops[blockIdx.x] = total;
-}
-
-// One workgroup: exclusive scan of the tile totals, tile after tile.
-__global__ __launch_bounds__(kBlock) void scan_tops(int64_t *__restrict__ tops, int64_t m)
-{
-    __shared__ int64_t tile[kScanTile];
-    __shared__ int64_t wsum[kWavesPerBlock];
-    int64_t carry = 0;
-    for (int64_t base = 0; base < m; base += kScanTile) {
-        const int64_t total = scan_tile(tops, m, base, tile, wsum);
-        for (int64_t i = base + threadIdx.x; i < min(m, base + kScanTile); i += kBlock) tops[i] += carry;
-        __syncthreads();
-        carry += total;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void pack_scatter(
+// Grid-stride over chunks, one wavefront per chunk at a time (a bounded
+// number of waves keeps the lanes' row reads resident in L2).  Lane l
+// emits entry k of its task at every step k < chunk_len: a row header (the
+// original row, value = the diagonal) when it starts a row, else the row's
+// next off-diagonal in stored order.
+__global__ __launch_bounds__(kBlock) void pack_chunks(
     const int32_t *__restrict__ perm, const int32_t *__restrict__ inv, const int64_t *__restrict__ row_ptr,
-    const int32_t *__restrict__ col, const double *__restrict__ val, const int64_t *__restrict__ pre,
-    const int64_t *__restrict__ tops, const int64_t *__restrict__ slot, const int32_t *__restrict__ task0, int64_t n,
-    int32_t upper, int64_t slots, uint32_t *__restrict__ word, double *__restrict__ value, int32_t *__restrict__ err)
+    const int32_t *__restrict__ col, const double *__restrict__ val, const int64_t *__restrict__ chunk_base,
+    const int32_t *__restrict__ chunk_len, const int32_t *__restrict__ lane_first,
+    const int32_t *__restrict__ lane_rows, int64_t chunks, int64_t n, int32_t upper, int64_t slots,
+    uint32_t *__restrict__ word, double *__restrict__ value, int32_t *__restrict__ err)
 {
-    const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (t >= n) return;
-    const int32_t v = perm[t];
-    const int64_t row = upper ? n - 1 - v : v;
-    const int32_t t0 = task0[t];
-    const int64_t off = (pre[t] + tops[t / kScanTile]) - (pre[t0] + tops[t0 / kScanTile]);
-    // off-diagonals [lo, hi) in stored order, diagonal at dg
-    const int64_t lo = upper ? row_ptr[row] + 1 : row_ptr[row];
-    const int64_t hi = upper ? row_ptr[row + 1] : row_ptr[row + 1] - 1;
-    const int64_t dg = upper ? row_ptr[row] : row_ptr[row + 1] - 1;
-    const int64_t base = slot[t] + int64_t(kLanes) * off;
-    if (off < 0 || t0 > t || base < 0 || base + int64_t(kLanes) * (hi - lo) >= slots) {
-        *err = 1;   // inconsistent layout: write nothing
-        return;
-    }
-    word[base] = kHdrBit | uint32_t(row);
-    value[base] = val[dg];
-    for (int64_t e = lo; e < hi; e++) {
-        const int32_t c = col[e];
-        const int32_t ic = inv[upper ? n - 1 - c : c];
-        uint32_t w = uint32_t(c);
-        // a parent inside the schedule order's task range is in this task
-        if (ic >= t0 && t - ic < kRing) w = kIntBit | uint32_t(t - ic);
-        const int64_t at = base + int64_t(kLanes) * (1 + e - lo);
-        word[at] = w;
-        value[at] = val[e];
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = int64_t(gridDim.x) * kWavesPerBlock;
+    for (int64_t c = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6); c < chunks; c += waves) {
+        const int64_t base = chunk_base[c] + lane;
+        const int32_t len = chunk_len[c];
+        const int32_t p0 = lane_first[c * kLanes + lane], nr = lane_rows[c * kLanes + lane];
+        if (base + int64_t(kLanes) * len > slots + lane || p0 < 0 || int64_t(p0) + nr > n) {
+            *err = 1;   // inconsistent layout: write nothing
+            continue;
+        }
+        int32_t q = 0;                 // rows started
+        int64_t t = p0, e = 0, hi = 0; // current position, next entry, end of its off-diagonals
+        for (int32_t k = 0; k < len; k++) {
+            const bool start = e >= hi;   // the previous row is complete
+            if (start && q >= nr) continue;   // this lane's task is done (padding was stored before)
+            uint32_t w;
+            double v;
+            if (start) {
+                t = int64_t(p0) + q++;
+                const int32_t vx = perm[t];
+                const int64_t row = upper ? n - 1 - vx : vx;
+                // off-diagonals [e, hi) in stored order, diagonal at dg
+                e = upper ? row_ptr[row] + 1 : row_ptr[row];
+                hi = upper ? row_ptr[row + 1] : row_ptr[row + 1] - 1;
+                const int64_t dg = upper ? row_ptr[row] : row_ptr[row + 1] - 1;
+                w = kHdrBit | uint32_t(row);
+                v = val[dg];
+            } else {
+                const int32_t cl = col[e];
+                const int32_t ic = inv[upper ? n - 1 - cl : cl];
+                w = uint32_t(cl);
+                // a parent inside the task's range of the order is in this task
+                if (ic >= p0 && t - ic < kRing) w = kIntBit | uint32_t(t - ic);
+                v = val[e];
+                e++;
+            }
+            word[base + int64_t(kLanes) * k] = w;
+            value[base + int64_t(kLanes) * k] = v;
+        }
+        if (e < hi || q < nr) *err = 1;   // the task did not fit its chunk length
     }
 }
 
@@ -175,39 +124,48 @@ int device_pack(const CsrView &A, const std::vector<int32_t> &perm, const PackLa
                 uint32_t *d_word, double *d_value)
 {
     const int64_t n = A.n, nnz = A.nnz, slots = lay.pk.slots;
+    const int64_t chunks = int64_t(lay.pk.chunk_len.size());
     if (n == 0 || slots == 0) return GLTRSV_OK;
     Scratch s;
     HIP_TRY(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
-    int64_t *d_rp, *d_pre, *d_tops, *d_slot;
-    int32_t *d_col, *d_perm, *d_inv, *d_t0, *d_err;
+    int64_t *d_rp, *d_base;
+    int32_t *d_col, *d_perm, *d_inv, *d_len, *d_first, *d_rows, *d_err;
     double *d_val;
-    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
     HIP_TRY(s.alloc(&d_rp, size_t(n + 1)));
     HIP_TRY(s.alloc(&d_col, size_t(nnz)));
     HIP_TRY(s.alloc(&d_val, size_t(nnz)));
     HIP_TRY(s.alloc(&d_perm, size_t(n)));
     HIP_TRY(s.alloc(&d_inv, size_t(n)));
-    HIP_TRY(s.alloc(&d_pre, size_t(n)));
-    HIP_TRY(s.alloc(&d_tops, size_t(tiles)));
-    HIP_TRY(s.alloc(&d_slot, size_t(n)));
-    HIP_TRY(s.alloc(&d_t0, size_t(n)));
+    HIP_TRY(s.alloc(&d_base, size_t(chunks)));
+    HIP_TRY(s.alloc(&d_len, size_t(chunks)));
+    HIP_TRY(s.alloc(&d_first, size_t(chunks) * kLanes));
+    HIP_TRY(s.alloc(&d_rows, size_t(chunks) * kLanes));
     HIP_TRY(s.alloc(&d_err, 1));
     HIP_TRY(hipMemsetAsync(d_err, 0, sizeof(int32_t), s.st));
     HIP_TRY(hipMemcpyAsync(d_rp, A.row_ptr, sizeof(int64_t) * size_t(n + 1), hipMemcpyHostToDevice, s.st));
     HIP_TRY(hipMemcpyAsync(d_col, A.col, sizeof(int32_t) * size_t(nnz), hipMemcpyHostToDevice, s.st));
     HIP_TRY(hipMemcpyAsync(d_val, A.val, sizeof(double) * size_t(nnz), hipMemcpyHostToDevice, s.st));
     HIP_TRY(hipMemcpyAsync(d_perm, perm.data(), sizeof(int32_t) * size_t(n), hipMemcpyHostToDevice, s.st));
-    HIP_TRY(hipMemcpyAsync(d_slot, lay.pos_slot.data(), sizeof(int64_t) * size_t(n), hipMemcpyHostToDevice, s.st));
-    HIP_TRY(hipMemcpyAsync(d_t0, lay.pos_task0.data(), sizeof(int32_t) * size_t(n), hipMemcpyHostToDevice, s.st));
+    HIP_TRY(hipMemcpyAsync(d_base, lay.pk.chunk_base.data(), sizeof(int64_t) * size_t(chunks), hipMemcpyHostToDevice,
+                           s.st));
+    HIP_TRY(hipMemcpyAsync(d_len, lay.pk.chunk_len.data(), sizeof(int32_t) * size_t(chunks), hipMemcpyHostToDevice,
+                           s.st));
+    HIP_TRY(hipMemcpyAsync(d_first, lay.lane_first.data(), sizeof(int32_t) * size_t(chunks) * kLanes,
+                           hipMemcpyHostToDevice, s.st));
+    HIP_TRY(hipMemcpyAsync(d_rows, lay.lane_rows.data(), sizeof(int32_t) * size_t(chunks) * kLanes,
+                           hipMemcpyHostToDevice, s.st));
     HIP_TRY(hipMemsetAsync(d_word, 0xFF, sizeof(uint32_t) * size_t(slots), s.st));   // padding words
     HIP_TRY(hipMemsetAsync(d_value, 0, sizeof(double) * size_t(slots), s.st));
-    const unsigned rows_grid = unsigned((n + kBlock - 1) / kBlock);
     const int32_t up = upper ? 1 : 0;
-    hipLaunchKernelGGL(pack_rows, dim3(rows_grid), dim3(kBlock), 0, s.st, d_perm, d_rp, n, up, d_inv, d_pre);
-    hipLaunchKernelGGL(scan_tiles, dim3(unsigned(tiles)), dim3(kBlock), 0, s.st, d_pre, n, d_tops);
-    hipLaunchKernelGGL(scan_tops, dim3(1), dim3(kBlock), 0, s.st, d_tops, tiles);
-    hipLaunchKernelGGL(pack_scatter, dim3(rows_grid), dim3(kBlock), 0, s.st, d_perm, d_inv, d_rp, d_col, d_val, d_pre,
-                       d_tops, d_slot, d_t0, n, up, slots, d_word, d_value, d_err);
+    hipLaunchKernelGGL(pack_inverse, dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s.st, d_perm, n,
+                       d_inv);
+    int cus = 0, dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(int64_t(cus) * kPackWavesPerCU / kWavesPerBlock,
+                                                                (chunks + kWavesPerBlock - 1) / kWavesPerBlock));
+    hipLaunchKernelGGL(pack_chunks, dim3(unsigned(grid)), dim3(kBlock), 0, s.st, d_perm, d_inv, d_rp, d_col, d_val,
+                       d_base, d_len, d_first, d_rows, chunks, n, up, slots, d_word, d_value, d_err);
     HIP_TRY(hipGetLastError());
     int32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s.st));
