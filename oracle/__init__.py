@@ -20,6 +20,9 @@ Each function cites the passage of the paper (arxiv 2503.05408) it follows:
 * :func:`reorder`    -- Sec. 5.
 * :func:`bsp_solve`  -- the schedule executed superstep by superstep with
   strict visibility (Sec. 2.3).
+* :func:`bsp_solve_parallel` -- the same schedule on host threads with a
+  barrier per superstep (``executor.c``; the kind of CPU executor the paper
+  times, Sec. 6.1): the benchmark's second CPU baseline.
 """
 from __future__ import annotations
 
@@ -33,6 +36,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_EXE_SRC = os.path.join(_HERE, "executor.c")
+_EXE_LIB = os.path.join(_HERE, "libexecutor.so")
+_exe = None
 _lock = threading.Lock()
 _lib = None
 
@@ -51,13 +57,65 @@ INVALID_EMPTY = 4
 
 
 def build(force: bool = True) -> str:
-    """Compile ``oracle.c`` into ``liboracle.so`` with gcc."""
+    """Compile ``oracle.c`` into ``liboracle.so`` and ``executor.c`` into
+    ``libexecutor.so`` (OpenMP) with gcc."""
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
            _SRC, "-o", _LIB + ".tmp", "-lm"]
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           _EXE_SRC, "-o", _EXE_LIB + ".tmp"]
+    if force or not os.path.exists(_EXE_LIB) or os.path.getmtime(_EXE_LIB) < os.path.getmtime(_EXE_SRC):
+        subprocess.run(cmd, check=True)
+        os.replace(_EXE_LIB + ".tmp", _EXE_LIB)
     return _LIB
+
+
+def _load_executor():
+    global _exe
+    with _lock:
+        if _exe is None:
+            if not os.path.exists(_EXE_LIB) or os.path.getmtime(_EXE_LIB) < os.path.getmtime(_EXE_SRC):
+                build(force=True)
+            lib = ctypes.CDLL(_EXE_LIB)
+            P = ctypes.c_void_p
+            lib.executor_bsp_omp.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int32, P, P,
+                                             ctypes.c_int32]
+            lib.executor_bsp_omp.restype = ctypes.c_int
+            _exe = lib
+    return _exe
+
+
+class Executor:
+    """A schedule prepared for :func:`executor.c`'s parallel run: the order of
+    Sec. 5 (superstep, then core, then row index), the task boundaries in it
+    and the first task of each superstep."""
+
+    def __init__(self, m, pi, sigma):
+        self.rp, self.c, self.v = _csr(m)
+        self.n = int(m.n)
+        pi = np.asarray(pi, dtype=np.int64)
+        sigma = np.asarray(sigma, dtype=np.int64)
+        order = np.lexsort((np.arange(self.n), pi, sigma)).astype(np.int32)
+        s_o, c_o = sigma[order], pi[order]
+        new_task = np.r_[True, (s_o[1:] != s_o[:-1]) | (c_o[1:] != c_o[:-1])] if self.n else np.zeros(0, bool)
+        starts = np.flatnonzero(new_task)
+        self.order = order
+        self.task_beg = np.r_[starts, self.n].astype(np.int64)
+        S = int(sigma.max()) + 1 if self.n else 0
+        task_s = s_o[starts]
+        self.super_task = np.searchsorted(task_s, np.arange(S + 1), side="left").astype(np.int32)
+        self.S = S
+
+    def solve(self, b, threads: int = 0):
+        """x for right-hand side b; returns (x, threads used)."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.empty(self.n, dtype=np.float64)
+        used = _load_executor().executor_bsp_omp(self.n, _p(self.rp), _p(self.c), _p(self.v), _p(self.order),
+                                                 _p(self.task_beg), _p(self.super_task), self.S, _p(b), _p(x),
+                                                 int(threads))
+        return x, int(used)
 
 
 def _load():
@@ -320,6 +378,15 @@ def bsp_solve(m, b, pi, sigma):
     if rc:
         raise OracleError(f"oracle_bsp_solve: {rc} at row {bad.value}")
     return x
+
+
+def bsp_solve_parallel(m, b, pi, sigma, threads: int = 0):
+    """The schedule (pi, sigma) of a lower-triangular m executed on `threads`
+    host threads (0 = the OpenMP default), superstep by superstep with a
+    barrier between them, each task's rows in the order of Sec. 5 (see
+    ``executor.c``).  The schedule must satisfy Definition 2.1 (check it with
+    :func:`validate`).  Returns (x, threads used)."""
+    return Executor(m, pi, sigma).solve(b, threads)
 
 
 def same_bits(a, b) -> bool:
