@@ -210,44 +210,48 @@ ER_PROBS = (1e-4, 5e-4, 2e-3)                            # Sec. 6.2.4
 def _stencil(dims, offsets, diag_value: float, name: str) -> CSR:
     """Lower triangle of a Laplacian stencil.  ``offsets`` are (dx, dy, dz)
     triples that point to lower-numbered neighbours in natural order
-    idx = x + nx*(y + ny*z)."""
+    idx = x + nx*(y + ny*z).  Each row lists its neighbours by rising
+    column, then the diagonal."""
     nx, ny, nz = dims
     n = nx * ny * nz
     strides = (1, nx, nx * ny)
     offs = sorted(offsets, key=lambda o: o[0] * strides[0] + o[1] * strides[1] + o[2] * strides[2])
-    idx = np.arange(n, dtype=np.int64)
-    x = idx % nx
-    y = (idx // nx) % ny
-    z = idx // (nx * ny)
-    valid = []
-    for dx, dy, dz in offs:
-        ok = np.ones(n, dtype=bool)
-        if dx:
-            ok &= (x + dx >= 0) & (x + dx < nx)
-        if dy:
-            ok &= (y + dy >= 0) & (y + dy < ny)
-        if dz:
-            ok &= (z + dz >= 0) & (z + dz < nz)
-        valid.append(ok)
-    counts = np.ones(n, dtype=np.int64)
-    for ok in valid:
-        counts += ok
+    lin = np.array([dx * strides[0] + dy * strides[1] + dz * strides[2] for dx, dy, dz in offs] + [0],
+                   dtype=np.int64)
+
+    def valid(idx):
+        # [rows, len(offs) + 1]: neighbour inside the grid (the diagonal always)
+        x = idx % nx
+        y = (idx // nx) % ny
+        z = idx // (nx * ny)
+        ok = np.ones((idx.size, len(offs) + 1), dtype=bool)
+        for j, (dx, dy, dz) in enumerate(offs):
+            if dx:
+                ok[:, j] &= (x + dx >= 0) & (x + dx < nx)
+            if dy:
+                ok[:, j] &= (y + dy >= 0) & (y + dy < ny)
+            if dz:
+                ok[:, j] &= (z + dz >= 0) & (z + dz < nz)
+        return ok
+
+    chunk = 1 << 20
+    counts = np.empty(n, dtype=np.int64)
+    for r0 in range(0, n, chunk):
+        idx = np.arange(r0, min(n, r0 + chunk), dtype=np.int64)
+        counts[r0:r0 + idx.size] = valid(idx).sum(axis=1)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
     nnz = int(row_ptr[-1])
     col = np.empty(nnz, dtype=np.int32)
     val = np.empty(nnz, dtype=np.float64)
-    rank = np.zeros(n, dtype=np.int64)
-    for (dx, dy, dz), ok in zip(offs, valid):
-        off = dx * strides[0] + dy * strides[1] + dz * strides[2]
-        r = idx[ok]
-        p = row_ptr[r] + rank[ok]
-        col[p] = (r + off).astype(np.int32)
-        val[p] = -1.0
-        rank += ok
-    dpos = row_ptr[1:] - 1
-    col[dpos] = idx.astype(np.int32)
-    val[dpos] = diag_value
+    vals = np.full(len(offs) + 1, -1.0)
+    vals[-1] = diag_value
+    for r0 in range(0, n, chunk):
+        idx = np.arange(r0, min(n, r0 + chunk), dtype=np.int64)
+        ok = valid(idx)
+        a, b = row_ptr[r0], row_ptr[r0 + idx.size]
+        col[a:b] = (idx[:, None] + lin[None, :])[ok].astype(np.int32)
+        val[a:b] = np.broadcast_to(vals, ok.shape)[ok]
     m = CSR(n, row_ptr, col, val, name)
     m.meta.update(family="stencil", dims=dims)
     return m
@@ -424,6 +428,13 @@ def batch_mix(count: int = 64, seed: int = SEED_BASE + 100, lo_exp: float = 3.0,
                          [(-1, 0, 0), (0, -1, 0), (0, 0, -1)], 6.0, f"mix{i}_st3d7_{side}")
             out.append(m)
     return out
+
+
+def er_n1e7() -> CSR:
+    """The single-system benchmark matrix: Erdos-Renyi as Sec. 6.2.4 with
+    n = 1e7 and 10 off-diagonals per row on average (q = 20 / (n - 1))."""
+    n = 10_000_000
+    return erdos_renyi(n, 20.0 / (n - 1), SEED_BASE + 200, name="ER_n1e7_d10")
 
 
 def upper_of(m: CSR, name: str | None = None) -> CSR:

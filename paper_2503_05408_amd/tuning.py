@@ -84,52 +84,80 @@ def matrix_key(m, opts) -> str:
     return f"{h.hexdigest()}/{tri}/{sig}/{dev.name}/{getattr(dev, 'gcnArchName', '')}"
 
 
-def best_plan(m, opts=None, path: str | None = None, reps: int = 5, core_widths=(1,)):
-    """A plan for m with the measured-fastest schedule (GrowLocal or
-    wavefront), core width (`core_widths`: 1 = a core is a lane, 64 = a core
-    is a wavefront) and
-    execution form (persistent, plain, semi-asynchronous) for
-    gltrsv_solve_auto.  With `path`, the choice is read from / stored in the
+def best_plan(m, opts=None, path: str | None = None, reps: int = 5, core_widths=(1,), params=None,
+              local: bool = False):
+    """A plan for m with the measured-fastest schedule, core width, schedule
+    parameters and execution form for gltrsv_solve_auto.
+
+    Candidates: for every core width in `core_widths` (1 = a core is a
+    lane, 64 = a core is a wavefront), the wavefront schedule and GrowLocal
+    at every (k, L) pair in `params` (default: the options' own; the
+    paper's L is architecture-dependent, Sec. 3 footnote and Appendix C, and
+    its Table 7.5 varies k); with `local`, also the one-workgroup form
+    (exec_hint 2) on GrowLocal with k = 64, L = 5 and on the dealt wavefront
+    schedule.  Each candidate plan is timed in all its forms
+    (``Plan.tune``).  With `path`, the choice is read from / stored in the
     JSON table there, so a later process builds only the chosen plan.
-    Returns (plan, entry) with entry = {"schedule", "core_width", "form",
-    "us"}."""
+    Returns (plan, entry) with entry = {"label" (the candidate), "schedule",
+    "core_width", "k", "L", "exec_hint", "form", "us" (per candidate and
+    form)}."""
     import ctypes
     base = opts if opts is not None else B.gpu_opts()
+    params = [(int(k), float(L)) for k, L in (params or [(base.k, base.L)])]
 
-    def variant(kind, width):
+    def variant(kind, width, k=None, L=None, hint=None):
         o = B.PlanOpts()
         ctypes.memmove(ctypes.byref(o), ctypes.byref(base), ctypes.sizeof(o))
         o.schedule_kind = kind
         o.core_width = width
+        if k is not None:
+            o.k = k
+        if L is not None:
+            o.L = L
+        if hint is not None:
+            o.exec_hint = hint
         return o
 
+    cands = []   # (label, schedule name, opts)
+    for width in core_widths:
+        cands.append((f"wavefront/w{width}", "wavefront", width, None, None, base.exec_hint,
+                      variant(B.SCHED_WAVEFRONT, width)))
+        for k, L in params:
+            cands.append((f"growlocal-k{k}-L{L:g}/w{width}", "growlocal", width, k, L, base.exec_hint,
+                          variant(B.SCHED_GROWLOCAL, width, k, L)))
+    if local:
+        cands.append(("local-growlocal-k64-L5/w1", "growlocal", 1, 64, 5.0, 2,
+                      variant(B.SCHED_GROWLOCAL, 1, 64, 5.0, 2)))
+        cands.append(("local-wavefront/w1", "wavefront", 1, None, None, 2, variant(B.SCHED_WAVEFRONT, 1, hint=2)))
     names = {v: k for k, v in SCHEDULES.items()}
     forms = {v: k for k, v in B.EXEC_NAMES.items()}
-    key = f"{matrix_key(m, base)}/w{'-'.join(str(w) for w in core_widths)}" if path else None
+    sig = "/".join(c[0] for c in cands)
+    key = f"{matrix_key(m, base)}/{sig}" if path else None
     if path:
         hit = load_table(path).get(key)
         if isinstance(hit, dict) and hit.get("schedule") in names and hit.get("form") in forms:
-            plan = B.Plan(m, variant(names[hit["schedule"]], int(hit.get("core_width", 1))))
+            plan = B.Plan(m, variant(names[hit["schedule"]], int(hit.get("core_width", 1)), hit.get("k"),
+                                     hit.get("L"), hit.get("exec_hint")))
             plan.set_exec(forms[hit["form"]])
             return plan, hit
     best, best_us, times = None, None, {}
-    for width in core_widths:
-        for kind, sname in SCHEDULES.items():
-            plan = B.Plan(m, variant(kind, width))
-            res = plan.tune(reps=reps)
-            usable = res["us"]
-            for f, us in usable.items():
-                times[f"{sname}/w{width}/{f}"] = us
-            form = min(usable, key=usable.get)
-            if best_us is None or usable[form] < best_us:
-                if best is not None:
-                    best[0].close()
-                best, best_us = (plan, sname, width, form), usable[form]
-            else:
-                plan.close()
-    plan, sname, width, form = best
+    for label, sname, width, k, L, hint, o in cands:
+        plan = B.Plan(m, o)
+        res = plan.tune(reps=reps)
+        usable = res["us"]
+        for f, us in usable.items():
+            times[f"{label}/{f}"] = us
+        form = min(usable, key=usable.get)
+        if best_us is None or usable[form] < best_us:
+            if best is not None:
+                best[0].close()
+            best, best_us = (plan, label, sname, width, k, L, hint, form), usable[form]
+        else:
+            plan.close()
+    plan, label, sname, width, k, L, hint, form = best
     plan.set_exec(forms[form])
-    entry = {"schedule": sname, "core_width": width, "form": form, "us": times}
+    entry = {"label": label, "schedule": sname, "core_width": width, "k": k, "L": L, "exec_hint": hint,
+             "form": form, "us": times}
     if path:
         table = load_table(path)
         table[key] = entry

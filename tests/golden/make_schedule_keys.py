@@ -24,12 +24,13 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))   # repository root
 import paper_schedule_keys as K  # noqa: E402
 
 BENCH_N = 10_000_000
-BENCH_SEED_OFFSET = 200
 
 
 def bench_matrix():
     from paper_2503_05408_amd import gen
-    return gen.erdos_renyi(BENCH_N, 20.0 / (BENCH_N - 1), gen.SEED_BASE + BENCH_SEED_OFFSET, name="ER_n1e7_d10")
+    m = gen.er_n1e7()
+    assert m.n == BENCH_N
+    return m
 
 
 def main():

@@ -137,7 +137,7 @@ def test_best_plan_over_schedules_and_forms(tmp_path):
     with plan:
         assert len(entry["us"]) == 6 and entry["core_width"] == 1
         fastest = min(entry["us"], key=entry["us"].get)
-        assert fastest == f"{entry['schedule']}/w1/{entry['form']}"
+        assert fastest == f"{entry['label']}/{entry['form']}"
         kind = {"growlocal": B.SCHED_GROWLOCAL, "wavefront": B.SCHED_WAVEFRONT}[entry["schedule"]]
         assert plan.info()["schedule_kind"] == kind
         assert B.EXEC_NAMES[plan.info()["exec_form"]] == entry["form"]
@@ -170,10 +170,55 @@ def test_best_plan_with_wave_cores(tmp_path):
     with plan:
         assert len(entry["us"]) == 12               # 2 schedules x 2 widths x 3 forms
         fastest = min(entry["us"], key=entry["us"].get)
-        assert fastest == f"{entry['schedule']}/w{entry['core_width']}/{entry['form']}"
+        assert fastest == f"{entry['label']}/{entry['form']}"
         assert plan.info()["core_width"] == entry["core_width"]
         x = plan.solve_auto(torch.ones(m.n, dtype=torch.float64, device="cuda"))
         torch.cuda.synchronize()
+        assert oracle.same_bits(x.cpu().numpy(), want)
+
+
+def test_best_plan_over_schedule_parameters_and_one_workgroup(tmp_path):
+    # GrowLocal at several (k, L) (the paper's L is architecture-dependent,
+    # Sec. 3) and the one-workgroup form beside the device-wide ones
+    import torch
+    path = str(tmp_path / "kl.json")
+    m = gen.narrow_band(20_000, 0.05, 20.0, gen.SEED_BASE + 49)
+    want = oracle.solve(m, np.ones(m.n))
+    params = [(1 << 16, 50.0), (4096, 50.0), (1 << 16, 10.0)]
+    plan, entry = tuning.best_plan(m, B.gpu_opts(), path, reps=2, params=params, local=True)
+    print(entry, flush=True)
+    with plan:
+        # 1 wavefront + 3 GrowLocal candidates x 3 forms, 2 one-workgroup candidates x 4 forms
+        assert len(entry["us"]) == 4 * 3 + 2 * 4
+        fastest = min(entry["us"], key=entry["us"].get)
+        assert fastest == f"{entry['label']}/{entry['form']}"
+        if entry["schedule"] == "growlocal":
+            assert (entry["k"], entry["L"]) in params + [(64, 5.0)]
+        x = plan.solve_auto(torch.ones(m.n, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        assert plan.device_status() == 0
+        assert oracle.same_bits(x.cpu().numpy(), want)
+    # the stored choice, (k, L) and execution hint included, is rebuilt as is
+    table = tuning.load_table(path)
+    (key,) = table
+    table[key] = {"schedule": "growlocal", "core_width": 1, "k": 4096, "L": 50.0, "exec_hint": 0,
+                  "form": "persistent", "us": {}}
+    tuning.store_table(path, table)
+    plan, entry = tuning.best_plan(m, B.gpu_opts(), path, params=params, local=True)
+    with plan:
+        assert plan.opts.k == 4096 and plan.info()["exec_form"] == B.EXEC_PERSISTENT
+        x = plan.solve_auto(torch.ones(m.n, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        assert oracle.same_bits(x.cpu().numpy(), want)
+    table[key] = {"schedule": "wavefront", "core_width": 1, "k": None, "L": None, "exec_hint": 2,
+                  "form": "local", "us": {}}
+    tuning.store_table(path, table)
+    plan, entry = tuning.best_plan(m, B.gpu_opts(), path, params=params, local=True)
+    with plan:
+        assert plan.info()["exec_form"] == B.EXEC_LOCAL and plan.info()["local_groups"] > 0
+        x = plan.solve_auto(torch.ones(m.n, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        assert plan.device_status() == 0
         assert oracle.same_bits(x.cpu().numpy(), want)
 
 
