@@ -983,7 +983,7 @@ def extra_st27(B, stream, cal, reps: int) -> dict:
                     res, "lane solve_plain", bound, f"AUTO -> {sched} (k=65536 L=50 alpha0=1); wave cores: wavefront",
                     inf["supersteps"])
     kern = {"lane solve": "trsv_persistent", "lane solve_async": "trsv_async",
-            "wave-core solve_async": "trsv_wave_async"}.get(out["form"])
+            "wave-core solve_async": "trsv_stream_async"}.get(out["form"])
     traffic = measured_traffic("st27", kern) if kern else None
     out["roofline"].update(kernel=kern, traffic=traffic,
                            traffic_GBs=(traffic / (out["ms_per_step"] * 1e-3) / 1e9) if traffic else None)

@@ -145,8 +145,11 @@ int upload(T **dst, const std::vector<T> &src, int64_t *bytes)
 // Wave-core layout (opts.core_width = 64): positions in the order of Sec. 5,
 // tasks of a superstep longest first; per position the original row, its
 // off-diagonals in stored order (a column among the task's last kWaveRing
-// rows as kIntBit | rows back) and its diagonal.
-int upload_wave(gltrsv_plan *p, const gltrsv_csr *A, int64_t *bytes)
+// rows as kIntBit | rows back) and its diagonal.  Also the per-wave record
+// streams of the semi-asynchronous form for W waves (trsv_stream_async):
+// slot v holds the records of tasks v, v + W, ... and then a PAD word; the
+// arrays end with kStreamPad PAD slots.
+int upload_wave(gltrsv_plan *p, const gltrsv_csr *A, int64_t W, int64_t *bytes)
 {
     const int64_t n = p->n;
     const bool up = p->upper;
@@ -209,11 +212,43 @@ int upload_wave(gltrsv_plan *p, const gltrsv_csr *A, int64_t *bytes)
     }
     wptr[size_t(n)] = e;
     p->wsuper_host = wsuper;
+    // per-wave record streams: a header (kHdrBit | row, kIntBit on a task's
+    // first row; the diagonal) and the row's off-diagonals, row after row
+    const int64_t T = int64_t(tasks.size());
+    std::vector<int64_t> sbeg(size_t(W) + 1), stask(size_t(std::max<int64_t>(T, 1)), 0);
+    int64_t so = 0;
+    for (int64_t v = 0; v < W; v++) {
+        sbeg[size_t(v)] = so;
+        for (int64_t t = v; t < T; t += W) {
+            stask[size_t(t)] = so;
+            const int64_t q0 = wtask[size_t(t)], q1 = wtask[size_t(t) + 1];
+            so += (q1 - q0) + (wptr[size_t(q1)] - wptr[size_t(q0)]);
+        }
+        so++;   // the slot's PAD
+    }
+    sbeg[size_t(W)] = so;
+    std::vector<uint32_t> scol(size_t(so + dev::kStreamPad), kPadWord);
+    std::vector<double> sval(size_t(so + dev::kStreamPad), 0.0);
+    for (int64_t t = 0; t < T; t++) {
+        int64_t o = stask[size_t(t)];
+        for (int64_t q = wtask[size_t(t)]; q < wtask[size_t(t) + 1]; q++) {
+            scol[size_t(o)] = kHdrBit | (q == wtask[size_t(t)] ? kIntBit : 0u) | uint32_t(wrow[size_t(q)]);
+            sval[size_t(o)] = wdiag[size_t(q)];
+            o++;
+            for (int64_t k = wptr[size_t(q)]; k < wptr[size_t(q) + 1]; k++, o++) {
+                scol[size_t(o)] = wcol[size_t(k)];
+                sval[size_t(o)] = wval[size_t(k)];
+            }
+        }
+    }
+    p->stream_w = W;
     int rc;
     if ((rc = upload(&p->d_wrow, wrow, bytes)) || (rc = upload(&p->d_wptr, wptr, bytes)) ||
         (rc = upload(&p->d_wdiag, wdiag, bytes)) || (rc = upload(&p->d_wcol, wcol, bytes)) ||
         (rc = upload(&p->d_wval, wval, bytes)) || (rc = upload(&p->d_wtask, wtask, bytes)) ||
-        (rc = upload(&p->d_wsuper, wsuper, bytes)))
+        (rc = upload(&p->d_wsuper, wsuper, bytes)) || (rc = upload(&p->d_scol, scol, bytes)) ||
+        (rc = upload(&p->d_sval, sval, bytes)) || (rc = upload(&p->d_sbeg, sbeg, bytes)) ||
+        (rc = upload(&p->d_stask, stask, bytes)))
         return rc;
     return GLTRSV_OK;
 }
@@ -500,6 +535,10 @@ int gltrsv_plan_destroy(gltrsv_plan *p)
     (void)hipFree(p->d_wval);
     (void)hipFree(p->d_wtask);
     (void)hipFree(p->d_wsuper);
+    (void)hipFree(p->d_scol);
+    (void)hipFree(p->d_sval);
+    (void)hipFree(p->d_sbeg);
+    (void)hipFree(p->d_stask);
     (void)hipFree(p->d_lrec);
     (void)hipFree(p->d_linfo);
     delete p;
@@ -660,7 +699,25 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
     }
     p->core_width = opts->core_width == 64 ? 64 : 1;
     if (p->core_width == 64) {
-        if ((rc = upload_wave(p, A, &bytes))) {
+        // semi-asynchronous wave cores: at least two workgroups per CU, more
+        // for large systems (about one wave per 1,024 rows), all co-resident.
+        // Measured on MI355X: 512 workgroups were best for the n = 1e5 ER
+        // and NB sets, the full 2,048 for n = 1e7.  The per-wave streams are
+        // built for this grid.
+        int per_cu_wa = 0, cus_wa = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_wa, dev::trsv_stream_async, dev::kBlock, 0);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus_wa, hipDeviceAttributeMultiprocessorCount, p->device);
+        if (e != hipSuccess) {
+            gltrsv_plan_destroy(p);
+            return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
+        }
+        int64_t gwa = std::min<int64_t>(int64_t(per_cu_wa) * cus_wa,
+                                        std::max<int64_t>(2 * int64_t(cus_wa), (p->n + 4095) / 4096));
+        if (opts->grid_blocks > 0) gwa = std::min<int64_t>(opts->grid_blocks, int64_t(per_cu_wa) * cus_wa);
+        gwa = std::min<int64_t>(gwa, dev::kMaxGrid);
+        p->grid_wave_async = int(std::max<int64_t>(
+            1, std::min<int64_t>(gwa, (p->tasks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
+        if ((rc = upload_wave(p, A, int64_t(p->grid_wave_async) * dev::kWavesPerBlock, &bytes))) {
             gltrsv_plan_destroy(p);
             return rc;
         }
@@ -723,22 +780,6 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         int64_t gw = std::min<int64_t>(int64_t(per_cu_w) * cus, dev::kMaxGrid);
         if (opts->grid_blocks > 0) gw = std::min<int64_t>(gw, opts->grid_blocks);
         p->grid_wave = int(std::max<int64_t>(1, std::min<int64_t>(gw, (most + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
-        // semi-asynchronous: at least two workgroups per CU, more for large
-        // systems (about one wave per 1,024 rows: each wave has one row in
-        // flight), all co-resident.  Measured on MI355X: 512 workgroups were
-        // best for the n = 1e5 ER and NB sets, the full 2,048 for n = 1e7.
-        int per_cu_wa = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_wa, dev::trsv_wave_async, dev::kBlock, 0);
-        if (e != hipSuccess) {
-            gltrsv_plan_destroy(p);
-            return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
-        }
-        const int64_t wtasks = p->wsuper_host.empty() ? 0 : p->wsuper_host.back();
-        int64_t gwa = std::min<int64_t>(int64_t(per_cu_wa) * cus,
-                                        std::max<int64_t>(2 * int64_t(cus), (p->n + 4095) / 4096));
-        if (opts->grid_blocks > 0) gwa = std::min<int64_t>(opts->grid_blocks, int64_t(per_cu_wa) * cus);
-        p->grid_wave_async = int(std::max<int64_t>(
-            1, std::min<int64_t>(gwa, (wtasks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
     }
 #ifdef GLTRSV_TRACE
     {
@@ -908,9 +949,9 @@ int gltrsv_solve_async(gltrsv_plan *p, const double *b, double *x, void *stream)
     // static task orders; waves that wait long rob workgroups that have not
     // started, so no co-residency is needed (plain launches)
     if (p->core_width == 64) {
-        hipLaunchKernelGGL(dev::trsv_wave_async, dim3(p->grid_wave_async), dim3(dev::kBlock), 0, st, p->d_wrow,
-                           p->d_wptr, p->d_wdiag, p->d_wcol, p->d_wval, p->d_wtask, p->wsuper_host.back(), bb, x,
-                           err, lim, async_ticket(p, 2), p->d_aalive + 2 * dev::kMaxGrid,
+        hipLaunchKernelGGL(dev::trsv_stream_async, dim3(p->grid_wave_async), dim3(dev::kBlock), 0, st, p->d_scol,
+                           p->d_sval, p->d_sbeg, p->d_stask, p->wsuper_host.back(), bb, x, err, lim,
+                           async_ticket(p, 2), p->d_aalive + 2 * dev::kMaxGrid,
                            p->d_vnext + 2 * dev::kMaxGrid * dev::kWavesPerBlock, dev::kRobTicks, p->delay_ticks);
         HIP_TRY(hipGetLastError());
         p->last_stream = st;

@@ -53,6 +53,19 @@ constexpr int64_t kStealTicks = 20000;
 // Wavefront cores: rows of the same task this many back or fewer come from
 // a per-wave LDS ring (the layout marks them).
 constexpr int kWaveRing = 64;
+// Per-wave record streams (trsv_stream_async) are read in chunks of
+// kStreamSub 64-slot windows, and the arrays hold kStreamPad PAD slots past
+// the last stream (a chunk and the one after it are read from a chunk that
+// starts at or before a stream's PAD).  Measured on MI355X (wavefront
+// schedules, n = 1e7): one window a chunk keeps the kernel at 55 VGPRs and
+// eight waves per SIMD, and was fastest (27-point grid 4.72 ms, ER 3.38 ms;
+// two windows 4.96 / 3.45 ms at 71 VGPRs, four 5.31 / 3.62 ms at 87).
+#ifndef GLTRSV_STREAM_SUB
+#define GLTRSV_STREAM_SUB 1
+#endif
+constexpr int kStreamSub = GLTRSV_STREAM_SUB;
+constexpr int64_t kStreamChunk = 64 * kStreamSub;
+constexpr int64_t kStreamPad = 2 * kStreamChunk;
 
 // Batched launches: the state word of system i sits at state[i * kStateStride]
 // (one per 256 bytes, so waves polling different systems do not queue on
@@ -167,10 +180,10 @@ __global__ void trsv_wave(const int32_t *wrow, const int64_t *wptr, const double
                           const double *wval, const int64_t *wtask, const int32_t *wsuper, int32_t s0, int32_t s1,
                           const double *b, double *x, uint32_t *bar, uint32_t *alive, uint32_t *claim,
                           int32_t *err, int64_t spin_limit, int64_t steal_ticks, int64_t delay_ticks);
-__global__ void trsv_wave_async(const int32_t *wrow, const int64_t *wptr, const double *wdiag, const uint32_t *wcol,
-                                const double *wval, const int64_t *wtask, int32_t tasks, const double *b, double *x,
-                                int32_t *err, int64_t spin_limit, unsigned long long *ticket, uint32_t *alive,
-                                unsigned long long *vnext, int64_t rob_ticks, int64_t delay_ticks);
+__global__ void trsv_stream_async(const uint32_t *scol, const double *sval, const int64_t *sbeg, const int64_t *stask,
+                                  int32_t tasks, const double *b, double *x, int32_t *err, int64_t spin_limit,
+                                  unsigned long long *ticket, uint32_t *alive, unsigned long long *vnext,
+                                  int64_t rob_ticks, int64_t delay_ticks);
 // lane cores, semi-asynchronous; R right-hand sides (row-major, leading dimension ld)
 // (static chunk order; ticket/alive/vnext: the robbing of workgroups that
 // have not started, a start ticket, kMaxGrid alive words and 4 kMaxGrid
@@ -275,6 +288,12 @@ struct gltrsv_plan {
     std::vector<int32_t> wsuper_host;   // [S + 1] task range of each superstep
     int grid_wave = 0;                  // workgroups of the persistent wave kernel
     int grid_wave_async = 0;            // workgroups of the semi-asynchronous wave kernel
+    // per-wave record streams of the semi-asynchronous wave kernel (trsv_stream_async)
+    uint32_t *d_scol = nullptr;         // [sbeg[W] + kStreamPad] header, column or ring word
+    double *d_sval = nullptr;           // [sbeg[W] + kStreamPad] diagonal or A_ij
+    int64_t *d_sbeg = nullptr;          // [W + 1] first slot of each wave's stream
+    int64_t *d_stask = nullptr;         // [wave tasks] first slot of each task
+    int64_t stream_w = 0;               // W: waves the streams were built for (4 x grid_wave_async)
     // one-workgroup layout (opts.exec_hint = 2, local.h)
     uint8_t *d_lrec = nullptr;          // the records
     gltrsv::LocalRec *d_linfo = nullptr;   // [l_nrec]

@@ -927,16 +927,203 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))
     }
 }
 
-// Semi-asynchronous wave cores: x holds the not-yet-computed mark at the
-// start; wave w (the i-th wave of workgroup g is w = 4 g + i) runs tasks
-// w, w + W, ... in their global order (superstep by superstep) and waits
-// only for the values it gathers.  Progress and the robbing of workgroups
-// that have not started as for trsv_async, with tasks in place of chunks.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))) void trsv_wave_async(
-    const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr, const double *__restrict__ wdiag,
-    const uint32_t *__restrict__ wcol, const double *__restrict__ wval, const int64_t *__restrict__ wtask,
-    int32_t tasks, const double *b, double *x, int32_t *err, int64_t spin_limit, unsigned long long *ticket,
-    uint32_t *alive, unsigned long long *vnext, int64_t rob_ticks, int64_t delay_ticks)
+// ---------------------------------------------------------------------------
+// Per-wave record streams (semi-asynchronous wave cores).  Tasks are
+// numbered superstep by superstep; wave slot v (the i-th wave of workgroup
+// g is v = 4 g + i) runs tasks v, v + W, v + 2W, ... (W waves) and waits
+// only for the values it gathers.  The rows of those tasks are stored one after the other in slot v's stream
+// as records: a header slot (word HDR | row, INTL set on a task's first row;
+// value the diagonal) and then the row's off-diagonal entries in stored
+// order (word the column, or INTL | distance to one of the task's last
+// kWaveRing rows; value A_ij).  A wave reads its stream as 64-slot windows:
+// one load brings a short row's header and entries, and often the next
+// rows' too, so a row waits for its gathers only.  Per row the operations
+// and their order are those of wave_task (Eq. (2.1)).
+// ---------------------------------------------------------------------------
+
+// Loads need no branch and no select on their result (either makes the
+// compiler wait for every load in flight at once): every slot's stream ends
+// with a PAD word, and the arrays hold kStreamPad PAD slots past the last
+// stream, so any window a wave reads is in bounds, and lanes past its
+// stream's PAD (the next slot's records) are never used.
+__device__ __forceinline__ void stream_load(const uint32_t *__restrict__ scol, const double *__restrict__ sval,
+                                            int64_t o, uint32_t &w, double &v)
+{
+    const int64_t e = o + (threadIdx.x & 63);
+    w = scol[e];
+    v = sval[e];
+}
+
+// b_i for a header, x_j for an entry whose column is read from memory; any
+// other lane loads b[0] and its value is not used (ring entries are read
+// at their row's turn).
+__device__ __forceinline__ double stream_gather(uint32_t w, const double *b, const double *x)
+{
+    const bool hdr = (w & HDR) && w != PAD;
+    const bool mem = (w & (HDR | INTL)) == 0;
+    return load_x(hdr ? b + (w & MASK) : (mem ? x + w : b));   // b is not written during the solve
+}
+
+// First lane >= l (l <= 64) whose bit is set in m, else 64.
+__device__ __forceinline__ int first_from(unsigned long long m, int l)
+{
+    const unsigned long long r = l >= 64 ? 0ull : (m >> l) << l;
+    return r ? __builtin_ctzll(r) : 64;
+}
+
+// Records of [o, end) of a stream, o at the first record of task t and end
+// at a header or at the stream's PAD.  Returns kReady at `end`; kAbandon or
+// kFailed from a wait, with (o, t) set to the first record of the task
+// being run and its number (that task is run again from its start: the
+// ring holds rows of the running task only).  The stream is read in chunks
+// of kStreamSub 64-slot windows: a chunk's words and values arrive while
+// the chunk before it is worked on; its gathers are issued together and
+// waited for together, and the next chunk's loads go out behind them.
+__device__ __forceinline__ int stream_run(const uint32_t *__restrict__ scol, const double *__restrict__ sval,
+                                          int64_t &o, int64_t end, int32_t &t, int32_t W, const double *b, double *x,
+                                          double *ring, int32_t *err, int64_t spin_limit, const AsyncRob &rob)
+{
+    constexpr int kMore = 3;   // the window is used up, the stream goes on
+    const int lane = threadIdx.x & 63;
+    // the row being worked on (open) and the task bookkeeping
+    bool open = false;
+    uint32_t hw = 0;
+    double diag = 0.0, acc = 0.0;
+    int32_t q = -1;        // the row's position within its task
+    int32_t tt = t - W;    // task of the last task-first header seen
+    int64_t task_o = o;
+    // rows of window [wb, wb + 64) whose words, values and gathers are wc, vc, gc
+    auto step = [&](const uint32_t wc, const double vc, double gc, const int64_t wb) -> int {
+        const unsigned long long stop = __ballot((wc & HDR) != 0);   // headers and PAD
+        int l = 0;
+        for (;;) {
+            if (open) {
+                const int e = first_from(stop, l);   // the row's entries here are lanes [l, e)
+                const bool in = lane >= l && lane < e;
+                const bool ring_in = in && (wc & INTL);
+                if (__ballot(ring_in)) {
+                    if (ring_in) gc = ring[(q - int32_t(wc & MASK)) & (kWaveRing - 1)];
+                }
+                bool miss = in && unready(wc, gc);
+                if (__ballot(miss)) {
+                    int64_t since = -1;   // wall clock at the first rob check
+                    for (int64_t spins = 1;; spins++) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (miss) {
+                            gc = load_x(x + wc);
+                            miss = unready(wc, gc);
+                        }
+                        if (__ballot(miss) == 0ull) break;
+                        int r = kReady;
+                        if (spins > spin_limit) {
+                            if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            r = kFailed;
+                        } else if ((spins & 255) == 0) {
+                            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                                r = kFailed;
+                            } else if (rob.alive) {
+                                const int64_t now = int64_t(wall_clock64());
+                                if (since < 0) {
+                                    since = now;
+                                } else if (now - since > rob.rob_ticks) {
+                                    if (any_not_started(rob)) r = kAbandon;
+                                    since = now;
+                                }
+                            }
+                        }
+                        if (r != kReady) return r;
+                    }
+                }
+                const double prod = vc * gc;
+                for (int j = l; j < e; j++) acc = acc - readlane_f64(prod, j);
+                if (e == 64) return kMore;   // the row goes on in the next window
+                const double y = acc / diag;
+                if (lane == 0) {
+                    ring[q & (kWaveRing - 1)] = y;
+                    store_x(x + (hw & MASK), y);
+                }
+                __builtin_amdgcn_wave_barrier();
+                open = false;
+                l = e;
+            }
+            if (l == 64) return kMore;
+            // a header (or the end) at lane l
+            if (wb + l >= end) return kReady;
+            hw = uint32_t(__builtin_amdgcn_readlane(int(wc), l));
+            diag = readlane_f64(vc, l);
+            acc = readlane_f64(gc, l);
+            if (hw & INTL) {
+                tt += W;
+                task_o = wb + l;
+                q = 0;
+            } else {
+                q++;
+            }
+            open = true;
+            l++;
+        }
+    };
+    int64_t cb = o;   // first slot of the chunk
+    uint32_t w[kStreamSub];
+    double v[kStreamSub];
+#pragma unroll
+    for (int j = 0; j < kStreamSub; j++) stream_load(scol, sval, cb + 64 * j, w[j], v[j]);
+    int r;
+    for (;;) {
+        double g[kStreamSub];
+#pragma unroll
+        for (int j = 0; j < kStreamSub; j++) g[j] = stream_gather(w[j], b, x);
+        uint32_t wn[kStreamSub];
+        double vn[kStreamSub];
+#pragma unroll
+        for (int j = 0; j < kStreamSub; j++) stream_load(scol, sval, cb + kStreamChunk + 64 * j, wn[j], vn[j]);
+        r = kMore;
+#pragma unroll 1
+        for (int j = 0; j < kStreamSub && r == kMore; j++) {
+            // window j of the chunk, picked by selects (no copy of a register
+            // whose load is in flight)
+            uint32_t wc = w[0];
+            double vc = v[0], gc = g[0];
+#pragma unroll
+            for (int i = 1; i < kStreamSub; i++) {
+                wc = j == i ? w[i] : wc;
+                vc = j == i ? v[i] : vc;
+                gc = j == i ? g[i] : gc;
+            }
+            r = step(wc, vc, gc, cb + 64 * j);
+        }
+        if (r != kMore) break;
+#pragma unroll
+        for (int j = 0; j < kStreamSub; j++) {
+            w[j] = wn[j];
+            v[j] = vn[j];
+        }
+        cb += kStreamChunk;
+    }
+    if (r == kReady) {
+        o = end;
+        t = tt;
+    } else {
+        o = task_o;
+        t = tt;
+    }
+    return r;
+}
+
+// Semi-asynchronous wave cores over per-wave record streams: slot v's
+// records are [sbeg[v], sbeg[v + 1] - 1), its PAD at sbeg[v + 1] - 1; task
+// t's first record is at stask[t]; the grid is the one the streams were
+// built for (W = 4 x grid).  Progress: the earliest unfinished task depends
+// only on earlier tasks, which are finished or running, and its wave has
+// finished its own earlier tasks.  Waves blocked for long while some
+// workgroup has not started rob that workgroup's tasks in order (see
+// trsv_async); a robbed task runs from stask[k] to the first record of its
+// slot's next task.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))) void trsv_stream_async(
+    const uint32_t *__restrict__ scol, const double *__restrict__ sval, const int64_t *__restrict__ sbeg,
+    const int64_t *__restrict__ stask, int32_t tasks, const double *b, double *x, int32_t *err,
+    int64_t spin_limit, unsigned long long *ticket, uint32_t *alive, unsigned long long *vnext, int64_t rob_ticks,
+    int64_t delay_ticks)
 {
     __shared__ double ring[kWavesPerBlock][kWaveRing];
     // the robbing context lives in LDS: it is only read on the rare slow
@@ -949,21 +1136,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))
         s_norob = AsyncRob{nullptr, 0u, 0};
     }
     __syncthreads();
-    const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
+    const int32_t W = int32_t(gridDim.x) * kWavesPerBlock;
+    const int32_t v = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6);
     double *my_ring = ring[threadIdx.x >> 6];
-    auto run = [&](int32_t t, const AsyncRob &r) {
-        return wave_task<true>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring, err, spin_limit,
-                               r);
-    };
-    for (int32_t t = int32_t(blockIdx.x) * kWavesPerBlock + int32_t(threadIdx.x >> 6); t < tasks;) {
-        const int r = run(t, s_rob);
-        if (r == kFailed) return;
-        if (r == kReady) {
-            t += waves;
+    const int64_t mine_end = sbeg[v + 1] - 1;
+    int64_t o = sbeg[v];
+    int32_t t = v;
+    // one call site of the row loop: a robbed task runs in the turn after
+    // the own stream was abandoned, the abandoned task again after it
+    int64_t ro = -1, rend = 0;
+    int32_t rt = 0;
+    for (;;) {
+        const bool robbed = ro >= 0;
+        if (!robbed && o >= mine_end) return;
+        int64_t oo = robbed ? ro : o;
+        int32_t tt = robbed ? rt : t;
+        const int r = stream_run(scol, sval, oo, robbed ? rend : mine_end, tt, W, b, x, my_ring, err, spin_limit,
+                                 robbed ? s_norob : s_rob);
+        if (r == kFailed) return;   // a wait ran out: *err is set, the other waves leave too
+        if (robbed) {
+            ro = -1;   // (a robbed task is never abandoned)
             continue;
         }
-        const int64_t o = rob_item(s_rob, vnext, tasks, t);
-        if (o >= 0 && run(int32_t(o), s_norob) == kFailed) return;
+        o = oo;
+        t = tt;
+        if (r == kReady) return;
+        const int64_t k = rob_item(s_rob, vnext, tasks, t);
+        if (k >= 0) {
+            ro = stask[k];
+            rt = int32_t(k);
+            rend = k + W < tasks ? stask[k + W] : sbeg[(k % W) + 1] - 1;
+        }
     }
 }
 
@@ -1544,7 +1747,7 @@ __global__ __launch_bounds__(kBlock) void trsv_batched_async(const SysDesc *__re
 // with atomics would cost more than running them; instead the host merges
 // the systems' tasks into one global order (each system's own order kept)
 // and wave w runs global tasks w, w + W, ... in order.  Progress as for
-// trsv_wave_async: the earliest unfinished task depends only on earlier
+// trsv_stream_async: the earliest unfinished task depends only on earlier
 // tasks of its system, which come earlier in the global order and are
 // finished, and its wave has finished its own earlier tasks; waves blocked
 // for long while some workgroup has not started rob it (see trsv_async).
@@ -1556,7 +1759,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))
                                                                   unsigned long long *vnext, int64_t rob_ticks)
 {
     __shared__ double ring[kWavesPerBlock][kWaveRing];
-    __shared__ AsyncRob s_rob, s_norob;   // in LDS, as in trsv_wave_async
+    __shared__ AsyncRob s_rob, s_norob;   // in LDS, as in trsv_stream_async
     const uint32_t epoch = async_start(ticket, alive, 0);
     if (threadIdx.x == 0) {
         s_rob = AsyncRob{alive, epoch, rob_ticks};
