@@ -998,7 +998,11 @@ __device__ __forceinline__ int stream_run(const uint32_t *__restrict__ scol, con
         int l = 0;
         for (;;) {
             if (open) {
-                const int e = first_from(stop, l);   // the row's entries here are lanes [l, e)
+                // the row's entries here are lanes [l, e); both are the same
+                // in every lane, which the compiler is told so that the
+                // subtraction loop below runs on scalar registers
+                l = __builtin_amdgcn_readfirstlane(l);
+                const int e = __builtin_amdgcn_readfirstlane(first_from(stop, l));
                 const bool in = lane >= l && lane < e;
                 const bool ring_in = in && (wc & INTL);
                 if (__ballot(ring_in)) {
