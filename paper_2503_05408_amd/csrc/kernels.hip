@@ -864,7 +864,8 @@ __device__ __forceinline__ int wave_task(const int32_t *__restrict__ wrow, const
                 if (r != kReady) return r;
             }
             const double p = v * g;
-            const int cnt = int(min<int64_t>(64, e1 - base));
+            // (the same in every lane: a scalar loop, see stream_run)
+            const int cnt = __builtin_amdgcn_readfirstlane(int(min<int64_t>(64, e1 - base)));
             for (int l = 0; l < cnt; l++) acc = acc - readlane_f64(p, l);
             v = vn;
             g = gn;
