@@ -215,14 +215,15 @@ int upload_wave(gltrsv_plan *p, const gltrsv_csr *A, int64_t W, int64_t *bytes)
     // per-wave record streams: a header (kHdrBit | row, kIntBit on a task's
     // first row; the diagonal) and the row's off-diagonals, row after row
     const int64_t T = int64_t(tasks.size());
-    std::vector<int64_t> sbeg(size_t(W) + 1), stask(size_t(std::max<int64_t>(T, 1)), 0);
+    std::vector<int64_t> sbeg(size_t(W) + 1), stask(size_t(std::max<int64_t>(T, 1)), 0), ssize(size_t(T), 0);
     int64_t so = 0;
     for (int64_t v = 0; v < W; v++) {
         sbeg[size_t(v)] = so;
         for (int64_t t = v; t < T; t += W) {
             stask[size_t(t)] = so;
             const int64_t q0 = wtask[size_t(t)], q1 = wtask[size_t(t) + 1];
-            so += (q1 - q0) + (wptr[size_t(q1)] - wptr[size_t(q0)]);
+            ssize[size_t(t)] = (q1 - q0) + (wptr[size_t(q1)] - wptr[size_t(q0)]);
+            so += ssize[size_t(t)];
         }
         so++;   // the slot's PAD
     }
@@ -242,6 +243,7 @@ int upload_wave(gltrsv_plan *p, const gltrsv_csr *A, int64_t W, int64_t *bytes)
         }
     }
     p->stream_w = W;
+    p->ssize_host = std::move(ssize);
     int rc;
     if ((rc = upload(&p->d_wrow, wrow, bytes)) || (rc = upload(&p->d_wptr, wptr, bytes)) ||
         (rc = upload(&p->d_wdiag, wdiag, bytes)) || (rc = upload(&p->d_wcol, wcol, bytes)) ||
@@ -370,15 +372,105 @@ struct gltrsv_batch {
     int32_t keep_waves = 0;            // waves that never retire (see dev::kRetireTicks)
     bool async_exec = false;           // semi-asynchronous kernel (no barriers)
     bool wave = false;                 // ... on wavefront cores (every plan has core width 64)
-    int32_t *d_gsys = nullptr;         // wave cores: system of each global task
-    int32_t *d_gtask = nullptr;        // ... and its task index in that system
-    int64_t gtasks = 0;
+    int64_t gtasks = 0;                // wave cores: tasks of the global order
+    // wave cores: the batch as one system (see stream_rebase): its record
+    // stream over the global task order, each system's first row there, and
+    // the concatenated b and x
+    uint32_t *d_bscol = nullptr;
+    double *d_bsval = nullptr;
+    int64_t *d_bbeg = nullptr;         // [4 grid + 1] first slot of each wave's stream
+    int64_t *d_btask = nullptr;        // [gtasks] first slot of each global task
+    int64_t *d_boff = nullptr;         // [count] first row of each system in bcat / xcat
+    double *d_bcat = nullptr;
+    double *d_xcat = nullptr;
+    int64_t rows = 0;                  // rows of all systems
     // wave cores: robbing of workgroups that have not started (start ticket,
     // kMaxGrid alive words, 4 kMaxGrid robbed-prefix words)
     unsigned long long *d_wticket = nullptr;
     uint32_t *d_walive = nullptr;
     unsigned long long *d_wvnext = nullptr;
 };
+
+// Semi-asynchronous batches of wavefront-core systems: the record stream of
+// the global task order (gsys[g], gtask[g]) for the grid of the launch
+// (at most `resident` workgroups, and grid_blocks if positive), built on the
+// device from the systems' own streams with rows and columns shifted to
+// the concatenated vectors; plus those vectors and the robbing words.
+static int batch_stream(gltrsv_batch *bt, const std::vector<int32_t> &gsys, const std::vector<int32_t> &gtask,
+                        int resident, int grid_blocks)
+{
+    const int64_t G = int64_t(gsys.size());
+    if (G > INT32_MAX) return set_error(GLTRSV_ERANGE, "too many tasks in a wave-core batch");
+    std::vector<int64_t> boff(size_t(bt->count) + 1, 0);
+    for (int32_t i = 0; i < bt->count; i++) boff[size_t(i) + 1] = boff[size_t(i)] + bt->plans[size_t(i)]->n;
+    bt->rows = boff.back();
+    if (bt->rows > kMaxRows)
+        return set_error(GLTRSV_ERANGE, "a semi-asynchronous wave-core batch holds at most 2^30 - 1 rows");
+    int64_t grid = std::min<int64_t>(std::max(1, resident), dev::kMaxGrid);
+    if (grid_blocks > 0) grid = std::min<int64_t>(grid, grid_blocks);
+    grid = std::max<int64_t>(1, std::min<int64_t>(grid, (G + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock));
+    bt->grid = int(grid);
+    const int64_t W = grid * dev::kWavesPerBlock;
+    std::vector<int64_t> bbeg(size_t(W) + 1), btask(size_t(std::max<int64_t>(G, 1)), 0), bsize(size_t(std::max<int64_t>(G, 1)), 0);
+    int64_t so = 0;
+    for (int64_t v = 0; v < W; v++) {
+        bbeg[size_t(v)] = so;
+        for (int64_t g = v; g < G; g += W) {
+            btask[size_t(g)] = so;
+            bsize[size_t(g)] = bt->plans[size_t(gsys[size_t(g)])]->ssize_host[size_t(gtask[size_t(g)])];
+            so += bsize[size_t(g)];
+        }
+        so++;   // the slot's PAD
+    }
+    bbeg[size_t(W)] = so;
+    std::vector<dev::StreamSrc> src(size_t(bt->count));
+    for (int32_t i = 0; i < bt->count; i++) {
+        const gltrsv_plan *pl = bt->plans[size_t(i)];
+        src[size_t(i)] = dev::StreamSrc{pl->d_scol, pl->d_sval, pl->d_stask, boff[size_t(i)]};
+    }
+    boff.pop_back();
+    int64_t bytes = 0;
+    int rc;
+    int32_t *d_gsys = nullptr, *d_gtask = nullptr;
+    int64_t *d_bsize = nullptr;
+    dev::StreamSrc *d_src = nullptr;
+    std::vector<unsigned long long> ticket(16, 0ull), vnext(size_t(dev::kMaxGrid * dev::kWavesPerBlock), 0ull);
+    std::vector<uint32_t> alive(size_t(dev::kMaxGrid), 0u);
+    auto release = [&]() {
+        (void)hipFree(d_gsys);
+        (void)hipFree(d_gtask);
+        (void)hipFree(d_bsize);
+        (void)hipFree(d_src);
+    };
+    if ((rc = upload(&d_gsys, gsys, &bytes)) || (rc = upload(&d_gtask, gtask, &bytes)) ||
+        (rc = upload(&d_bsize, bsize, &bytes)) || (rc = upload(&d_src, src, &bytes)) ||
+        (rc = upload(&bt->d_bbeg, bbeg, &bytes)) || (rc = upload(&bt->d_btask, btask, &bytes)) ||
+        (rc = upload(&bt->d_boff, boff, &bytes)) || (rc = upload(&bt->d_wticket, ticket, &bytes)) ||
+        (rc = upload(&bt->d_walive, alive, &bytes)) || (rc = upload(&bt->d_wvnext, vnext, &bytes))) {
+        release();
+        return rc;
+    }
+    const size_t slots = size_t(so + dev::kStreamPad);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&bt->d_bscol), slots * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_bsval), slots * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_bcat), size_t(std::max<int64_t>(1, bt->rows)) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_xcat), size_t(std::max<int64_t>(1, bt->rows)) * sizeof(double));
+    // every slot starts as PAD (the slots' ends and the padding keep it)
+    if (e == hipSuccess) e = hipMemset(bt->d_bscol, 0xFF, slots * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(bt->d_bsval, 0, slots * sizeof(double));
+    if (e == hipSuccess && G > 0) {
+        const int64_t blocks = std::min<int64_t>(4096, (G + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock);
+        hipLaunchKernelGGL(dev::stream_rebase, dim3(unsigned(blocks)), dim3(dev::kBlock), 0, nullptr, d_src, d_gsys,
+                           d_gtask, bt->d_btask, d_bsize, G, bt->d_bscol, bt->d_bsval);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    release();
+    if (e != hipSuccess)
+        return set_error(e == hipErrorOutOfMemory ? GLTRSV_ENOMEM : GLTRSV_EHIP,
+                         std::string("batch stream: ") + hipGetErrorString(e));
+    return GLTRSV_OK;
+}
 
 extern "C" {
 
@@ -1208,8 +1300,13 @@ int gltrsv_batch_destroy(gltrsv_batch *bt)
     (void)hipFree(bt->d_done);
     (void)hipFree(bt->d_finished);
     (void)hipFree(bt->d_err);
-    (void)hipFree(bt->d_gsys);
-    (void)hipFree(bt->d_gtask);
+    (void)hipFree(bt->d_bscol);
+    (void)hipFree(bt->d_bsval);
+    (void)hipFree(bt->d_bbeg);
+    (void)hipFree(bt->d_btask);
+    (void)hipFree(bt->d_boff);
+    (void)hipFree(bt->d_bcat);
+    (void)hipFree(bt->d_xcat);
     (void)hipFree(bt->d_wticket);
     (void)hipFree(bt->d_walive);
     (void)hipFree(bt->d_wvnext);
@@ -1300,7 +1397,7 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
     }
     int per_cu = 0, cus = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, bt->wave ? reinterpret_cast<const void *>(dev::trsv_batched_wave_async)
+        &per_cu, bt->wave ? reinterpret_cast<const void *>(dev::trsv_stream_async)
                           : reinterpret_cast<const void *>(dev::trsv_batched), dev::kBlock, 0);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
     if (e != hipSuccess) {
@@ -1334,13 +1431,7 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
             }
         }
         bt->gtasks = int64_t(gsys.size());
-        int64_t bytes = 0;
-        int rc;
-        std::vector<unsigned long long> ticket(16, 0ull), vnext(size_t(dev::kMaxGrid * dev::kWavesPerBlock), 0ull);
-        std::vector<uint32_t> alive(size_t(dev::kMaxGrid), 0u);
-        if ((rc = upload(&bt->d_gsys, gsys, &bytes)) || (rc = upload(&bt->d_gtask, gtask, &bytes)) ||
-            (rc = upload(&bt->d_wticket, ticket, &bytes)) || (rc = upload(&bt->d_walive, alive, &bytes)) ||
-            (rc = upload(&bt->d_wvnext, vnext, &bytes))) {
+        if (int rc = batch_stream(bt, gsys, gtask, per_cu * cus, opts->grid_blocks)) {
             gltrsv_batch_destroy(bt);
             return rc;
         }
@@ -1348,7 +1439,7 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
     int grid = std::max(1, per_cu * cus);
     if (opts->grid_blocks > 0) grid = std::min(grid, opts->grid_blocks);
     grid = int(std::max<int64_t>(1, std::min<int64_t>(grid, (chunks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock)));
-    bt->grid = grid;
+    if (!bt->wave) bt->grid = grid;   // (wave cores: the grid the batch stream was built for)
     bt->keep_waves = dev::keep_waves_for(widest_of(bt->plans), bt->per_claim, grid);
     *out = bt;
     return GLTRSV_OK;
@@ -1406,20 +1497,30 @@ static int batch_enqueue(gltrsv_batch *bt, hipStream_t st)
         int64_t widest_n = 1;
         for (auto *pl : bt->plans) widest_n = std::max(widest_n, pl->n);
         const unsigned gx = unsigned(std::min<int64_t>(256, (widest_n + dev::kBlock - 1) / dev::kBlock));
-        hipLaunchKernelGGL(dev::fill_unready_sys, dim3(gx, unsigned(bt->count)), dim3(dev::kBlock), 0, st, bt->d_desc,
-                           bt->count);
         hipLaunchKernelGGL(dev::batch_reset, dim3(unsigned(std::max(1, (bt->count + dev::kBlock - 1) / dev::kBlock))),
                            dim3(dev::kBlock), 0, st, bt->d_state, bt->d_done, bt->count, 0, bt->d_finished,
                            bt->d_err);
         if (bt->wave) {
-            // static global task order; waves that wait long rob workgroups
-            // that have not started, so no co-residency is needed
-            hipLaunchKernelGGL(dev::trsv_batched_wave_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st,
-                               bt->d_desc, bt->d_gsys, bt->d_gtask, bt->gtasks, bt->d_err, int64_t(5000000),
-                               bt->d_wticket, bt->d_walive, bt->d_wvnext, dev::kRobTicks);
+            // the batch as one system over the global task order (static;
+            // waves that wait long rob workgroups that have not started, so
+            // no co-residency is needed)
+            const unsigned cx = gx;
+            hipLaunchKernelGGL(dev::batch_concat, dim3(cx, unsigned(bt->count)), dim3(dev::kBlock), 0, st, bt->d_desc,
+                               bt->d_boff, bt->d_bcat, true);
+            const int64_t fb = std::min<int64_t>(4096, (bt->rows + dev::kBlock - 1) / dev::kBlock);
+            hipLaunchKernelGGL(dev::fill_unready, dim3(unsigned(std::max<int64_t>(1, fb))), dim3(dev::kBlock), 0, st,
+                               reinterpret_cast<unsigned long long *>(bt->d_xcat), bt->rows);
+            hipLaunchKernelGGL(dev::trsv_stream_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st,
+                               bt->d_bscol, bt->d_bsval, bt->d_bbeg, bt->d_btask, int32_t(bt->gtasks), bt->d_bcat,
+                               bt->d_xcat, bt->d_err, int64_t(5000000), bt->d_wticket, bt->d_walive, bt->d_wvnext,
+                               dev::kRobTicks, int64_t(0));
+            hipLaunchKernelGGL(dev::batch_concat, dim3(cx, unsigned(bt->count)), dim3(dev::kBlock), 0, st, bt->d_desc,
+                               bt->d_boff, bt->d_xcat, false);
             HIP_TRY(hipGetLastError());
             return GLTRSV_OK;
         }
+        hipLaunchKernelGGL(dev::fill_unready_sys, dim3(gx, unsigned(bt->count)), dim3(dev::kBlock), 0, st, bt->d_desc,
+                           bt->count);
         hipLaunchKernelGGL(dev::trsv_batched_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st, bt->d_desc,
                            bt->count, bt->d_state, bt->d_finished, bt->d_err, int64_t(5000000), bt->per_claim,
                            int64_t(0));

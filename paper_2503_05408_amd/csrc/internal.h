@@ -124,6 +124,17 @@ struct SysDesc {
     int32_t ntasks;
 };
 
+// A system's record stream and its first row in a batch (stream_rebase).
+struct StreamSrc {
+    const uint32_t *scol;
+    const double *sval;
+    const int64_t *stask;
+    int64_t off;
+};
+__global__ void stream_rebase(const StreamSrc *src, const int32_t *gsys, const int32_t *gtask, const int64_t *boff,
+                              const int64_t *bsize, int64_t ntasks, uint32_t *scol, double *sval);
+__global__ void batch_concat(const SysDesc *sys, const int64_t *off, double *cat, bool in);
+
 // Chunks a semi-asynchronous batched launch lets one system have in flight:
 // about four supersteps of its average width.
 inline int32_t async_window(int64_t chunks, int32_t S)
@@ -143,13 +154,6 @@ __global__ void trsv_batched_async(const SysDesc *__restrict__ sys, int32_t coun
                                    int64_t quantum);
 // x[0, n) = the not-yet-computed mark
 __global__ void fill_unready(unsigned long long *x, int64_t n);
-// the same for systems planned with wavefront cores: global task g is task
-// gtask[g] of system gsys[g] (each system's tasks in their order), run in
-// order by wave g mod W of a co-resident grid
-__global__ void trsv_batched_wave_async(const SysDesc *__restrict__ sys, const int32_t *__restrict__ gsys,
-                                        const int32_t *__restrict__ gtask, int64_t ntasks, int32_t *err,
-                                        int64_t spin_limit, unsigned long long *ticket, uint32_t *alive,
-                                        unsigned long long *vnext, int64_t rob_ticks);
 
 // Fills the plan's stream (d_word, d_value: lay.pk.slots entries) on the
 // device from A, the schedule order and the host layout; synchronous.
@@ -294,6 +298,7 @@ struct gltrsv_plan {
     int64_t *d_sbeg = nullptr;          // [W + 1] first slot of each wave's stream
     int64_t *d_stask = nullptr;         // [wave tasks] first slot of each task
     int64_t stream_w = 0;               // W: waves the streams were built for (4 x grid_wave_async)
+    std::vector<int64_t> ssize_host;    // [wave tasks] slots of each task's records
     // one-workgroup layout (opts.exec_hint = 2, local.h)
     uint8_t *d_lrec = nullptr;          // the records
     gltrsv::LocalRec *d_linfo = nullptr;   // [l_nrec]

@@ -791,41 +791,6 @@ __device__ __forceinline__ void wave_load(const uint32_t *__restrict__ wcol, con
     }
 }
 
-// Semi-asynchronous wave cores: gathers that returned the not-yet-computed
-// mark are read again until every lane holds a computed value.  Returns
-// false once the spin limit is hit (setting *err) or another wave failed.
-__device__ __forceinline__ int wave_await(uint32_t c, double &g, const double *x, int32_t *err, int64_t spin_limit,
-                                          const AsyncRob &rob)
-{
-    bool miss = (c & (HDR | INTL)) == 0 && static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
-    if (__ballot(miss) == 0ull) return kReady;
-    int64_t since = -1;   // wall clock at the first rob check
-    for (int64_t spins = 1;; spins++) {
-        __builtin_amdgcn_s_sleep(1);
-        if (miss) {
-            g = load_x(x + c);
-            miss = static_cast<unsigned long long>(__double_as_longlong(g)) == kUnready;
-        }
-        if (__ballot(miss) == 0ull) return kReady;
-        if (spins > spin_limit) {
-            if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return kFailed;
-        }
-        if ((spins & 255) == 0) {
-            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return kFailed;
-            if (rob.alive) {
-                const int64_t now = int64_t(wall_clock64());
-                if (since < 0) {
-                    since = now;
-                } else if (now - since > rob.rob_ticks) {
-                    if (any_not_started(rob)) return kAbandon;
-                    since = now;
-                }
-            }
-        }
-    }
-}
-
 // Scalar registers of the wave-core kernels.  Measured on MI355X: with 88 or
 // more only 7 of their 256-thread workgroups are resident per CU (both the
 // compiler and the occupancy query report 8), with 80 or fewer all 8 are.
@@ -836,14 +801,11 @@ __device__ __forceinline__ int wave_await(uint32_t c, double &g, const double *x
 #endif
 constexpr int kWaveSgprs = GLTRSV_WAVE_SGPRS;
 
-// Runs one wave-core task; returns kReady when done, or (semi-asynchronous
-// form) kAbandon / kFailed from the wait (rows stored so far are final).
-template <bool kAsync>
-__device__ __forceinline__ int wave_task(const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr,
-                                         const double *__restrict__ wdiag, const uint32_t *__restrict__ wcol,
-                                         const double *__restrict__ wval, int64_t t0, int64_t t1, const double *b,
-                                         double *x, double *ring, int32_t *err, int64_t spin_limit,
-                                         const AsyncRob &rob)
+// Runs one wave-core task: the rows at positions [t0, t1) of the layout.
+__device__ __forceinline__ void wave_task(const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr,
+                                          const double *__restrict__ wdiag, const uint32_t *__restrict__ wcol,
+                                          const double *__restrict__ wval, int64_t t0, int64_t t1, const double *b,
+                                          double *x, double *ring)
 {
     const int lane = threadIdx.x & 63;
     for (int64_t t = t0; t < t1; t++) {
@@ -859,10 +821,6 @@ __device__ __forceinline__ int wave_task(const int32_t *__restrict__ wrow, const
             double vn, gn;
             uint32_t cn;
             wave_load(wcol, wval, base + 64 + lane, e1, x, ring, q, vn, gn, cn);
-            if constexpr (kAsync) {
-                const int r = wave_await(c, g, x, err, spin_limit, rob);
-                if (r != kReady) return r;
-            }
             const double p = v * g;
             // (the same in every lane: a scalar loop, see stream_run)
             const int cnt = __builtin_amdgcn_readfirstlane(int(min<int64_t>(64, e1 - base)));
@@ -878,7 +836,6 @@ __device__ __forceinline__ int wave_task(const int32_t *__restrict__ wrow, const
         }
         __builtin_amdgcn_wave_barrier();
     }
-    return kReady;
 }
 
 // Supersteps [s0, s1) of a wave-core plan.  One superstep per launch needs
@@ -897,13 +854,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))
     const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
     const int32_t slot = int32_t(threadIdx.x >> 6) * int32_t(gridDim.x) + int32_t(blockIdx.x);
     double *my_ring = ring[threadIdx.x >> 6];
-    __shared__ AsyncRob s_norob;
-    if (threadIdx.x == 0) s_norob = AsyncRob{nullptr, 0u, 0};
-    __syncthreads();
-    auto run_task = [&](int32_t t) {
-        wave_task<false>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring, err, spin_limit,
-                         s_norob);
-    };
+    auto run_task = [&](int32_t t) { wave_task(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring); };
     if (!claim) {   // one superstep, no other workgroup to wait for
         for (int32_t t = wsuper[s0] + slot; t < wsuper[s0 + 1]; t += waves) run_task(t);
         return;
@@ -1747,46 +1698,50 @@ __global__ __launch_bounds__(kBlock) void trsv_batched_async(const SysDesc *__re
     }
 }
 
-// Semi-asynchronous batches of wavefront-core systems.  A task of a wave
-// core is small (a wavefront schedule's task is one row), so claiming tasks
-// with atomics would cost more than running them; instead the host merges
-// the systems' tasks into one global order (each system's own order kept)
-// and wave w runs global tasks w, w + W, ... in order.  Progress as for
-// trsv_stream_async: the earliest unfinished task depends only on earlier
-// tasks of its system, which come earlier in the global order and are
-// finished, and its wave has finished its own earlier tasks; waves blocked
-// for long while some workgroup has not started rob it (see trsv_async).
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))) void trsv_batched_wave_async(const SysDesc *__restrict__ sys,
-                                                                  const int32_t *__restrict__ gsys,
-                                                                  const int32_t *__restrict__ gtask, int64_t ntasks,
-                                                                  int32_t *err, int64_t spin_limit,
-                                                                  unsigned long long *ticket, uint32_t *alive,
-                                                                  unsigned long long *vnext, int64_t rob_ticks)
+// Semi-asynchronous batches of wavefront-core systems run as one system: the
+// systems' b are copied into one vector, their rows and columns shifted by
+// the system's first row there (off[i]), and trsv_stream_async runs over a
+// stream of the batch's global task order; x is copied back at the end.
+// stream_rebase copies task g (task gtask[g] of system gsys[g]) from that
+// system's own stream to boff[g] of the batch stream, one wave per task.
+__global__ __launch_bounds__(kBlock) void stream_rebase(const StreamSrc *__restrict__ src,
+                                                        const int32_t *__restrict__ gsys,
+                                                        const int32_t *__restrict__ gtask,
+                                                        const int64_t *__restrict__ boff,
+                                                        const int64_t *__restrict__ bsize, int64_t ntasks,
+                                                        uint32_t *__restrict__ scol, double *__restrict__ sval)
 {
-    __shared__ double ring[kWavesPerBlock][kWaveRing];
-    __shared__ AsyncRob s_rob, s_norob;   // in LDS, as in trsv_stream_async
-    const uint32_t epoch = async_start(ticket, alive, 0);
-    if (threadIdx.x == 0) {
-        s_rob = AsyncRob{alive, epoch, rob_ticks};
-        s_norob = AsyncRob{nullptr, 0u, 0};
-    }
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
     const int64_t waves = int64_t(gridDim.x) * kWavesPerBlock;
-    auto run = [&](int64_t g, const AsyncRob &r) {
-        const SysDesc &d = sys[gsys[g]];
-        const int32_t t = gtask[g];
-        return wave_task<true>(d.wrow, d.wptr, d.wdiag, d.wcol, d.wval, d.wtask[t], d.wtask[t + 1], d.b, d.x,
-                               ring[threadIdx.x >> 6], err, spin_limit, r);
-    };
-    for (int64_t g = int64_t(blockIdx.x) * kWavesPerBlock + int64_t(threadIdx.x >> 6); g < ntasks;) {
-        const int r = run(g, s_rob);
-        if (r == kFailed) return;   // a wait ran out: *err is set, the other waves leave too
-        if (r == kReady) {
-            g += waves;
-            continue;
+    for (int64_t g = int64_t(blockIdx.x) * kWavesPerBlock + (threadIdx.x >> 6); g < ntasks; g += waves) {
+        const StreamSrc S = src[gsys[g]];
+        const int64_t from = S.stask[gtask[g]], to = boff[g], len = bsize[g];
+        const uint32_t off = uint32_t(S.off);
+        for (int64_t k = lane; k < len; k += 64) {
+            uint32_t w = S.scol[from + k];
+            if (w & HDR)
+                w = (w & (HDR | INTL)) | ((w & MASK) + off);   // a row header
+            else if (!(w & INTL))
+                w += off;                                     // a column read from memory
+            scol[to + k] = w;
+            sval[to + k] = S.sval[from + k];
         }
-        const int64_t o = rob_item(s_rob, vnext, ntasks, g);
-        if (o >= 0 && run(o, s_norob) == kFailed) return;
+    }
+}
+
+// b of system blockIdx.y into cat[off[y] ...] (in = true), or cat back into
+// its x (in = false).
+__global__ __launch_bounds__(kBlock) void batch_concat(const SysDesc *__restrict__ sys,
+                                                       const int64_t *__restrict__ off, double *cat, bool in)
+{
+    const SysDesc &d = sys[blockIdx.y];
+    const int64_t o = off[blockIdx.y];
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < d.n; i += stride) {
+        if (in)
+            cat[o + i] = d.b[i];
+        else
+            d.x[i] = cat[o + i];
     }
 }
 
