@@ -572,6 +572,30 @@ int gltrsv_plan_local_size(const gltrsv_plan *plan, int64_t *rec_bytes, int64_t 
  * GLTRSV_UPPER (as opts.triangle).  Host only. */
 int gltrsv_local_layout(const gltrsv_csr *A, int32_t triangle, const int32_t *core, const int32_t *superstep,
                         void *rec, int64_t *rec_bytes, uint32_t *info, int64_t *records);
+
+/* The per-wave record streams that the semi-asynchronous solve of a
+ * wave-core plan (opts.core_width = 64) reads, built on the host from a
+ * schedule (core[n] and superstep[n] per row, host arrays, checked against
+ * Definition 2.1) for `waves` waves (1 .. 4 x 2048; a plan uses 4 x its
+ * grid), without a plan or a device.  Tasks are the runs of one core in a
+ * superstep, numbered superstep by superstep in the order of Sec. 5 with
+ * each superstep's tasks longest first; wave v runs tasks v, v + waves,
+ * ...  Its stream, [sbeg[v], sbeg[v + 1] - 1) of scol/sval followed by one
+ * 0xFFFFFFFF word, holds those tasks' rows one after another as records: a
+ * header (scol = 0x80000000 | row, with 0x40000000 also set on a task's
+ * first row; sval = the diagonal) and the row's off-diagonals in stored
+ * order (scol = the column, or 0x40000000 | d for the row d positions
+ * earlier in the same task when d < 64; sval = A_ij).  Task t's header is
+ * at stask[t].  The arrays end with 0xFFFFFFFF slots (value 0) that the
+ * kernel reads past a stream's end.  With any of scol, sval, sbeg, stask
+ * NULL it stores the sizes in *slots (scol/sval slots, padding included)
+ * and *tasks; otherwise those must hold them, sbeg has waves + 1 entries,
+ * and the arrays receive the streams.  triangle: GLTRSV_LOWER or
+ * GLTRSV_UPPER (as opts.triangle; rows and columns are the matrix's own).
+ * Host only. */
+int gltrsv_wave_streams(const gltrsv_csr *A, int32_t triangle, const int32_t *core, const int32_t *superstep,
+                        int64_t waves, uint32_t *scol, double *sval, int64_t *sbeg, int64_t *stask, int64_t *slots,
+                        int64_t *tasks);
 int gltrsv_plan_local_records(const gltrsv_plan *plan, void *rec, int64_t rec_bytes, uint32_t *info, int64_t records);
 
 /* ------------------------------------------------------- execution forms */

@@ -115,6 +115,7 @@ SIGNATURES = {
     "gltrsv_plan_local_size": ([P, P, P], i32),
     "gltrsv_plan_local_records": ([P, P, i64, P, i64], i32),
     "gltrsv_local_layout": ([P, i32, P, P, P, P, P, P], i32),
+    "gltrsv_wave_streams": ([P, i32, P, P, i64, P, P, P, P, P, P], i32),
     "gltrsv_solve_multi": ([P, P, P, i32, P], i32),
     "gltrsv_plan_set_spin_limit": ([P, i64], i32),
     "gltrsv_plan_set_steal_wait": ([P, i64], i32),
@@ -235,6 +236,26 @@ def schedule(m, opts: PlanOpts | None = None):
     _check(load().gltrsv_schedule(h.ref, ctypes.byref(opts), _np_ptr(core), _np_ptr(sup), ctypes.byref(S)),
            "gltrsv_schedule")
     return core, sup, S.value
+
+
+def wave_streams(m, core, superstep, waves: int, triangle: int = 0):
+    """Host-built per-wave record streams of the schedule (core, superstep)
+    per row for `waves` waves: dict of scol (uint32), sval (float64), sbeg
+    (int64 [waves + 1]) and stask (int64 [tasks])."""
+    h = _HostCsr(m)
+    core = np.ascontiguousarray(core, dtype=np.int32)
+    superstep = np.ascontiguousarray(superstep, dtype=np.int32)
+    ns, nt = ctypes.c_int64(0), ctypes.c_int64(0)
+    f = load().gltrsv_wave_streams
+    _check(f(h.ref, int(triangle), _np_ptr(core), _np_ptr(superstep), int(waves), None, None, None, None,
+             ctypes.byref(ns), ctypes.byref(nt)), "gltrsv_wave_streams")
+    scol = np.empty(max(1, ns.value), dtype=np.uint32)
+    sval = np.empty(max(1, ns.value), dtype=np.float64)
+    sbeg = np.empty(int(waves) + 1, dtype=np.int64)
+    stask = np.empty(max(1, nt.value), dtype=np.int64)
+    _check(f(h.ref, int(triangle), _np_ptr(core), _np_ptr(superstep), int(waves), _np_ptr(scol), _np_ptr(sval),
+             _np_ptr(sbeg), _np_ptr(stask), ctypes.byref(ns), ctypes.byref(nt)), "gltrsv_wave_streams")
+    return {"scol": scol[:ns.value], "sval": sval[:ns.value], "sbeg": sbeg, "stask": stask[:nt.value]}
 
 
 def local_layout(m, core, superstep, triangle: int = 0):

@@ -16,14 +16,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgltrsv.so")
-SOURCES_HOST = ["analysis.cpp", "local.cpp"]
+SOURCES_HOST = ["analysis.cpp", "local.cpp", "wave.cpp"]
 SOURCES_HIP = ["kernels.hip", "gltrsv.hip", "serve.hip", "pack.hip", "local.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GLTRSV_ARCH", "gfx950")
 
 
 def sources():
-    return [os.path.join(CSRC, f) for f in SOURCES_HOST + SOURCES_HIP + ["analysis.h", "internal.h", "local.h"]] + [
+    return [os.path.join(CSRC, f) for f in SOURCES_HOST + SOURCES_HIP + ["analysis.h", "internal.h", "local.h", "wave.h"]] + [
         os.path.join(ROOT, "include", "gltrsv.h")]
 
 

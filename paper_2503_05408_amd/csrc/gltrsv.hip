@@ -142,115 +142,21 @@ int upload(T **dst, const std::vector<T> &src, int64_t *bytes)
     return upload_raw(dst, src.data(), src.size(), bytes);
 }
 
-// Wave-core layout (opts.core_width = 64): positions in the order of Sec. 5,
-// tasks of a superstep longest first; per position the original row, its
-// off-diagonals in stored order (a column among the task's last kWaveRing
-// rows as kIntBit | rows back) and its diagonal.  Also the per-wave record
-// streams of the semi-asynchronous form for W waves (trsv_stream_async):
-// slot v holds the records of tasks v, v + W, ... and then a PAD word; the
-// arrays end with kStreamPad PAD slots.
+// Wave-core layouts (wave.h) of a plan, the record streams for W waves.
 int upload_wave(gltrsv_plan *p, const gltrsv_csr *A, int64_t W, int64_t *bytes)
 {
-    const int64_t n = p->n;
-    const bool up = p->upper;
-    std::vector<std::pair<int64_t, int64_t>> tasks;   // (first position in perm, length)
-    std::vector<int32_t> wsuper(size_t(p->S) + 1, 0);
-    int64_t pos = 0;
-    for (int32_t s = 0; s < p->S; s++) {
-        const size_t first = tasks.size();
-        while (pos < n && p->superstep[size_t(p->perm[size_t(pos)])] == s) {
-            const int32_t c = p->core[size_t(p->perm[size_t(pos)])];
-            int64_t q = pos;
-            while (q < n && p->superstep[size_t(p->perm[size_t(q)])] == s && p->core[size_t(p->perm[size_t(q)])] == c)
-                q++;
-            tasks.emplace_back(pos, q - pos);
-            pos = q;
-        }
-        std::stable_sort(tasks.begin() + std::ptrdiff_t(first), tasks.end(),
-                         [](const std::pair<int64_t, int64_t> &a, const std::pair<int64_t, int64_t> &b) {
-                             return a.second > b.second;
-                         });
-        wsuper[size_t(s) + 1] = int32_t(tasks.size());
-    }
-    // new position of every row, and the task of every new position
-    const size_t un = static_cast<size_t>(n);
-    std::vector<int32_t> wrow(un), task_of(un);
-    std::vector<int64_t> wtask(tasks.size() + 1, 0), newpos(un);
-    int64_t np = 0;
-    for (size_t t = 0; t < tasks.size(); t++) {
-        wtask[t] = np;
-        for (int64_t q = 0; q < tasks[t].second; q++, np++) {
-            const int32_t v = p->perm[size_t(tasks[t].first + q)];
-            const int32_t row = up ? int32_t(n - 1 - v) : v;
-            wrow[size_t(np)] = row;
-            task_of[size_t(np)] = int32_t(t);
-            newpos[size_t(row)] = np;
-        }
-    }
-    wtask[tasks.size()] = np;
-    const int64_t noff = A->nnz - n;
-    std::vector<int64_t> wptr(size_t(n) + 1, 0);
-    const size_t uoff = static_cast<size_t>(std::max<int64_t>(noff, 0));
-    std::vector<double> wdiag(un);
-    std::vector<uint32_t> wcol(uoff);
-    std::vector<double> wval(uoff);
-    int64_t e = 0;
-    for (int64_t t = 0; t < n; t++) {
-        const int32_t row = wrow[size_t(t)];
-        const int64_t beg = A->row_ptr[row], end = A->row_ptr[row + 1];
-        const int64_t d = up ? beg : end - 1;
-        wdiag[size_t(t)] = A->val[d];
-        wptr[size_t(t)] = e;
-        for (int64_t k = up ? beg + 1 : beg; k < (up ? end : end - 1); k++, e++) {
-            const int32_t c = A->col[k];
-            const int64_t pc = newpos[size_t(c)];
-            const int64_t back = t - pc;
-            const bool same = task_of[size_t(pc)] == task_of[size_t(t)] && back > 0 && back < dev::kWaveRing;
-            wcol[size_t(e)] = same ? (kIntBit | uint32_t(back)) : uint32_t(c);
-            wval[size_t(e)] = A->val[k];
-        }
-    }
-    wptr[size_t(n)] = e;
-    p->wsuper_host = wsuper;
-    // per-wave record streams: a header (kHdrBit | row, kIntBit on a task's
-    // first row; the diagonal) and the row's off-diagonals, row after row
-    const int64_t T = int64_t(tasks.size());
-    std::vector<int64_t> sbeg(size_t(W) + 1), stask(size_t(std::max<int64_t>(T, 1)), 0), ssize(size_t(T), 0);
-    int64_t so = 0;
-    for (int64_t v = 0; v < W; v++) {
-        sbeg[size_t(v)] = so;
-        for (int64_t t = v; t < T; t += W) {
-            stask[size_t(t)] = so;
-            const int64_t q0 = wtask[size_t(t)], q1 = wtask[size_t(t) + 1];
-            ssize[size_t(t)] = (q1 - q0) + (wptr[size_t(q1)] - wptr[size_t(q0)]);
-            so += ssize[size_t(t)];
-        }
-        so++;   // the slot's PAD
-    }
-    sbeg[size_t(W)] = so;
-    std::vector<uint32_t> scol(size_t(so + dev::kStreamPad), kPadWord);
-    std::vector<double> sval(size_t(so + dev::kStreamPad), 0.0);
-    for (int64_t t = 0; t < T; t++) {
-        int64_t o = stask[size_t(t)];
-        for (int64_t q = wtask[size_t(t)]; q < wtask[size_t(t) + 1]; q++) {
-            scol[size_t(o)] = kHdrBit | (q == wtask[size_t(t)] ? kIntBit : 0u) | uint32_t(wrow[size_t(q)]);
-            sval[size_t(o)] = wdiag[size_t(q)];
-            o++;
-            for (int64_t k = wptr[size_t(q)]; k < wptr[size_t(q) + 1]; k++, o++) {
-                scol[size_t(o)] = wcol[size_t(k)];
-                sval[size_t(o)] = wval[size_t(k)];
-            }
-        }
-    }
+    WaveLayout L;
+    build_wave_layout(view_of(A), p->upper, p->core.data(), p->superstep.data(), p->S, p->perm, W, &L);
+    p->wsuper_host = L.wsuper;
     p->stream_w = W;
-    p->ssize_host = std::move(ssize);
+    p->ssize_host = std::move(L.ssize);
     int rc;
-    if ((rc = upload(&p->d_wrow, wrow, bytes)) || (rc = upload(&p->d_wptr, wptr, bytes)) ||
-        (rc = upload(&p->d_wdiag, wdiag, bytes)) || (rc = upload(&p->d_wcol, wcol, bytes)) ||
-        (rc = upload(&p->d_wval, wval, bytes)) || (rc = upload(&p->d_wtask, wtask, bytes)) ||
-        (rc = upload(&p->d_wsuper, wsuper, bytes)) || (rc = upload(&p->d_scol, scol, bytes)) ||
-        (rc = upload(&p->d_sval, sval, bytes)) || (rc = upload(&p->d_sbeg, sbeg, bytes)) ||
-        (rc = upload(&p->d_stask, stask, bytes)))
+    if ((rc = upload(&p->d_wrow, L.wrow, bytes)) || (rc = upload(&p->d_wptr, L.wptr, bytes)) ||
+        (rc = upload(&p->d_wdiag, L.wdiag, bytes)) || (rc = upload(&p->d_wcol, L.wcol, bytes)) ||
+        (rc = upload(&p->d_wval, L.wval, bytes)) || (rc = upload(&p->d_wtask, L.wtask, bytes)) ||
+        (rc = upload(&p->d_wsuper, L.wsuper, bytes)) || (rc = upload(&p->d_scol, L.scol, bytes)) ||
+        (rc = upload(&p->d_sval, L.sval, bytes)) || (rc = upload(&p->d_sbeg, L.sbeg, bytes)) ||
+        (rc = upload(&p->d_stask, L.stask, bytes)))
         return rc;
     return GLTRSV_OK;
 }
@@ -450,7 +356,7 @@ static int batch_stream(gltrsv_batch *bt, const std::vector<int32_t> &gsys, cons
         release();
         return rc;
     }
-    const size_t slots = size_t(so + dev::kStreamPad);
+    const size_t slots = size_t(so + kStreamPad);
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&bt->d_bscol), slots * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_bsval), slots * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_bcat), size_t(std::max<int64_t>(1, bt->rows)) * sizeof(double));
@@ -595,6 +501,50 @@ int gltrsv_local_layout(const gltrsv_csr *A, int32_t triangle, const int32_t *co
         return set_error(GLTRSV_EINVAL, "buffer sizes differ from the layout's (query them with null buffers)");
     if (!lay.rec.empty()) std::memcpy(rec, lay.rec.data(), lay.rec.size());
     if (!lay.info.empty()) std::memcpy(info, lay.info.data(), lay.info.size() * sizeof(LocalRec));
+    return GLTRSV_OK;
+}
+
+int gltrsv_wave_streams(const gltrsv_csr *A, int32_t triangle, const int32_t *core, const int32_t *superstep,
+                        int64_t waves, uint32_t *scol, double *sval, int64_t *sbeg, int64_t *stask, int64_t *slots,
+                        int64_t *tasks)
+{
+    if (!A || !slots || !tasks || (A->n > 0 && (!core || !superstep))) return set_error(GLTRSV_EINVAL, "null argument");
+    if (triangle != GLTRSV_LOWER && triangle != GLTRSV_UPPER) return set_error(GLTRSV_EINVAL, "bad triangle");
+    if (waves < 1 || waves > int64_t(dev::kMaxGrid) * dev::kWavesPerBlock)
+        return set_error(GLTRSV_EINVAL, "waves must be 1 .. 4 x the largest grid");
+    const bool upper = triangle == GLTRSV_UPPER;
+    const CsrView V = view_of(A);
+    std::string msg;
+    int rc = upper ? check_csr_upper(V, true, &msg) : check_csr(V, true, &msg);
+    if (rc) return set_error(rc, msg);
+    Mirror mir;
+    if (upper) mir = mirror_upper(V);
+    const CsrView D = upper ? mir.view() : V;
+    const int64_t n = A->n;
+    Schedule s;
+    s.core.resize(size_t(n));
+    s.superstep.resize(size_t(n));
+    for (int64_t v = 0; v < n; v++) {
+        const int64_t row = upper ? n - 1 - v : v;
+        s.core[size_t(v)] = core[row];
+        s.superstep[size_t(v)] = superstep[row];
+        s.S = std::max(s.S, superstep[row] + 1);
+    }
+    if ((rc = validate_schedule(D, s, &msg))) return set_error(rc, "schedule: " + msg);
+    const std::vector<int32_t> perm = schedule_order(n, s.core.data(), s.superstep.data(), s.S);
+    WaveLayout L;
+    build_wave_layout(V, upper, s.core.data(), s.superstep.data(), s.S, perm, waves, &L);
+    if (!scol || !sval || !sbeg || !stask) {
+        *slots = int64_t(L.scol.size());
+        *tasks = int64_t(L.stask.size());
+        return GLTRSV_OK;
+    }
+    if (*slots != int64_t(L.scol.size()) || *tasks != int64_t(L.stask.size()))
+        return set_error(GLTRSV_EINVAL, "buffer sizes differ from the streams' (query them with null buffers)");
+    std::memcpy(scol, L.scol.data(), L.scol.size() * sizeof(uint32_t));
+    std::memcpy(sval, L.sval.data(), L.sval.size() * sizeof(double));
+    std::memcpy(sbeg, L.sbeg.data(), L.sbeg.size() * sizeof(int64_t));
+    if (!L.stask.empty()) std::memcpy(stask, L.stask.data(), L.stask.size() * sizeof(int64_t));
     return GLTRSV_OK;
 }
 

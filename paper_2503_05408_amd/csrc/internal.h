@@ -10,6 +10,7 @@
 #include "../../include/gltrsv.h"
 #include "analysis.h"
 #include "local.h"
+#include "wave.h"
 
 namespace gltrsv {
 
@@ -50,22 +51,8 @@ constexpr int kMaxGrid = kGroup * 128;   // workgroups of a persistent launch at
 // act when some workgroup cannot start or has stalled.
 constexpr int64_t kStealTicks = 20000;
 
-// Wavefront cores: rows of the same task this many back or fewer come from
-// a per-wave LDS ring (the layout marks them).
-constexpr int kWaveRing = 64;
-// Per-wave record streams (trsv_stream_async) are read in chunks of
-// kStreamSub 64-slot windows, and the arrays hold kStreamPad PAD slots past
-// the last stream (a chunk and the one after it are read from a chunk that
-// starts at or before a stream's PAD).  Measured on MI355X (wavefront
-// schedules, n = 1e7): one window a chunk keeps the kernel at 55 VGPRs and
-// eight waves per SIMD, and was fastest (27-point grid 4.72 ms, ER 3.38 ms;
-// two windows 4.96 / 3.45 ms at 71 VGPRs, four 5.31 / 3.62 ms at 87).
-#ifndef GLTRSV_STREAM_SUB
-#define GLTRSV_STREAM_SUB 1
-#endif
-constexpr int kStreamSub = GLTRSV_STREAM_SUB;
-constexpr int64_t kStreamChunk = 64 * kStreamSub;
-constexpr int64_t kStreamPad = 2 * kStreamChunk;
+// (Wavefront cores: kWaveRing and the record-stream constants are in
+// wave.h.)
 
 // Batched launches: the state word of system i sits at state[i * kStateStride]
 // (one per 256 bytes, so waves polling different systems do not queue on
