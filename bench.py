@@ -79,7 +79,8 @@ def kernel_sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in ("paper_2503_05408_amd/csrc/kernels.hip", "paper_2503_05408_amd/csrc/internal.h",
-              "paper_2503_05408_amd/csrc/analysis.cpp", "paper_2503_05408_amd/csrc/analysis.h"):
+              "paper_2503_05408_amd/csrc/analysis.cpp", "paper_2503_05408_amd/csrc/analysis.h",
+              "paper_2503_05408_amd/csrc/wave.cpp", "paper_2503_05408_amd/csrc/wave.h"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -834,7 +835,7 @@ def bench_batch(args):
         "speedup_vs_plain": (ms_plain / ms_b) if ms_plain else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": {"async": "trsv_batched_async", "wave": "trsv_batched_wave_async"}.get(form, "trsv_batched"),
+                     "kernel": {"async": "trsv_batched_async", "wave": "trsv_stream_async"}.get(form, "trsv_batched"),
                      "alg_bytes_per_launch": alg},
     }
     bt.close()
@@ -1056,14 +1057,15 @@ def extra_c3(B, stream, cal, reps: int) -> dict:
     worst_a = max(bounds, key=lambda d: d["async_ms"])
     return {
         "workload": "64 independent systems, n = floor(10^U[3,6]), ER/NB/2-D/3-D mix, b = ones; "
-                    "one hipGraph-replayed semi-asynchronous launch on wavefront cores",
+                    "one hipGraph replay: b copied into one vector, one semi-asynchronous record-stream "
+                    "launch over the batch's global task order on wavefront cores, x copied back",
         "rows": rows, "nnz": nnz, "exact": bool(exact and exact_plain), "ms_per_step": ms_b,
         "value": rows / (ms_b * 1e-3) if exact else 0.0, "unit": "rows/s",
         "plain_sequential_ms": ms_plain, "speedup_vs_plain": ms_plain / ms_b,
         "roofline": {"bound": "hbm", "alg_bytes_per_solve": alg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "achieved": alg / (ms_b * 1e-3) / 1e9, "frac": alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "kernel": "trsv_batched_wave_async",
-                     "traffic": measured_traffic("c3", "trsv_batched_wave_async")},
+                     "kernel": "trsv_stream_async",
+                     "traffic": measured_traffic("c3", "trsv_stream_async")},
         "third_bound": {"ms": worst["ms"], "supersteps": worst["supersteps"],
                         "critical_entries": worst["critical_entries"],
                         "formula": "the largest single-system BSP bound (lane-core AUTO plans) of the 64: "
