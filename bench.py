@@ -21,6 +21,10 @@ Erdos-Renyi system) the default line carries:
   cpu_baseline the serial oracle and, as parallel_executor, the schedule run
               on all host threads (oracle/executor.c, the paper's kind of
               CPU executor, Sec. 6.1).
+Each roofline object names its kernel and carries, besides the algorithmic
+bytes against HBM, the measured traffic and VALU issue of that kernel from
+the committed rocprofv3 counters (profiles/*_traffic.json), over this run's
+time; both are null once the kernel sources differ from the profiled ones.
 """
 from __future__ import annotations
 
@@ -99,6 +103,28 @@ def measured_traffic(workload_name: str, kernel: str):
         return None
     k = t["per_launch"][kernel]
     return k["fetch_bytes"] + k["write_bytes"]
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per 4 cycles per SIMD
+VALU_PEAK_INSTS = 256 * 4 * 2.4e9 / 4
+
+
+def measured_valu(workload_name: str, kernel: str, ms: float):
+    """VALU issue of a kernel from the committed rocprofv3 counters
+    (SQ_INSTS_VALU per launch) over its live-measured time, against the issue
+    peak; None when no summary exists or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"trsv_{workload_name}_traffic.json")
+    if not os.path.exists(path) or not ms:
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    k = t.get("per_launch", {}).get(kernel, {})
+    if t.get("kernel_sources_hash") != kernel_sources_hash() or "valu_insts" not in k:
+        return None
+    rate = k["valu_insts"] / (ms * 1e-3)
+    return {"insts_per_launch": k["valu_insts"], "achieved": rate, "peak": VALU_PEAK_INSTS,
+            "unit": "wave64 VALU instructions/s", "frac": rate / VALU_PEAK_INSTS,
+            "source": f"profiles/trsv_{workload_name}_traffic.json (SQ_INSTS_VALU) over this run's time"}
 
 
 def cpu_model() -> str:
@@ -548,6 +574,7 @@ def main():
             "gather_floor_ms": gather_ms,
             "frac_of_gather_floor": gather_ms / kern_ms if kern_ms > 0 else None,
             "traffic_GBs": (traffic / (kern_ms * 1e-3) / 1e9) if traffic else None,
+            "valu": measured_valu("er1e7", "trsv_persistent", kern_ms),
         },
     }
     prop = torch.cuda.get_device_properties(0)
@@ -987,7 +1014,8 @@ def extra_st27(B, stream, cal, reps: int) -> dict:
             "wave-core solve_async": "trsv_stream_async"}.get(out["form"])
     traffic = measured_traffic("st27", kern) if kern else None
     out["roofline"].update(kernel=kern, traffic=traffic,
-                           traffic_GBs=(traffic / (out["ms_per_step"] * 1e-3) / 1e9) if traffic else None)
+                           traffic_GBs=(traffic / (out["ms_per_step"] * 1e-3) / 1e9) if traffic else None,
+                           valu=measured_valu("st27", kern, out["ms_per_step"]) if kern else None)
     return out
 
 
@@ -1065,7 +1093,8 @@ def extra_c3(B, stream, cal, reps: int) -> dict:
         "roofline": {"bound": "hbm", "alg_bytes_per_solve": alg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "achieved": alg / (ms_b * 1e-3) / 1e9, "frac": alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "kernel": "trsv_stream_async",
-                     "traffic": measured_traffic("c3", "trsv_stream_async")},
+                     "traffic": measured_traffic("c3", "trsv_stream_async"),
+                     "valu": measured_valu("c3", "trsv_stream_async", ms_b)},
         "third_bound": {"ms": worst["ms"], "supersteps": worst["supersteps"],
                         "critical_entries": worst["critical_entries"],
                         "formula": "the largest single-system BSP bound (lane-core AUTO plans) of the 64: "
