@@ -12,7 +12,9 @@ the CPU oracle's (checked before timing).  Besides the headline (the n = 1e7
 Erdos-Renyi system) the default line carries:
   c2_st27     the 3-D 27-point 216^3 grid in every single-system form;
   c3_batch    64 systems in one hipGraph launch against 64 plain solves;
-  c5_serve    a 10 s Poisson serving run, every result compared bit for bit;
+  c5_serve    a 10 s Poisson serving run, every result compared bit for bit
+              (c5_serve_other_form: the same stream with the server's other
+              execution form, BSP or semi-asynchronous);
   third_bound the bound t >= t0 + S t_sync + sum_s max_p w(task) t_entry of
               Sec. 2.3 / Eq. (3.1) with measured constants (and, for the
               semi-asynchronous forms, t0 + levels t_hop), also per key;
@@ -607,6 +609,11 @@ def main():
         log("C5: serving ...")
         out["c5_serve"] = serve_run(args.pool, args.rate, args.serve_seconds, args.quantum_us, args.async_exec)
         log(f"  p50 {out['c5_serve']['latency_ms']['p50']} ms p99 {out['c5_serve']['latency_ms']['p99']} ms")
+        # the same stream through the other execution form of the server
+        out["c5_serve_other_form"] = serve_run(args.pool, args.rate, args.serve_seconds, args.quantum_us,
+                                               not args.async_exec)
+        log(f"  ({out['c5_serve_other_form']['form']}) p50 {out['c5_serve_other_form']['latency_ms']['p50']} ms "
+            f"p99 {out['c5_serve_other_form']['latency_ms']['p99']} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(m)
