@@ -753,6 +753,7 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
             gltrsv_plan_destroy(p);
             return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
         }
+        per_cu_wa = std::min(per_cu_wa, dev::kStreamWgPerCu);   // (the query counts no scalar registers)
         int64_t gwa = std::min<int64_t>(int64_t(per_cu_wa) * cus_wa,
                                         std::max<int64_t>(2 * int64_t(cus_wa), (p->n + 4095) / 4096));
         if (opts->grid_blocks > 0) gwa = std::min<int64_t>(opts->grid_blocks, int64_t(per_cu_wa) * cus_wa);
@@ -1354,6 +1355,7 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
         gltrsv_batch_destroy(bt);
         return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
     }
+    if (bt->wave) per_cu = std::min(per_cu, dev::kStreamWgPerCu);   // (see kStreamSgprs)
     int64_t chunks = 0;   // wave units of work: chunks, or tasks on wavefront cores
     for (auto *pl : bt->plans) chunks += bt->wave ? (pl->wsuper_host.empty() ? 0 : pl->wsuper_host.back()) : pl->chunks;
     if (bt->wave) {

@@ -53,6 +53,19 @@ constexpr int64_t kStealTicks = 20000;
 
 // (Wavefront cores: kWaveRing and the record-stream constants are in
 // wave.h.)
+// Scalar registers of the record-stream kernel (trsv_stream_async): with 96
+// it needs no spills (92 used; at 80 it spilled 19 into vector lanes), and
+// MI355X then holds 7 of its 256-thread workgroups per CU, although the
+// occupancy query reports 8.  Measured: grids of 7 per CU were 2-4% faster
+// than the 80-register build at 8 per CU (27-point 216^3 3.96 against 4.08
+// ms, the 64-system batch 6.05 against 6.28 ms); a grid of 8 per CU with 96
+// registers waited on workgroups that could not start (3.5 s per solve).
+// So the kernel's grids are capped at kStreamWgPerCu per CU.
+#ifndef GLTRSV_STREAM_SGPRS
+#define GLTRSV_STREAM_SGPRS 96
+#endif
+constexpr int kStreamSgprs = GLTRSV_STREAM_SGPRS;
+constexpr int kStreamWgPerCu = kStreamSgprs > 80 ? 7 : 8;
 
 // Batched launches: the state word of system i sits at state[i * kStateStride]
 // (one per 256 bytes, so waves polling different systems do not queue on

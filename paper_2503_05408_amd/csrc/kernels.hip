@@ -1075,7 +1075,7 @@ __device__ __forceinline__ int stream_run(const uint32_t *__restrict__ scol, con
 // workgroup has not started rob that workgroup's tasks in order (see
 // trsv_async); a robbed task runs from stask[k] to the first record of its
 // slot's next task.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))) void trsv_stream_async(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kStreamSgprs))) void trsv_stream_async(
     const uint32_t *__restrict__ scol, const double *__restrict__ sval, const int64_t *__restrict__ sbeg,
     const int64_t *__restrict__ stask, int32_t tasks, const double *b, double *x, int32_t *err,
     int64_t spin_limit, unsigned long long *ticket, uint32_t *alive, unsigned long long *vnext, int64_t rob_ticks,
