@@ -317,7 +317,8 @@ static int batch_stream(gltrsv_batch *bt, const std::vector<int32_t> &gsys, cons
     grid = std::max<int64_t>(1, std::min<int64_t>(grid, (G + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock));
     bt->grid = int(grid);
     const int64_t W = grid * dev::kWavesPerBlock;
-    std::vector<int64_t> bbeg(size_t(W) + 1), btask(size_t(std::max<int64_t>(G, 1)), 0), bsize(size_t(std::max<int64_t>(G, 1)), 0);
+    const size_t ng = size_t(std::max<int64_t>(G, 1));
+    std::vector<int64_t> bbeg(size_t(W) + 1), btask(ng, 0), bsize(ng, 0);
     int64_t so = 0;
     for (int64_t v = 0; v < W; v++) {
         bbeg[size_t(v)] = so;
@@ -359,8 +360,9 @@ static int batch_stream(gltrsv_batch *bt, const std::vector<int32_t> &gsys, cons
     const size_t slots = size_t(so + kStreamPad);
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&bt->d_bscol), slots * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_bsval), slots * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_bcat), size_t(std::max<int64_t>(1, bt->rows)) * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_xcat), size_t(std::max<int64_t>(1, bt->rows)) * sizeof(double));
+    const size_t vec = size_t(std::max<int64_t>(1, bt->rows)) * sizeof(double);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_bcat), vec);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&bt->d_xcat), vec);
     // every slot starts as PAD (the slots' ends and the padding keep it)
     if (e == hipSuccess) e = hipMemset(bt->d_bscol, 0xFF, slots * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(bt->d_bsval, 0, slots * sizeof(double));

@@ -880,17 +880,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))
 }
 
 // ---------------------------------------------------------------------------
-// Per-wave record streams (semi-asynchronous wave cores).  Tasks are
-// numbered superstep by superstep; wave slot v (the i-th wave of workgroup
-// g is v = 4 g + i) runs tasks v, v + W, v + 2W, ... (W waves) and waits
-// only for the values it gathers.  The rows of those tasks are stored one after the other in slot v's stream
-// as records: a header slot (word HDR | row, INTL set on a task's first row;
-// value the diagonal) and then the row's off-diagonal entries in stored
-// order (word the column, or INTL | distance to one of the task's last
-// kWaveRing rows; value A_ij).  A wave reads its stream as 64-slot windows:
-// one load brings a short row's header and entries, and often the next
-// rows' too, so a row waits for its gathers only.  Per row the operations
-// and their order are those of wave_task (Eq. (2.1)).
+// Per-wave record streams (semi-asynchronous wave cores; layout in wave.h).
+// Tasks are numbered superstep by superstep; wave slot v (the i-th wave of
+// workgroup g is v = 4 g + i) runs tasks v, v + W, v + 2W, ... (W waves)
+// and waits only for the values it gathers.  Slot v's stream holds the rows
+// of those tasks one after another as records: a header slot (word HDR |
+// row, INTL set on a task's first row; value the diagonal) and then the
+// row's off-diagonal entries in stored order (word the column, or INTL |
+// distance to one of the task's last kWaveRing rows; value A_ij).  A wave
+// reads its stream as 64-slot windows: one load brings a short row's header
+// and entries, and often the next rows' too, so a row waits for its gathers
+// only.  Per row the operations and their order are those of wave_task
+// (Eq. (2.1)).
 // ---------------------------------------------------------------------------
 
 // Loads need no branch and no select on their result (either makes the
