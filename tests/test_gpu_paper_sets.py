@@ -77,7 +77,8 @@ def test_full_size_single_system():
     """The n = 1e7 workload of the benchmark: the plan's GrowLocal schedule
     and Sec. 5 order equal the oracle's (the stored key of
     tests/golden/schedule_keys.json), and the persistent, plain,
-    semi-asynchronous and several-column solves equal the full oracle solve."""
+    semi-asynchronous and several-column solves, and the semi-asynchronous
+    solve on wavefront cores, equal the full oracle solve."""
     import json
     import os
     import torch
@@ -108,6 +109,13 @@ def test_full_size_single_system():
         torch.cuda.synchronize()
         for r in (0, 3):
             assert oracle.same_bits(X[:, r].cpu().numpy(), want)
+    # wavefront cores over per-wave record streams, at the benchmark's size
+    with B.Plan(m, B.default_opts(schedule_kind=B.SCHED_WAVEFRONT, core_width=64)) as p:
+        x.fill_(float("nan"))
+        p.solve_async(b, x)
+        torch.cuda.synchronize()
+        assert p.device_status() == 0
+        assert oracle.same_bits(x.cpu().numpy(), want)
 
 
 @pytest.mark.parametrize("maker", [lambda: gen.stencil_3d7(216), lambda: gen.stencil_3d27(216)])
