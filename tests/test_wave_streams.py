@@ -6,6 +6,8 @@ by task they give the oracle's x bit for bit under every valid schedule
 (Definition 2.1)."""
 import numpy as np
 import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
 
 import oracle
 from paper_2503_05408_amd import binding as B
@@ -161,3 +163,73 @@ def test_bad_arguments():
     empty = gen.edgeless(0)
     st = B.wave_streams(empty, np.zeros(0, np.int32), np.zeros(0, np.int32), 4)
     assert len(st["stask"]) == 0 and list(st["sbeg"]) == [0, 1, 2, 3, 4]
+
+
+def _run_waves(st, n, b, waves):
+    """Runs the streams the way the semi-asynchronous kernel does, without
+    its global order: every wave walks only its own stream and takes a row
+    once every column it reads from memory has been computed; the waves take
+    turns.  The run must finish (a wave's next row always becomes ready:
+    Definition 2.1 and the task order) and give the oracle's bits."""
+    scol, sval, sbeg = st["scol"], st["sval"], st["sbeg"]
+    x = np.full(n, np.nan)
+    done = np.zeros(n, dtype=bool)
+    pos = [int(sbeg[v]) for v in range(waves)]
+    end = [int(sbeg[v + 1]) - 1 for v in range(waves)]
+    rings = [[] for _ in range(waves)]
+    with np.errstate(invalid="ignore", over="ignore", divide="ignore"):
+        while True:
+            moved = False
+            for v in range(waves):
+                if pos[v] >= end[v]:
+                    continue
+                o = pos[v]
+                w = int(scol[o])
+                assert w & HDR and w != PAD
+                e = o + 1
+                while e < end[v] and not (int(scol[e]) & HDR):
+                    e += 1
+                cols = [int(c) for c in scol[o + 1:e] if not (int(c) & INTL)]
+                if not all(done[c] for c in cols):
+                    continue
+                if w & INTL:
+                    rings[v] = []
+                row, acc = w & MASK, b[w & MASK]
+                for k in range(o + 1, e):
+                    c = int(scol[k])
+                    g = rings[v][-(c & MASK)] if c & INTL else x[c]
+                    acc = acc - sval[k] * g
+                x[row] = acc / sval[o]
+                done[row] = True
+                rings[v].append(x[row])
+                pos[v] = e
+                moved = True
+            if all(pos[v] >= end[v] for v in range(waves)):
+                return x
+            assert moved, "no wave can take its next row"
+
+
+@st.composite
+def _small_systems(draw):
+    n = draw(st.integers(1, 40))
+    density = draw(st.sampled_from([0.0, 0.05, 0.2, 0.5]))
+    seed = draw(st.integers(0, 2 ** 31 - 1))
+    band = draw(st.sampled_from([None, 3, 8]))
+    return gen.random_lower(n, density, seed, band=band)
+
+
+@settings(max_examples=300, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(_small_systems(), st.sampled_from([1, 2, 3, 5, 64, 300]),
+       st.sampled_from([("growlocal", 1), ("growlocal", 3), ("growlocal", 64), ("wavefront", 0)]),
+       st.integers(0, 2 ** 31 - 1), st.booleans())
+def test_streams_run_by_waves_of_their_own(m, waves, sched, bseed, upper):
+    kind, k = sched
+    if upper:
+        m = gen.upper_of(m)
+    core, sup = (_schedule(m, B.SCHED_WAVEFRONT, upper=upper) if kind == "wavefront"
+                 else _schedule(m, B.SCHED_GROWLOCAL, upper=upper, k=k, L=3.0, alpha0=1.0))
+    s = B.wave_streams(m, core, sup, waves, triangle=B.UPPER if upper else B.LOWER)
+    b = gen.rhs_uniform(m.n, bseed % 1000)
+    want = oracle.solve_upper(m, b) if upper else oracle.solve(m, b)
+    assert oracle.same_bits(_run(s, m.n, b, waves), want)
+    assert oracle.same_bits(_run_waves(s, m.n, b, waves), want)
