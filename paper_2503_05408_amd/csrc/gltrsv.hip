@@ -290,6 +290,7 @@ struct gltrsv_batch {
     double *d_bcat = nullptr;
     double *d_xcat = nullptr;
     int64_t rows = 0;                  // rows of all systems
+    bool stream_dpp = false;           // DPP row subtraction (as for one system of all the rows)
     // wave cores: robbing of workgroups that have not started (start ticket,
     // kMaxGrid alive words, 4 kMaxGrid robbed-prefix words)
     unsigned long long *d_wticket = nullptr;
@@ -748,8 +749,13 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         // Measured on MI355X: 512 workgroups were best for the n = 1e5 ER
         // and NB sets, the full 2,048 for n = 1e7.  The per-wave streams are
         // built for this grid.
+        p->stream_dpp = p->n > 0 && p->nnz - p->n >= dev::kDppMinPerRow * p->n;
         int per_cu_wa = 0, cus_wa = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_wa, dev::trsv_stream_async, dev::kBlock, 0);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu_wa,
+            p->stream_dpp ? reinterpret_cast<const void *>(dev::trsv_stream_async<true>)
+                          : reinterpret_cast<const void *>(dev::trsv_stream_async<false>),
+            dev::kBlock, 0);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus_wa, hipDeviceAttributeMultiprocessorCount, p->device);
         if (e != hipSuccess) {
             gltrsv_plan_destroy(p);
@@ -994,10 +1000,11 @@ int gltrsv_solve_async(gltrsv_plan *p, const double *b, double *x, void *stream)
     // static task orders; waves that wait long rob workgroups that have not
     // started, so no co-residency is needed (plain launches)
     if (p->core_width == 64) {
-        hipLaunchKernelGGL(dev::trsv_stream_async, dim3(p->grid_wave_async), dim3(dev::kBlock), 0, st, p->d_scol,
-                           p->d_sval, p->d_sbeg, p->d_stask, p->wsuper_host.back(), bb, x, err, lim,
-                           async_ticket(p, 2), p->d_aalive + 2 * dev::kMaxGrid,
-                           p->d_vnext + 2 * dev::kMaxGrid * dev::kWavesPerBlock, dev::kRobTicks, p->delay_ticks);
+        hipLaunchKernelGGL(p->stream_dpp ? dev::trsv_stream_async<true> : dev::trsv_stream_async<false>,
+                           dim3(p->grid_wave_async), dim3(dev::kBlock), 0, st, p->d_scol, p->d_sval, p->d_sbeg,
+                           p->d_stask, p->wsuper_host.back(), bb, x, err, lim, async_ticket(p, 2),
+                           p->d_aalive + 2 * dev::kMaxGrid, p->d_vnext + 2 * dev::kMaxGrid * dev::kWavesPerBlock,
+                           dev::kRobTicks, p->delay_ticks);
         HIP_TRY(hipGetLastError());
         p->last_stream = st;
         return GLTRSV_OK;
@@ -1303,6 +1310,12 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
     bt->count = int32_t(bt->plans.size());
     bt->wave = bt->async_exec && bt->count > 0;
     for (auto *pl : bt->plans) bt->wave = bt->wave && pl->core_width == 64;
+    int64_t all_rows = 0, all_off = 0;
+    for (auto *pl : bt->plans) {
+        all_rows += pl->n;
+        all_off += pl->nnz - pl->n;
+    }
+    bt->stream_dpp = all_rows > 0 && all_off >= dev::kDppMinPerRow * all_rows;
     const size_t ndesc = std::max<size_t>(1, bt->plans.size());
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&bt->d_desc), ndesc * sizeof(dev::SysDesc));
     if (e == hipSuccess)
@@ -1350,8 +1363,11 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
     }
     int per_cu = 0, cus = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, bt->wave ? reinterpret_cast<const void *>(dev::trsv_stream_async)
-                          : reinterpret_cast<const void *>(dev::trsv_batched), dev::kBlock, 0);
+        &per_cu,
+        bt->wave ? (bt->stream_dpp ? reinterpret_cast<const void *>(dev::trsv_stream_async<true>)
+                                   : reinterpret_cast<const void *>(dev::trsv_stream_async<false>))
+                 : reinterpret_cast<const void *>(dev::trsv_batched),
+        dev::kBlock, 0);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
     if (e != hipSuccess) {
         gltrsv_batch_destroy(bt);
@@ -1464,7 +1480,8 @@ static int batch_enqueue(gltrsv_batch *bt, hipStream_t st)
             const int64_t fb = std::min<int64_t>(4096, (bt->rows + dev::kBlock - 1) / dev::kBlock);
             hipLaunchKernelGGL(dev::fill_unready, dim3(unsigned(std::max<int64_t>(1, fb))), dim3(dev::kBlock), 0, st,
                                reinterpret_cast<unsigned long long *>(bt->d_xcat), bt->rows);
-            hipLaunchKernelGGL(dev::trsv_stream_async, dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st,
+            hipLaunchKernelGGL(bt->stream_dpp ? dev::trsv_stream_async<true> : dev::trsv_stream_async<false>,
+                               dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st,
                                bt->d_bscol, bt->d_bsval, bt->d_bbeg, bt->d_btask, int32_t(bt->gtasks), bt->d_bcat,
                                bt->d_xcat, bt->d_err, int64_t(5000000), bt->d_wticket, bt->d_walive, bt->d_wvnext,
                                dev::kRobTicks, int64_t(0));

@@ -66,6 +66,16 @@ constexpr int64_t kStealTicks = 20000;
 #endif
 constexpr int kStreamSgprs = GLTRSV_STREAM_SGPRS;
 constexpr int kStreamWgPerCu = kStreamSgprs > 80 ? 7 : 8;
+// The record-stream kernel subtracts a row's products with the DPP form
+// (subtract_lanes) when the system averages at least this many stored
+// off-diagonals per row.  Measured on MI355X (that form against readlane
+// for every system): 27-point 216^3 (13 a row) 3.75 against 3.97 ms, ER
+// n = 1e7 (11) 2.71 against 2.76; NB n = 1e5, p = 0.03, B = 42 (about 1.3)
+// 1.22 against 1.11, the 64-system batch (4.3) 6.51 against 6.05.
+#ifndef GLTRSV_DPP_MIN_PER_ROW
+#define GLTRSV_DPP_MIN_PER_ROW 8
+#endif
+constexpr int64_t kDppMinPerRow = GLTRSV_DPP_MIN_PER_ROW;
 
 // Batched launches: the state word of system i sits at state[i * kStateStride]
 // (one per 256 bytes, so waves polling different systems do not queue on
@@ -184,6 +194,7 @@ __global__ void trsv_wave(const int32_t *wrow, const int64_t *wptr, const double
                           const double *wval, const int64_t *wtask, const int32_t *wsuper, int32_t s0, int32_t s1,
                           const double *b, double *x, uint32_t *bar, uint32_t *alive, uint32_t *claim,
                           int32_t *err, int64_t spin_limit, int64_t steal_ticks, int64_t delay_ticks);
+template <bool kDpp>
 __global__ void trsv_stream_async(const uint32_t *scol, const double *sval, const int64_t *sbeg, const int64_t *stask,
                                   int32_t tasks, const double *b, double *x, int32_t *err, int64_t spin_limit,
                                   unsigned long long *ticket, uint32_t *alive, unsigned long long *vnext,
@@ -298,6 +309,7 @@ struct gltrsv_plan {
     int64_t *d_sbeg = nullptr;          // [W + 1] first slot of each wave's stream
     int64_t *d_stask = nullptr;         // [wave tasks] first slot of each task
     int64_t stream_w = 0;               // W: waves the streams were built for (4 x grid_wave_async)
+    bool stream_dpp = false;            // the kernel's DPP row subtraction (see kDppMinPerRow)
     std::vector<int64_t> ssize_host;    // [wave tasks] slots of each task's records
     // one-workgroup layout (opts.exec_hint = 2, local.h)
     uint8_t *d_lrec = nullptr;          // the records

@@ -774,6 +774,64 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
+// acc minus the products of lanes [l, e), one after another in lane order
+// (l and e the same in every lane, acc too).  The plain form reads each
+// product out with readlane and subtracts it: three VALU instructions an
+// entry.  The DPP form takes each product to the accumulator with the
+// data-parallel-primitive broadcast of its lane within its 16-lane row
+// (row_newbcast) folded into a fused multiply-add by -1: one instruction an
+// entry, and as the product by -1 is exact the single rounding is that of
+// the subtraction, so the bits are those of acc - p.  It runs a 16-lane row
+// at a time: every row of the wave executes the same instructions, the one
+// holding the entries gets the result, and readlane hands that to all lanes
+// before the next row.  Its entry point into a row is picked by a branch
+// tree on the first lane, and the row ends after lane e - 1; that fixed
+// cost makes it slower than the plain form on rows of few entries.
+#define GLTRSV_DPP_PAIR(a, b) "s_bitcmp1_b32 %3, 0\n s_cbranch_scc1 .Ls" #b "_%=\n s_branch .Ls" #a "_%=\n"
+#define GLTRSV_DPP_NODE(bit, hi) "s_bitcmp1_b32 %3, " #bit "\n s_cbranch_scc1 .Ln" #hi "_%=\n"
+#define GLTRSV_DPP_SUB(k) "v_fmac_f64_dpp %0, %1, %2 row_newbcast:" #k " row_mask:0xf bank_mask:0xf\n"
+#define GLTRSV_DPP_STEP(k, n) ".Ls" #k "_%=:\n " GLTRSV_DPP_SUB(k) " s_cmp_eq_u32 %4, " #n "\n s_cbranch_scc1 .Lend_%=\n"
+
+template <bool kDpp>
+__device__ __forceinline__ double subtract_lanes(double acc, const double prod, const int l, const int e)
+{
+    if constexpr (!kDpp) {
+        for (int j = l; j < e; j++) acc = acc - readlane_f64(prod, j);
+        return acc;
+    } else {
+        const double m1 = -1.0;
+        for (int rb = l >> 4; l < e && (rb << 4) < e; rb++) {
+            // lanes [k0, k1) of row rb, 0 <= k0 < k1 <= 16
+            const int k0 = __builtin_amdgcn_readfirstlane(max(l - (rb << 4), 0));
+            const int k1 = __builtin_amdgcn_readfirstlane(min(e - (rb << 4), 16));
+            double a = acc;
+            // (the leading s_nop: two wait states between the VALU write of
+            // the products and their first DPP read)
+            asm volatile("s_nop 1\n"
+                         GLTRSV_DPP_NODE(3, 8) GLTRSV_DPP_NODE(2, 4) GLTRSV_DPP_NODE(1, 2) GLTRSV_DPP_PAIR(0, 1)
+                         ".Ln2_%=:\n" GLTRSV_DPP_PAIR(2, 3)
+                         ".Ln4_%=:\n" GLTRSV_DPP_NODE(1, 6) GLTRSV_DPP_PAIR(4, 5)
+                         ".Ln6_%=:\n" GLTRSV_DPP_PAIR(6, 7)
+                         ".Ln8_%=:\n" GLTRSV_DPP_NODE(2, 12) GLTRSV_DPP_NODE(1, 10) GLTRSV_DPP_PAIR(8, 9)
+                         ".Ln10_%=:\n" GLTRSV_DPP_PAIR(10, 11)
+                         ".Ln12_%=:\n" GLTRSV_DPP_NODE(1, 14) GLTRSV_DPP_PAIR(12, 13)
+                         ".Ln14_%=:\n" GLTRSV_DPP_PAIR(14, 15)
+                         GLTRSV_DPP_STEP(0, 1) GLTRSV_DPP_STEP(1, 2) GLTRSV_DPP_STEP(2, 3) GLTRSV_DPP_STEP(3, 4)
+                         GLTRSV_DPP_STEP(4, 5) GLTRSV_DPP_STEP(5, 6) GLTRSV_DPP_STEP(6, 7) GLTRSV_DPP_STEP(7, 8)
+                         GLTRSV_DPP_STEP(8, 9) GLTRSV_DPP_STEP(9, 10) GLTRSV_DPP_STEP(10, 11)
+                         GLTRSV_DPP_STEP(11, 12) GLTRSV_DPP_STEP(12, 13) GLTRSV_DPP_STEP(13, 14)
+                         GLTRSV_DPP_STEP(14, 15)
+                         ".Ls15_%=:\n " GLTRSV_DPP_SUB(15)
+                         ".Lend_%=:\n"
+                         : "+v"(a)
+                         : "v"(prod), "v"(m1), "s"(k0), "s"(k1)
+                         : "scc");
+            acc = readlane_f64(a, rb << 4);
+        }
+        return acc;
+    }
+}
+
 // value of entry e (if e < e1) of the current row: a column from memory or
 // from the ring; the product is formed by the caller.  c receives the word
 // (kPadWord past the row's end).
@@ -824,7 +882,7 @@ __device__ __forceinline__ void wave_task(const int32_t *__restrict__ wrow, cons
             const double p = v * g;
             // (the same in every lane: a scalar loop, see stream_run)
             const int cnt = __builtin_amdgcn_readfirstlane(int(min<int64_t>(64, e1 - base)));
-            for (int l = 0; l < cnt; l++) acc = acc - readlane_f64(p, l);
+            acc = subtract_lanes<false>(acc, p, 0, cnt);
             v = vn;
             g = gn;
             c = cn;
@@ -932,6 +990,7 @@ __device__ __forceinline__ int first_from(unsigned long long m, int l)
 // of kStreamSub 64-slot windows: a chunk's words and values arrive while
 // the chunk before it is worked on; its gathers are issued together and
 // waited for together, and the next chunk's loads go out behind them.
+template <bool kDpp>
 __device__ __forceinline__ int stream_run(const uint32_t *__restrict__ scol, const double *__restrict__ sval,
                                           int64_t &o, int64_t end, int32_t &t, int32_t W, const double *b, double *x,
                                           double *ring, int32_t *err, int64_t spin_limit, const AsyncRob &rob)
@@ -991,8 +1050,7 @@ __device__ __forceinline__ int stream_run(const uint32_t *__restrict__ scol, con
                         if (r != kReady) return r;
                     }
                 }
-                const double prod = vc * gc;
-                for (int j = l; j < e; j++) acc = acc - readlane_f64(prod, j);
+                acc = subtract_lanes<kDpp>(acc, vc * gc, l, e);
                 if (e == 64) return kMore;   // the row goes on in the next window
                 const double y = acc / diag;
                 if (lane == 0) {
@@ -1075,7 +1133,9 @@ __device__ __forceinline__ int stream_run(const uint32_t *__restrict__ scol, con
 // finished its own earlier tasks.  Waves blocked for long while some
 // workgroup has not started rob that workgroup's tasks in order (see
 // trsv_async); a robbed task runs from stask[k] to the first record of its
-// slot's next task.
+// slot's next task.  kDpp: the DPP form of the row subtraction (see
+// subtract_lanes), for systems of long rows.
+template <bool kDpp>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kStreamSgprs))) void trsv_stream_async(
     const uint32_t *__restrict__ scol, const double *__restrict__ sval, const int64_t *__restrict__ sbeg,
     const int64_t *__restrict__ stask, int32_t tasks, const double *b, double *x, int32_t *err,
@@ -1108,7 +1168,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kStreamSgprs
         if (!robbed && o >= mine_end) return;
         int64_t oo = robbed ? ro : o;
         int32_t tt = robbed ? rt : t;
-        const int r = stream_run(scol, sval, oo, robbed ? rend : mine_end, tt, W, b, x, my_ring, err, spin_limit,
+        const int r = stream_run<kDpp>(scol, sval, oo, robbed ? rend : mine_end, tt, W, b, x, my_ring, err, spin_limit,
                                  robbed ? s_norob : s_rob);
         if (r == kFailed) return;   // a wait ran out: *err is set, the other waves leave too
         if (robbed) {
@@ -1126,6 +1186,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kStreamSgprs
         }
     }
 }
+template __global__ void trsv_stream_async<false>(const uint32_t *, const double *, const int64_t *, const int64_t *,
+                                                  int32_t, const double *, double *, int32_t *, int64_t,
+                                                  unsigned long long *, uint32_t *, unsigned long long *, int64_t,
+                                                  int64_t);
+template __global__ void trsv_stream_async<true>(const uint32_t *, const double *, const int64_t *, const int64_t *,
+                                                 int32_t, const double *, double *, int32_t *, int64_t,
+                                                 unsigned long long *, uint32_t *, unsigned long long *, int64_t,
+                                                 int64_t);
 
 // ---------------------------------------------------------------------------
 // Semi-asynchronous solve: no barriers.  Chunks are numbered superstep by
