@@ -873,6 +873,7 @@ int gltrsv_plan_info_get(const gltrsv_plan *p, gltrsv_plan_info *o)
     o->local_groups = p->l_groups;
     o->local_records = p->l_nrec;
     o->local_far = p->l_far;
+    o->stream_dpp = p->stream_dpp ? 1 : 0;
     return GLTRSV_OK;
 }
 

@@ -78,3 +78,59 @@ def test_wave_cores_repeat_and_reject_bad_width():
             assert oracle.same_bits(x.cpu().numpy(), want)
     with pytest.raises(B.GltrsvError):
         B.Plan(m, B.default_opts(core_width=32))
+
+
+def _every_row_length(reps, seed, longest=140):
+    """160 rows without off-diagonals, then rows with every count of stored
+    off-diagonals from 0 to `longest`, `reps` times over (so rows start at
+    every lane of a 64-slot window and end across 16-lane rows and windows),
+    columns drawn at random below the row, the paper's values."""
+    rng = np.random.default_rng(seed)
+    base = 160
+    counts = np.tile(np.arange(longest + 1), reps)
+    n = base + counts.size
+    rows, cols = [], []
+    for i, c in enumerate(counts):
+        r = base + i
+        rows.append(np.full(c, r, dtype=np.int64))
+        cols.append(np.sort(rng.choice(r, size=c, replace=False)).astype(np.int64))
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    off, diag = gen.paper_values(rng, rows.size, n)
+    return gen._assemble(n, rows, cols, off, diag, f"every_row_length_{reps}_{seed}", presorted=True)
+
+
+@pytest.mark.parametrize("upper", [False, True])
+def test_both_row_subtraction_forms(upper):
+    """The semi-asynchronous wave-core solve subtracts a row's products
+    through DPP lane broadcasts on systems of long rows and through readlane
+    on the others; both give the oracle's bits on rows of every length, for
+    single systems and for a batch of each kind."""
+    import torch
+    long_rows = [_every_row_length(4, 81), _every_row_length(2, 82, longest=70)]
+    short_rows = [gen.narrow_band(3000, 0.05, 20.0, gen.SEED_BASE + 83), gen.chain(200)]
+    for group, dpp in ((long_rows, 1), (short_rows, 0)):
+        ms = [gen.upper_of(m) for m in group] if upper else group
+        bs = [gen.rhs_uniform(m.n, 90 + i) for i, m in enumerate(ms)]
+        wants = [oracle.solve_upper(m, b) if upper else oracle.solve(m, b) for m, b in zip(ms, bs)]
+        bd = [torch.from_numpy(b).cuda() for b in bs]
+        tri = B.UPPER if upper else B.LOWER
+        for over in (dict(schedule_kind=B.SCHED_WAVEFRONT), dict(k=4)):
+            ps = [B.Plan(m, B.default_opts(core_width=64, triangle=tri, **over)) for m in ms]
+            try:
+                for p, b, want in zip(ps, bd, wants):
+                    assert p.info()["stream_dpp"] == dpp
+                    x = torch.full_like(b, float("nan"))
+                    p.solve_async(b, x)
+                    torch.cuda.synchronize()
+                    assert p.device_status() == 0
+                    assert oracle.same_bits(x.cpu().numpy(), want), (p.info()["n"], over)
+                with B.Batch(ps, async_exec=True) as bt:
+                    xd = [torch.full_like(b, float("nan")) for b in bd]
+                    bt.solve(bd, xd)
+                    torch.cuda.synchronize()
+                    assert bt.status() == 0
+                    for x, want in zip(xd, wants):
+                        assert oracle.same_bits(x.cpu().numpy(), want), ("batch", over)
+            finally:
+                for p in ps:
+                    p.close()
