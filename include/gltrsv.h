@@ -273,8 +273,8 @@ typedef struct gltrsv_plan_info {
     int64_t local_records;  /* ... and the records they are cut into          */
     int64_t local_far;      /* ... and the operands read from x in global
                                memory rather than from LDS                    */
-    int32_t stream_dpp;     /* core width 64: 1 if gltrsv_solve_async
-                               subtracts a row's products through DPP lane
+    int32_t row_dpp;        /* core width 64: 1 if the wave-core solves
+                               subtract a row's products through DPP lane
                                broadcasts (systems averaging at least 8
                                stored off-diagonals a row), 0 if through
                                readlane; the bits are the same either way     */

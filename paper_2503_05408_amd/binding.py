@@ -85,7 +85,7 @@ class PlanInfo(ctypes.Structure):
                 ("schedule_kind", i32), ("predicted_us", dbl), ("device_packed", i32),
                 ("async_grid_blocks", i32), ("exec_form", i32), ("core_width", i32),
                 ("local_groups", i64), ("local_records", i64), ("local_far", i64),
-                ("stream_dpp", i32)]
+                ("row_dpp", i32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -290,7 +290,7 @@ struct gltrsv_batch {
     double *d_bcat = nullptr;
     double *d_xcat = nullptr;
     int64_t rows = 0;                  // rows of all systems
-    bool stream_dpp = false;           // DPP row subtraction (as for one system of all the rows)
+    bool row_dpp = false;              // DPP row subtraction (as for one system of all the rows)
     // wave cores: robbing of workgroups that have not started (start ticket,
     // kMaxGrid alive words, 4 kMaxGrid robbed-prefix words)
     unsigned long long *d_wticket = nullptr;
@@ -743,17 +743,17 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         return rc;
     }
     p->core_width = opts->core_width == 64 ? 64 : 1;
+    p->row_dpp = p->core_width == 64 && p->n > 0 && p->nnz - p->n >= dev::kDppMinPerRow * p->n;
     if (p->core_width == 64) {
         // semi-asynchronous wave cores: at least two workgroups per CU, more
         // for large systems (about one wave per 1,024 rows), all co-resident.
         // Measured on MI355X: 512 workgroups were best for the n = 1e5 ER
         // and NB sets, the full 2,048 for n = 1e7.  The per-wave streams are
         // built for this grid.
-        p->stream_dpp = p->n > 0 && p->nnz - p->n >= dev::kDppMinPerRow * p->n;
         int per_cu_wa = 0, cus_wa = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu_wa,
-            p->stream_dpp ? reinterpret_cast<const void *>(dev::trsv_stream_async<true>)
+            p->row_dpp ? reinterpret_cast<const void *>(dev::trsv_stream_async<true>)
                           : reinterpret_cast<const void *>(dev::trsv_stream_async<false>),
             dev::kBlock, 0);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus_wa, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -820,7 +820,11 @@ static int plan_create_impl(const gltrsv_csr *A, const gltrsv_plan_opts *opts, c
         // wave cores: co-resident for the barrier, no more workgroups than
         // the superstep with the most tasks can use
         int per_cu_w = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_w, dev::trsv_wave, dev::kBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu_w,
+            p->row_dpp ? reinterpret_cast<const void *>(dev::trsv_wave<true>)
+                       : reinterpret_cast<const void *>(dev::trsv_wave<false>),
+            dev::kBlock, 0);
         if (e != hipSuccess) {
             gltrsv_plan_destroy(p);
             return set_error(GLTRSV_EHIP, std::string("occupancy query: ") + hipGetErrorString(e));
@@ -873,7 +877,7 @@ int gltrsv_plan_info_get(const gltrsv_plan *p, gltrsv_plan_info *o)
     o->local_groups = p->l_groups;
     o->local_records = p->l_nrec;
     o->local_far = p->l_far;
-    o->stream_dpp = p->stream_dpp ? 1 : 0;
+    o->row_dpp = p->row_dpp ? 1 : 0;
     return GLTRSV_OK;
 }
 
@@ -906,10 +910,10 @@ int gltrsv_solve_plain(gltrsv_plan *p, const double *b, double *x, void *stream)
             const int32_t tasks = p->wsuper_host[size_t(s) + 1] - p->wsuper_host[size_t(s)];
             const int32_t blocks = (tasks + dev::kWavesPerBlock - 1) / dev::kWavesPerBlock;
             if (blocks == 0) continue;
-            hipLaunchKernelGGL(dev::trsv_wave, dim3(blocks), dim3(dev::kBlock), 0, st, p->d_wrow, p->d_wptr,
-                               p->d_wdiag, p->d_wcol, p->d_wval, p->d_wtask, p->d_wsuper, s, s + 1, b, x,
-                               p->d_bar, static_cast<uint32_t *>(nullptr), static_cast<uint32_t *>(nullptr),
-                               p->d_err, p->spin_limit, int64_t(0), int64_t(0));
+            hipLaunchKernelGGL(p->row_dpp ? dev::trsv_wave<true> : dev::trsv_wave<false>, dim3(blocks),
+                               dim3(dev::kBlock), 0, st, p->d_wrow, p->d_wptr, p->d_wdiag, p->d_wcol, p->d_wval,
+                               p->d_wtask, p->d_wsuper, s, s + 1, b, x, p->d_bar, static_cast<uint32_t *>(nullptr),
+                               static_cast<uint32_t *>(nullptr), p->d_err, p->spin_limit, int64_t(0), int64_t(0));
         }
         HIP_TRY(hipGetLastError());
         p->last_stream = st;
@@ -948,8 +952,9 @@ int gltrsv_solve(gltrsv_plan *p, const double *b, double *x, void *stream)
         int64_t delay = p->delay_ticks;
         void *args[] = {&wr, &wp, &wd, &wc, &wv, &wt, &ws, &s0, &s1, &b, &x, &bar, &alive, &claim, &err, &lim, &steal,
                         &delay};
-        if (int rc = launch_coresident(reinterpret_cast<const void *>(dev::trsv_wave), dim3(p->grid_wave), args, st,
-                                       p->cooperative))
+        const void *kern = p->row_dpp ? reinterpret_cast<const void *>(dev::trsv_wave<true>)
+                                      : reinterpret_cast<const void *>(dev::trsv_wave<false>);
+        if (int rc = launch_coresident(kern, dim3(p->grid_wave), args, st, p->cooperative))
             return rc;
         p->last_stream = st;
         return GLTRSV_OK;
@@ -1001,7 +1006,7 @@ int gltrsv_solve_async(gltrsv_plan *p, const double *b, double *x, void *stream)
     // static task orders; waves that wait long rob workgroups that have not
     // started, so no co-residency is needed (plain launches)
     if (p->core_width == 64) {
-        hipLaunchKernelGGL(p->stream_dpp ? dev::trsv_stream_async<true> : dev::trsv_stream_async<false>,
+        hipLaunchKernelGGL(p->row_dpp ? dev::trsv_stream_async<true> : dev::trsv_stream_async<false>,
                            dim3(p->grid_wave_async), dim3(dev::kBlock), 0, st, p->d_scol, p->d_sval, p->d_sbeg,
                            p->d_stask, p->wsuper_host.back(), bb, x, err, lim, async_ticket(p, 2),
                            p->d_aalive + 2 * dev::kMaxGrid, p->d_vnext + 2 * dev::kMaxGrid * dev::kWavesPerBlock,
@@ -1316,7 +1321,7 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
         all_rows += pl->n;
         all_off += pl->nnz - pl->n;
     }
-    bt->stream_dpp = all_rows > 0 && all_off >= dev::kDppMinPerRow * all_rows;
+    bt->row_dpp = all_rows > 0 && all_off >= dev::kDppMinPerRow * all_rows;
     const size_t ndesc = std::max<size_t>(1, bt->plans.size());
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&bt->d_desc), ndesc * sizeof(dev::SysDesc));
     if (e == hipSuccess)
@@ -1365,7 +1370,7 @@ int gltrsv_batch_create(gltrsv_plan *const *plans, int32_t count, const gltrsv_b
     int per_cu = 0, cus = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu,
-        bt->wave ? (bt->stream_dpp ? reinterpret_cast<const void *>(dev::trsv_stream_async<true>)
+        bt->wave ? (bt->row_dpp ? reinterpret_cast<const void *>(dev::trsv_stream_async<true>)
                                    : reinterpret_cast<const void *>(dev::trsv_stream_async<false>))
                  : reinterpret_cast<const void *>(dev::trsv_batched),
         dev::kBlock, 0);
@@ -1481,7 +1486,7 @@ static int batch_enqueue(gltrsv_batch *bt, hipStream_t st)
             const int64_t fb = std::min<int64_t>(4096, (bt->rows + dev::kBlock - 1) / dev::kBlock);
             hipLaunchKernelGGL(dev::fill_unready, dim3(unsigned(std::max<int64_t>(1, fb))), dim3(dev::kBlock), 0, st,
                                reinterpret_cast<unsigned long long *>(bt->d_xcat), bt->rows);
-            hipLaunchKernelGGL(bt->stream_dpp ? dev::trsv_stream_async<true> : dev::trsv_stream_async<false>,
+            hipLaunchKernelGGL(bt->row_dpp ? dev::trsv_stream_async<true> : dev::trsv_stream_async<false>,
                                dim3(unsigned(bt->grid)), dim3(dev::kBlock), 0, st,
                                bt->d_bscol, bt->d_bsval, bt->d_bbeg, bt->d_btask, int32_t(bt->gtasks), bt->d_bcat,
                                bt->d_xcat, bt->d_err, int64_t(5000000), bt->d_wticket, bt->d_walive, bt->d_wvnext,

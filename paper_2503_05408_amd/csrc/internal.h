@@ -66,12 +66,17 @@ constexpr int64_t kStealTicks = 20000;
 #endif
 constexpr int kStreamSgprs = GLTRSV_STREAM_SGPRS;
 constexpr int kStreamWgPerCu = kStreamSgprs > 80 ? 7 : 8;
-// The record-stream kernel subtracts a row's products with the DPP form
+// The wave-core kernels subtract a row's products with the DPP form
 // (subtract_lanes) when the system averages at least this many stored
-// off-diagonals per row.  Measured on MI355X (that form against readlane
-// for every system): 27-point 216^3 (13 a row) 3.75 against 3.97 ms, ER
-// n = 1e7 (11) 2.71 against 2.76; NB n = 1e5, p = 0.03, B = 42 (about 1.3)
-// 1.22 against 1.11, the 64-system batch (4.3) 6.51 against 6.05.
+// off-diagonals per row.  Measured on MI355X, the semi-asynchronous
+// record-stream kernel with that form against readlane for every system:
+// 27-point 216^3 (13 a row) 3.75 against 3.97 ms, ER n = 1e7 (11) 2.71
+// against 2.76; NB n = 1e5, p = 0.03, B = 42 (about 1.3) 1.22 against 1.11,
+// the 64-system batch (4.3) 6.51 against 6.05.  The BSP wave-core kernel
+// (persistent / one launch per superstep): ER n = 1e5, p = 2e-3 (about 100
+// a row) 7.57 / 7.56 against 10.62 / 11.07 ms, 27-point 12.35 / 10.08
+// against 12.76 / 10.64; NB n = 1e5, p = 0.05, B = 20 0.530 / 0.353
+// against 0.520 / 0.357.
 #ifndef GLTRSV_DPP_MIN_PER_ROW
 #define GLTRSV_DPP_MIN_PER_ROW 8
 #endif
@@ -190,6 +195,7 @@ __global__ void trsv_persistent(const uint32_t *word, const double *value, const
 // wavefront cores: supersteps [s0, s1) (claim = nullptr for a single
 // superstep, else one word per task as in trsv_persistent), and the
 // semi-asynchronous form over all tasks
+template <bool kDpp>
 __global__ void trsv_wave(const int32_t *wrow, const int64_t *wptr, const double *wdiag, const uint32_t *wcol,
                           const double *wval, const int64_t *wtask, const int32_t *wsuper, int32_t s0, int32_t s1,
                           const double *b, double *x, uint32_t *bar, uint32_t *alive, uint32_t *claim,
@@ -309,7 +315,7 @@ struct gltrsv_plan {
     int64_t *d_sbeg = nullptr;          // [W + 1] first slot of each wave's stream
     int64_t *d_stask = nullptr;         // [wave tasks] first slot of each task
     int64_t stream_w = 0;               // W: waves the streams were built for (4 x grid_wave_async)
-    bool stream_dpp = false;            // the kernel's DPP row subtraction (see kDppMinPerRow)
+    bool row_dpp = false;               // wave cores: DPP row subtraction (see kDppMinPerRow)
     std::vector<int64_t> ssize_host;    // [wave tasks] slots of each task's records
     // one-workgroup layout (opts.exec_hint = 2, local.h)
     uint8_t *d_lrec = nullptr;          // the records

@@ -860,6 +860,8 @@ __device__ __forceinline__ void wave_load(const uint32_t *__restrict__ wcol, con
 constexpr int kWaveSgprs = GLTRSV_WAVE_SGPRS;
 
 // Runs one wave-core task: the rows at positions [t0, t1) of the layout.
+// kDpp: the DPP form of the row subtraction (see subtract_lanes).
+template <bool kDpp>
 __device__ __forceinline__ void wave_task(const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr,
                                           const double *__restrict__ wdiag, const uint32_t *__restrict__ wcol,
                                           const double *__restrict__ wval, int64_t t0, int64_t t1, const double *b,
@@ -882,7 +884,7 @@ __device__ __forceinline__ void wave_task(const int32_t *__restrict__ wrow, cons
             const double p = v * g;
             // (the same in every lane: a scalar loop, see stream_run)
             const int cnt = __builtin_amdgcn_readfirstlane(int(min<int64_t>(64, e1 - base)));
-            acc = subtract_lanes<false>(acc, p, 0, cnt);
+            acc = subtract_lanes<kDpp>(acc, p, 0, cnt);
             v = vn;
             g = gn;
             c = cn;
@@ -900,7 +902,9 @@ __device__ __forceinline__ void wave_task(const int32_t *__restrict__ wrow, cons
 // no synchronisation (claim = nullptr); several run as in trsv_persistent
 // (counted completion, robbing of workgroups that have not started), so no
 // co-residency is needed.  The i-th wave of workgroup g is slot i G + g
-// (tasks of a superstep sorted longest first).
+// (tasks of a superstep sorted longest first).  kDpp: the DPP form of the
+// row subtraction (see subtract_lanes), for systems of long rows.
+template <bool kDpp>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))) void trsv_wave(
     const int32_t *__restrict__ wrow, const int64_t *__restrict__ wptr, const double *__restrict__ wdiag,
     const uint32_t *__restrict__ wcol, const double *__restrict__ wval, const int64_t *__restrict__ wtask,
@@ -912,7 +916,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))
     const int32_t waves = int32_t(gridDim.x) * kWavesPerBlock;
     const int32_t slot = int32_t(threadIdx.x >> 6) * int32_t(gridDim.x) + int32_t(blockIdx.x);
     double *my_ring = ring[threadIdx.x >> 6];
-    auto run_task = [&](int32_t t) { wave_task(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring); };
+    auto run_task = [&](int32_t t) { wave_task<kDpp>(wrow, wptr, wdiag, wcol, wval, wtask[t], wtask[t + 1], b, x, my_ring); };
     if (!claim) {   // one superstep, no other workgroup to wait for
         for (int32_t t = wsuper[s0] + slot; t < wsuper[s0 + 1]; t += waves) run_task(t);
         return;
@@ -936,6 +940,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(kWaveSgprs))
             return;
     }
 }
+template __global__ void trsv_wave<false>(const int32_t *, const int64_t *, const double *, const uint32_t *,
+                                          const double *, const int64_t *, const int32_t *, int32_t, int32_t,
+                                          const double *, double *, uint32_t *, uint32_t *, uint32_t *, int32_t *,
+                                          int64_t, int64_t, int64_t);
+template __global__ void trsv_wave<true>(const int32_t *, const int64_t *, const double *, const uint32_t *,
+                                         const double *, const int64_t *, const int32_t *, int32_t, int32_t,
+                                         const double *, double *, uint32_t *, uint32_t *, uint32_t *, int32_t *,
+                                         int64_t, int64_t, int64_t);
 
 // ---------------------------------------------------------------------------
 // Per-wave record streams (semi-asynchronous wave cores; layout in wave.h).

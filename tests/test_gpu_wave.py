@@ -101,10 +101,10 @@ def _every_row_length(reps, seed, longest=140):
 
 @pytest.mark.parametrize("upper", [False, True])
 def test_both_row_subtraction_forms(upper):
-    """The semi-asynchronous wave-core solve subtracts a row's products
-    through DPP lane broadcasts on systems of long rows and through readlane
-    on the others; both give the oracle's bits on rows of every length, for
-    single systems and for a batch of each kind."""
+    """The wave-core solves subtract a row's products through DPP lane
+    broadcasts on systems of long rows and through readlane on the others;
+    both give the oracle's bits on rows of every length, in every solve form
+    and for a batch of each kind."""
     import torch
     long_rows = [_every_row_length(4, 81), _every_row_length(2, 82, longest=70)]
     short_rows = [gen.narrow_band(3000, 0.05, 20.0, gen.SEED_BASE + 83), gen.chain(200)]
@@ -118,12 +118,13 @@ def test_both_row_subtraction_forms(upper):
             ps = [B.Plan(m, B.default_opts(core_width=64, triangle=tri, **over)) for m in ms]
             try:
                 for p, b, want in zip(ps, bd, wants):
-                    assert p.info()["stream_dpp"] == dpp
-                    x = torch.full_like(b, float("nan"))
-                    p.solve_async(b, x)
-                    torch.cuda.synchronize()
-                    assert p.device_status() == 0
-                    assert oracle.same_bits(x.cpu().numpy(), want), (p.info()["n"], over)
+                    assert p.info()["row_dpp"] == dpp
+                    for solve in (p.solve, p.solve_plain, p.solve_async):
+                        x = torch.full_like(b, float("nan"))
+                        solve(b, x)
+                        torch.cuda.synchronize()
+                        assert p.device_status() == 0
+                        assert oracle.same_bits(x.cpu().numpy(), want), (p.info()["n"], over, solve.__name__)
                 with B.Batch(ps, async_exec=True) as bt:
                     xd = [torch.full_like(b, float("nan")) for b in bd]
                     bt.solve(bd, xd)
