@@ -135,3 +135,42 @@ def test_both_row_subtraction_forms(upper):
             finally:
                 for p in ps:
                     p.close()
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 129])
+def test_wave_cores_at_degenerate_sizes(n):
+    """Wave-core plans of 0, 1, 2 rows and around a window's 64 slots, as a
+    chain (every row waits for the one before) and without edges, in every
+    solve form, and all of them in one semi-asynchronous batch."""
+    import torch
+    ms = [gen.chain(n) if n else gen.edgeless(0), gen.edgeless(n)]
+    plans = [B.Plan(m, B.default_opts(core_width=64, schedule_kind=B.SCHED_WAVEFRONT)) for m in ms]
+    try:
+        bs = [gen.rhs_uniform(m.n, 7 + n) for m in ms]
+        wants = [oracle.solve(m, b) for m, b in zip(ms, bs)]
+        bd = [torch.from_numpy(b).cuda() for b in bs]
+        for p, b, want in zip(plans, bd, wants):
+            for solve in (p.solve, p.solve_plain, p.solve_async):
+                x = torch.full_like(b, float("nan"))
+                solve(b, x)
+                torch.cuda.synchronize()
+                assert p.device_status() == 0
+                assert oracle.same_bits(x.cpu().numpy(), want), (n, solve.__name__)
+        more = [B.Plan(gen.chain(70), B.default_opts(core_width=64, schedule_kind=B.SCHED_WAVEFRONT))]
+        try:
+            bm = [torch.from_numpy(gen.rhs_uniform(70, 3)).cuda()]
+            allp, allb = plans + more, bd + bm
+            allw = wants + [oracle.solve(gen.chain(70), bm[0].cpu().numpy())]
+            with B.Batch(allp, async_exec=True) as bt:
+                xd = [torch.full_like(b, float("nan")) for b in allb]
+                bt.solve(allb, xd)
+                torch.cuda.synchronize()
+                assert bt.status() == 0
+                for x, want in zip(xd, allw):
+                    assert oracle.same_bits(x.cpu().numpy(), want), ("batch", n)
+        finally:
+            for p in more:
+                p.close()
+    finally:
+        for p in plans:
+            p.close()
