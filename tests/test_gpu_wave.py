@@ -137,14 +137,16 @@ def test_both_row_subtraction_forms(upper):
                     p.close()
 
 
+@pytest.mark.parametrize("width", [64, 1])
 @pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 129])
-def test_wave_cores_at_degenerate_sizes(n):
-    """Wave-core plans of 0, 1, 2 rows and around a window's 64 slots, as a
-    chain (every row waits for the one before) and without edges, in every
-    solve form, and all of them in one semi-asynchronous batch."""
+def test_wave_cores_at_degenerate_sizes(n, width):
+    """Plans of 0, 1, 2 rows and around a window's 64 slots (wave cores, and
+    lane cores for comparison), as a chain (every row waits for the one
+    before) and without edges, in every solve form, and all of them in one
+    semi-asynchronous batch."""
     import torch
     ms = [gen.chain(n) if n else gen.edgeless(0), gen.edgeless(n)]
-    plans = [B.Plan(m, B.default_opts(core_width=64, schedule_kind=B.SCHED_WAVEFRONT)) for m in ms]
+    plans = [B.Plan(m, B.default_opts(core_width=width, schedule_kind=B.SCHED_WAVEFRONT)) for m in ms]
     try:
         bs = [gen.rhs_uniform(m.n, 7 + n) for m in ms]
         wants = [oracle.solve(m, b) for m, b in zip(ms, bs)]
@@ -156,7 +158,7 @@ def test_wave_cores_at_degenerate_sizes(n):
                 torch.cuda.synchronize()
                 assert p.device_status() == 0
                 assert oracle.same_bits(x.cpu().numpy(), want), (n, solve.__name__)
-        more = [B.Plan(gen.chain(70), B.default_opts(core_width=64, schedule_kind=B.SCHED_WAVEFRONT))]
+        more = [B.Plan(gen.chain(70), B.default_opts(core_width=width, schedule_kind=B.SCHED_WAVEFRONT))]
         try:
             bm = [torch.from_numpy(gen.rhs_uniform(70, 3)).cuda()]
             allp, allb = plans + more, bd + bm
